@@ -1,0 +1,207 @@
+"""Python driver for the FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the slow, plain reference that the GPU library is
+checked against.  Only the test suite, the package smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code with
+the GPU library and never calls it.
+
+Parity status of each function (what pins it, see ``tests/test_oracle_*.py``):
+  canonicalise, neighbours  - invariants (symmetry, hull count, Euler formula,
+                              orientation), brute-force edge matching
+  sns                       - exact-rational brute-force containment over all
+                              triangles; closed forms on strips and structured
+                              grids; dual-graph BFS lower bound on I_t;
+                              scipy/Qhull find_simplex at scale
+  lookup                    - brute force over all triangles and cells in exact
+                              rationals on small grids
+  cnn_window / cnn_forward  - torch.nn.functional.conv2d in float64; impulse
+                              responses; constructed pass-through weights
+  cnnsns_start              - closed-form cells on hand-made cases
+  brute_force               - exact-rational containment
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_SO = os.path.join(_HERE, "_oracle.so")
+_lib = None
+
+OK, EINVAL, ENOMEM, EMESH = 0, -1, -2, -4
+FOUND, OUTSIDE, MAXITER, BADSTART = 0, 1, 2, 3
+CHANNELS = (2, 32, 32, 32, 2)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what} failed with code {code}")
+        self.code = code
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: FP64, no FMA contraction, OpenMP threads."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared",
+                               "-fPIC", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=True)
+        lib = ctypes.CDLL(_SO)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        sig = {
+            "orc_set_threads": [ctypes.c_int],
+            "orc_canonicalise": [i64, vp, i64, vp, vp],
+            "orc_neighbours": [i64, i64, vp, vp],
+            "orc_sns": [i64, vp, vp, vp, i64, vp, vp, i32, vp, vp, vp],
+            "orc_lookup": [i64, vp, vp, i32, vp],
+            "orc_cnn_window": [i32, vp, vp, vp, vp, i64, i64, i64, i64, vp],
+            "orc_cnnsns_start": [i64, vp, i32, vp, vp, vp, vp],
+            "orc_brute_force": [i64, vp, vp, i64, vp, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise OracleError(rc, what)
+
+
+def set_threads(n: int = 0) -> int:
+    """Set the thread count of the oracle's parallel loops (0: query)."""
+    return int(_L().orc_set_threads(int(n)))
+
+
+def canonicalise(xy, tri):
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    out = np.empty_like(tri)
+    _check(_L().orc_canonicalise(xy.shape[0], _p(xy), tri.shape[0], _p(tri), _p(out)), "canonicalise")
+    return out
+
+
+def neighbours(n_nodes: int, tri_ccw):
+    tri_ccw = np.ascontiguousarray(tri_ccw, dtype=np.int32)
+    nbr = np.empty_like(tri_ccw)
+    _check(_L().orc_neighbours(int(n_nodes), tri_ccw.shape[0], _p(tri_ccw), _p(nbr)), "neighbours")
+    return nbr
+
+
+def prepare_mesh(xy, tri):
+    """(counter-clockwise triangles, neighbour table) of a mesh."""
+    tc = canonicalise(xy, tri)
+    return tc, neighbours(np.asarray(xy).shape[0], tc)
+
+
+def sns(xy, tri_ccw, nbr, xp, start, max_iter: int = 0):
+    """Alg. 1 for every point: (host, iters, status)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    start = np.ascontiguousarray(start, dtype=np.int32)
+    n = xp.shape[0]
+    host = np.empty(n, np.int32)
+    iters = np.empty(n, np.int32)
+    status = np.empty(n, np.uint8)
+    _check(_L().orc_sns(tri_ccw.shape[0], _p(xy), _p(tri_ccw), _p(nbr), n, _p(xp), _p(start), int(max_iter),
+                        _p(host), _p(iters), _p(status)), "sns")
+    return host, iters, status
+
+
+def lookup(xy, tri_ccw, G: int):
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    out = np.empty((G, G), np.int32)
+    _check(_L().orc_lookup(tri_ccw.shape[0], _p(xy), _p(tri_ccw), int(G), _p(out)), "lookup")
+    return out
+
+
+def cnn_window(vel, ws, bs, r0: int, c0: int, h: int, w: int):
+    """Four-layer CNN output on rows [r0, r0+h) x cols [c0, c0+w): FP64 [C_out][h][w]."""
+    vel = np.ascontiguousarray(vel, dtype=np.float32)
+    G = vel.shape[-1]
+    ws = [np.ascontiguousarray(x, dtype=np.float32) for x in ws]
+    bs = [np.ascontiguousarray(x, dtype=np.float32) for x in bs]
+    chan = np.array([ws[0].shape[1]] + [x.shape[0] for x in ws], dtype=np.int32)
+    wp = (ctypes.c_void_p * 4)(*[x.ctypes.data for x in ws])
+    bp = (ctypes.c_void_p * 4)(*[x.ctypes.data for x in bs])
+    out = np.empty((chan[4], h, w), np.float64)
+    _check(_L().orc_cnn_window(G, _p(vel), _p(chan), wp, bp, r0, c0, h, w, _p(out)), "cnn_window")
+    return out
+
+
+def cnn_forward(vel, ws, bs):
+    G = vel.shape[-1]
+    return cnn_window(vel, ws, bs, 0, 0, G, G)
+
+
+def cnn_pixels(vel, ws, bs, rows, cols):
+    """CNN output at individual pixels: FP64 [len(rows)][C_out]."""
+    out = np.empty((len(rows), ws[-1].shape[0]), np.float64)
+    for k, (r, c) in enumerate(zip(rows, cols)):
+        out[k] = cnn_window(vel, ws, bs, int(r), int(c), 1, 1)[:, 0, 0]
+    return out
+
+
+def cnnsns_start(origin, disp, lookup_grid, fallback=None):
+    """Alg. 2 start element from the predicted displacement (FP64 [2][G][G])."""
+    origin = np.ascontiguousarray(origin, dtype=np.float64)
+    disp = np.ascontiguousarray(disp, dtype=np.float64)
+    lk = np.ascontiguousarray(lookup_grid, dtype=np.int32)
+    fb = None if fallback is None else np.ascontiguousarray(fallback, dtype=np.int32)
+    n = origin.shape[0]
+    out = np.empty(n, np.int32)
+    _check(_L().orc_cnnsns_start(n, _p(origin), lk.shape[0], _p(disp), _p(lk), _p(fb), _p(out)), "cnnsns_start")
+    return out
+
+
+def brute_force(xy, tri_ccw, xp):
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    host = np.empty(xp.shape[0], np.int32)
+    _check(_L().orc_brute_force(tri_ccw.shape[0], _p(xy), _p(tri_ccw), xp.shape[0], _p(xp), _p(host)),
+           "brute_force")
+    return host
+
+
+def cnnsns(xy, tri_ccw, nbr, lookup_grid, origin, xp, disp, fallback=None, max_iter: int = 0):
+    """Alg. 2 end to end from a given displacement grid: (start, host, iters, status)."""
+    st = cnnsns_start(origin, disp, lookup_grid, fallback)
+    h, it, s = sns(xy, tri_ccw, nbr, xp, st, max_iter)
+    return st, h, it, s
+
+
+# ---------------------------------------------------------------------------- metrics
+
+def element_centroids(xy, tri):
+    xy = np.asarray(xy)
+    return (xy[tri[:, 0]] + xy[tri[:, 1]] + xy[tri[:, 2]]) / 3.0
+
+
+def err_metric(xy, tri, start, host):
+    """Distance between the centroids of the start element and the host (Sec. 3.1)."""
+    c = element_centroids(xy, tri)
+    return np.hypot(*(c[host] - c[start]).T)
+
+
+def opt(c_sns: float, c_cnnsns: float) -> float:
+    """Optimisation rate (C(SNS) - C(CNN-SNS)) / C(SNS) (Sec. 3.1)."""
+    return (c_sns - c_cnnsns) / c_sns

@@ -1,0 +1,409 @@
+/*
+ * CPU oracle for 2D CNN-SNS particle location (Luo et al., "A CNN-based
+ * particle tracking method for large-scale fluid simulations with
+ * Lagrangian-Eulerian approaches").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the package smoke check and the benchmark's CPU-baseline leg may load it;
+ * the GPU library never links, imports or falls back to it, and it shares no
+ * code with the GPU library.
+ *
+ * Arithmetic: IEEE FP64 throughout for geometry, compiled with
+ * -ffp-contract=off (no fused multiply-add) and no fast-math, so every
+ * expression below is evaluated exactly as written, operation by operation.
+ * The CNN is accumulated in FP64 from FP32 inputs and weights widened exactly.
+ *
+ * Paper -> 2D: the paper works with tetrahedra (4 barycentric coordinates,
+ * 4 neighbours).  Here elements are triangles: 3 barycentric coordinates from
+ * 3x3 determinants and 3 neighbours, one across each edge.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC oracle.c
+ */
+#include <math.h>
+#include <omp.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_EMESH (-4)
+
+/* per-point outcome of a walk */
+#define ORC_FOUND 0
+#define ORC_OUTSIDE 1
+#define ORC_MAXITER 2
+#define ORC_BADSTART 3
+
+/* Number of threads used by the parallel loops (n <= 0 only queries). */
+int orc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
+
+/* ------------------------------------------------------------------------ */
+/* Element geometry.                                                         */
+
+/*
+ * Twice the signed area of triangle (a, b, c): the determinant |S_0| of the
+ * matrix of homogeneous vertex coordinates (Sec. 2.2, definition of the
+ * barycentric coordinates), in 2D.  Positive for counter-clockwise order.
+ */
+static double area2(const double* a, const double* b, const double* c)
+{
+    return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
+}
+
+/*
+ * The three barycentric numerators of p in the triangle with vertices
+ * v[0], v[1], v[2] (Sec. 2.2): s_j = |S_j| is the determinant with vertex j's
+ * column replaced by p, so lambda_j = s_j / |S_0|.  Written out, with indices
+ * taken mod 3:
+ *     s_j = (x_{j+1} - px) (y_{j+2} - py) - (y_{j+1} - py) (x_{j+2} - px).
+ * For a counter-clockwise triangle |S_0| > 0, so sign(lambda_j) = sign(s_j)
+ * and the smallest lambda_j is at the smallest s_j; the walk compares the
+ * numerators and never divides.  Because IEEE multiplication commutes and
+ * fl(b - a) = -fl(a - b), the numerator for a shared edge evaluated in the
+ * two triangles that share it (which traverse the edge in opposite
+ * directions) are exact negatives of each other.
+ */
+static void bary_numerators(const double* const v[3], const double* p, double s[3])
+{
+    for (int j = 0; j < 3; ++j) {
+        const double* u = v[(j + 1) % 3];
+        const double* w = v[(j + 2) % 3];
+        s[j] = (u[0] - p[0]) * (w[1] - p[1]) - (u[1] - p[1]) * (w[0] - p[0]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh preparation: the element list {K_l} and neighbour table {m^l}.      */
+
+/*
+ * Put every triangle in counter-clockwise order (swap its 2nd and 3rd vertex
+ * when |S_0| < 0), keeping triangle ids.  Zero-area triangles and vertex
+ * indices outside [0, n_nodes) are mesh errors.
+ */
+int orc_canonicalise(int64_t n_nodes, const double* xy, int64_t n_tri, const int32_t* tri_in, int32_t* tri_out)
+{
+    if (n_nodes < 0 || n_tri < 0 || (n_tri > 0 && (!xy || !tri_in || !tri_out))) return ORC_EINVAL;
+    for (int64_t t = 0; t < n_tri; ++t) {
+        int32_t a = tri_in[3 * t], b = tri_in[3 * t + 1], c = tri_in[3 * t + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= n_nodes || b >= n_nodes || c >= n_nodes) return ORC_EMESH;
+        double d = area2(xy + 2 * (int64_t)a, xy + 2 * (int64_t)b, xy + 2 * (int64_t)c);
+        if (d == 0.0) return ORC_EMESH;
+        tri_out[3 * t] = a;
+        tri_out[3 * t + 1] = d > 0 ? b : c;
+        tri_out[3 * t + 2] = d > 0 ? c : b;
+    }
+    return ORC_OK;
+}
+
+/*
+ * Neighbour table (Sec. 2.2): nbr[3t + j] is the triangle across the edge
+ * opposite vertex j of triangle t, i.e. the other triangle containing both
+ * vertices (j+1)%3 and (j+2)%3, or -1 when that edge is on the boundary.
+ * Mesh errors: an edge in more than two triangles, or an edge whose two
+ * triangles traverse it in the same direction (overlapping triangles).
+ * The triangles must already be counter-clockwise.
+ */
+int orc_neighbours(int64_t n_nodes, int64_t n_tri, const int32_t* tri, int32_t* nbr)
+{
+    if (n_nodes < 0 || n_tri < 0) return ORC_EINVAL;
+    int64_t* first = (int64_t*)calloc((size_t)n_nodes + 1, sizeof(int64_t));
+    int64_t* cursor = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_nodes + 1));
+    int32_t* inc = (int32_t*)malloc(sizeof(int32_t) * (size_t)(3 * n_tri + 1));
+    if (!first || !cursor || !inc) { free(first); free(cursor); free(inc); return ORC_ENOMEM; }
+    /* triangles incident to each node */
+    for (int64_t k = 0; k < 3 * n_tri; ++k) first[tri[k] + 1]++;
+    for (int64_t v = 0; v < n_nodes; ++v) first[v + 1] += first[v];
+    memcpy(cursor, first, sizeof(int64_t) * ((size_t)n_nodes + 1));
+    for (int64_t t = 0; t < n_tri; ++t)
+        for (int j = 0; j < 3; ++j) inc[cursor[tri[3 * t + j]]++] = (int32_t)t;
+    int rc = ORC_OK;
+    for (int64_t t = 0; t < n_tri && rc == ORC_OK; ++t) {
+        for (int j = 0; j < 3 && rc == ORC_OK; ++j) {
+            int32_t u = tri[3 * t + (j + 1) % 3], w = tri[3 * t + (j + 2) % 3];
+            int32_t found = -1;
+            for (int64_t k = first[u]; k < first[u + 1]; ++k) {
+                int32_t s = inc[k];
+                if (s == t) continue;
+                const int32_t* S = tri + 3 * (int64_t)s;
+                int iu = -1, iw = -1;
+                for (int q = 0; q < 3; ++q) {
+                    if (S[q] == u) iu = q;
+                    if (S[q] == w) iw = q;
+                }
+                if (iw < 0) continue;
+                if (found >= 0) { rc = ORC_EMESH; break; }       /* edge in 3+ triangles */
+                if ((iu + 1) % 3 == iw) { rc = ORC_EMESH; break; } /* same direction u->w */
+                found = s;
+            }
+            nbr[3 * t + j] = found;
+        }
+    }
+    free(first); free(cursor); free(inc);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1: successive neighbour search.                                */
+
+/*
+ * SNS walk for one point (Alg. 1 / eq. 6), from the start element k0:
+ *   I <- 0; loop { I <- I + 1; compute the barycentric coordinates of x_p in
+ *   the current element; if all are >= 0 the element contains x_p (closed
+ *   test, Sec. 2.2) -> stop; otherwise take j with the smallest coordinate
+ *   (eq. 5; ties go to the lowest j); if the neighbour m_j of the current
+ *   element is -1 the walk has reached the domain boundary and x_p lies
+ *   outside -> stop; else move to m_j }.
+ * The paper's loop has no bound; max_iter caps it (status MAXITER, returned
+ * with the element just moved to).  A start outside [0, n_tri) is reported
+ * as BADSTART with host -1 and zero iterations.
+ */
+static void sns_one(int64_t n_tri, const double* xy, const int32_t* tri, const int32_t* nbr,
+                    const double* p, int32_t k0, int32_t max_iter,
+                    int32_t* host, int32_t* iters, uint8_t* status)
+{
+    if (k0 < 0 || k0 >= n_tri) { *host = -1; *iters = 0; *status = ORC_BADSTART; return; }
+    int32_t K = k0, I = 0;
+    for (;;) {
+        I = I + 1;
+        const double* v[3] = { xy + 2 * (int64_t)tri[3 * (int64_t)K], xy + 2 * (int64_t)tri[3 * (int64_t)K + 1],
+                               xy + 2 * (int64_t)tri[3 * (int64_t)K + 2] };
+        double s[3];
+        bary_numerators(v, p, s);
+        if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0) { *host = K; *iters = I; *status = ORC_FOUND; return; }
+        int j = 0;
+        if (s[1] < s[j]) j = 1;
+        if (s[2] < s[j]) j = 2;
+        int32_t m = nbr[3 * (int64_t)K + j];
+        if (m == -1) { *host = K; *iters = I; *status = ORC_OUTSIDE; return; }
+        K = m;
+        if (I >= max_iter) { *host = K; *iters = I; *status = ORC_MAXITER; return; }
+    }
+}
+
+/*
+ * Locate n points: host[i] = SNS(xp[i], start[i]).  max_iter <= 0 selects
+ * the default cap 2^20.  tri must be counter-clockwise and nbr its
+ * neighbour table.  Points are independent; they are split over threads.
+ */
+int orc_sns(int64_t n_tri, const double* xy, const int32_t* tri, const int32_t* nbr,
+            int64_t n, const double* xp, const int32_t* start, int32_t max_iter,
+            int32_t* host, int32_t* iters, uint8_t* status)
+{
+    if (n < 0 || n_tri < 0) return ORC_EINVAL;
+    if (max_iter <= 0) max_iter = 1 << 20;
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i)
+        sns_one(n_tri, xy, tri, nbr, xp + 2 * i, start[i], max_iter, host + i, iters + i, status + i);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ASG overlay: cell -> element lookup.                                      */
+
+/*
+ * The auxiliary structured grid (Sec. 1, Alg. 2): a G x G Cartesian grid over
+ * the unit square.  lookup[cy*G + cx] is the smallest id of a triangle whose
+ * closed region contains the cell centre ((cx + 1/2)/G, (cy + 1/2)/G), or -1
+ * when no triangle contains it.  Triangles are visited in increasing id, and
+ * each tests the centres inside its bounding box (a conservative superset of
+ * the centres it can contain); the first triangle to claim a cell is the
+ * smallest containing id.  tri must be counter-clockwise.
+ */
+int orc_lookup(int64_t n_tri, const double* xy, const int32_t* tri, int32_t G, int32_t* lookup)
+{
+    if (G <= 0 || n_tri < 0) return ORC_EINVAL;
+    for (int64_t c = 0; c < (int64_t)G * G; ++c) lookup[c] = -1;
+    for (int64_t t = 0; t < n_tri; ++t) {
+        const double* v[3] = { xy + 2 * (int64_t)tri[3 * t], xy + 2 * (int64_t)tri[3 * t + 1],
+                               xy + 2 * (int64_t)tri[3 * t + 2] };
+        double xmin = fmin(v[0][0], fmin(v[1][0], v[2][0])), xmax = fmax(v[0][0], fmax(v[1][0], v[2][0]));
+        double ymin = fmin(v[0][1], fmin(v[1][1], v[2][1])), ymax = fmax(v[0][1], fmax(v[1][1], v[2][1]));
+        /* centre (c + 1/2)/G in [min, max]  <=>  c in [min*G - 1/2, max*G - 1/2]; widened by one */
+        int64_t cx0 = (int64_t)floor(xmin * G - 0.5) - 1, cx1 = (int64_t)ceil(xmax * G - 0.5) + 1;
+        int64_t cy0 = (int64_t)floor(ymin * G - 0.5) - 1, cy1 = (int64_t)ceil(ymax * G - 0.5) + 1;
+        if (cx0 < 0) cx0 = 0;
+        if (cy0 < 0) cy0 = 0;
+        if (cx1 > G - 1) cx1 = G - 1;
+        if (cy1 > G - 1) cy1 = G - 1;
+        for (int64_t cy = cy0; cy <= cy1; ++cy) {
+            for (int64_t cx = cx0; cx <= cx1; ++cx) {
+                if (lookup[cy * G + cx] != -1) continue;
+                double p[2] = { ((double)cx + 0.5) / (double)G, ((double)cy + 0.5) / (double)G };
+                double s[3];
+                bary_numerators(v, p, s);
+                if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0) lookup[cy * G + cx] = (int32_t)t;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* CNN: displacement predictor over the overlay grid.                        */
+
+/*
+ * One 3x3 convolution layer (stride 1, "same" zero padding, cross-correlation
+ * with weights in [out][in][ky][kx] order, bias, optional ReLU; the layers of
+ * Sec. 2.3 with ReLU between layers), evaluated on a window of the G x G grid:
+ *   y[o][r][c] = b[o] + sum_i sum_{dy,dx in -1..1} W[o][i][dy+1][dx+1] * x[i][r+dy][c+dx],
+ * where x is zero outside [0, G)^2.  The input window covers global rows
+ * [ir0, ir0 + ih) and columns [ic0, ic0 + iw); the output window
+ * [or0, or0 + oh) x [oc0, oc0 + ow) must be such that every in-grid tap falls
+ * inside the input window.
+ */
+static void conv3x3(int32_t G, const double* x, int32_t cin, int64_t ir0, int64_t ic0, int64_t ih, int64_t iw,
+                    double* y, int32_t cout, int64_t or0, int64_t oc0, int64_t oh, int64_t ow,
+                    const double* W, const double* b, int relu)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t rr = 0; rr < oh; ++rr) {
+        for (int32_t o = 0; o < cout; ++o) {
+            for (int64_t cc = 0; cc < ow; ++cc) {
+                int64_t r = or0 + rr, c = oc0 + cc;
+                double acc = b[o];
+                for (int32_t i = 0; i < cin; ++i) {
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            int64_t R = r + dy, C = c + dx;
+                            if (R < 0 || R >= G || C < 0 || C >= G) continue;
+                            double xv = x[((int64_t)i * ih + (R - ir0)) * iw + (C - ic0)];
+                            acc += W[(((int64_t)o * cin + i) * 3 + (dy + 1)) * 3 + (dx + 1)] * xv;
+                        }
+                    }
+                }
+                if (relu && acc < 0.0) acc = 0.0;
+                y[((int64_t)o * oh + rr) * ow + cc] = acc;
+            }
+        }
+    }
+}
+
+/*
+ * Four-layer displacement CNN, channels chan[0] -> chan[1] -> ... -> chan[4]
+ * (2 -> 32 -> 32 -> 32 -> 2 for the velocity-to-displacement net), ReLU after
+ * layers 1-3 and none after the last.  Evaluates the output on rows
+ * [r0, r0+h) and columns [c0, c0+w) of the G x G grid; with r0 = c0 = 0 and
+ * h = w = G this is the whole forward pass.  Each inner layer is computed on
+ * the output window grown by one cell per remaining layer (clipped to the
+ * grid), so that the result equals the full-grid forward pass restricted to
+ * the window.
+ *   vel: FP32 [chan0][G][G]; w[l]: FP32 [chan(l+1)][chan(l)][3][3]; b[l]: FP32;
+ *   out: FP64 [chan4][h][w].
+ */
+int orc_cnn_window(int32_t G, const float* vel, const int32_t* chan, const float* const* w, const float* const* b,
+                   int64_t r0, int64_t c0, int64_t h, int64_t wd, double* out)
+{
+    if (G <= 0 || h <= 0 || wd <= 0 || r0 < 0 || c0 < 0 || r0 + h > G || c0 + wd > G) return ORC_EINVAL;
+    /* window of each activation: act 0 = input, act 4 = output */
+    int64_t wr0[5], wc0[5], wh[5], ww[5];
+    for (int l = 0; l <= 4; ++l) {
+        int64_t grow = 4 - l;
+        int64_t ra = r0 - grow, rb = r0 + h + grow, ca = c0 - grow, cb = c0 + wd + grow;
+        if (ra < 0) ra = 0;
+        if (ca < 0) ca = 0;
+        if (rb > G) rb = G;
+        if (cb > G) cb = G;
+        wr0[l] = ra; wc0[l] = ca; wh[l] = rb - ra; ww[l] = cb - ca;
+    }
+    double* act[5] = { 0 };
+    double* Wd[4] = { 0 };
+    double* bd[4] = { 0 };
+    int rc = ORC_OK;
+    for (int l = 0; l <= 4; ++l) {
+        act[l] = (double*)malloc(sizeof(double) * (size_t)(chan[l] * wh[l] * ww[l]));
+        if (!act[l]) rc = ORC_ENOMEM;
+    }
+    for (int l = 0; l < 4; ++l) {
+        Wd[l] = (double*)malloc(sizeof(double) * (size_t)(chan[l + 1] * chan[l] * 9));
+        bd[l] = (double*)malloc(sizeof(double) * (size_t)chan[l + 1]);
+        if (!Wd[l] || !bd[l]) rc = ORC_ENOMEM;
+    }
+    if (rc == ORC_OK) {
+        for (int l = 0; l < 4; ++l) {
+            for (int64_t k = 0; k < (int64_t)chan[l + 1] * chan[l] * 9; ++k) Wd[l][k] = (double)w[l][k];
+            for (int32_t k = 0; k < chan[l + 1]; ++k) bd[l][k] = (double)b[l][k];
+        }
+        for (int32_t i = 0; i < chan[0]; ++i)
+            for (int64_t r = 0; r < wh[0]; ++r)
+                for (int64_t c = 0; c < ww[0]; ++c)
+                    act[0][((int64_t)i * wh[0] + r) * ww[0] + c] =
+                        (double)vel[((int64_t)i * G + (wr0[0] + r)) * G + (wc0[0] + c)];
+        for (int l = 0; l < 4; ++l)
+            conv3x3(G, act[l], chan[l], wr0[l], wc0[l], wh[l], ww[l], act[l + 1], chan[l + 1], wr0[l + 1],
+                    wc0[l + 1], wh[l + 1], ww[l + 1], Wd[l], bd[l], l < 3);
+        memcpy(out, act[4], sizeof(double) * (size_t)(chan[4] * h * wd));
+    }
+    for (int l = 0; l <= 4; ++l) free(act[l]);
+    for (int l = 0; l < 4; ++l) { free(Wd[l]); free(bd[l]); }
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 2: the CNN-SNS start element.                                   */
+
+/* overlay cell index of a coordinate: min(G-1, floor(x G)), clamped to >= 0 */
+static int64_t cell_of(double x, int32_t G)
+{
+    double f = floor(x * (double)G);
+    if (!(f >= 0.0)) return 0; /* negative or NaN */
+    if (f > (double)(G - 1)) return G - 1;
+    return (int64_t)f;
+}
+
+/*
+ * Start element K_p of CNN-SNS (Alg. 2): the predicted departure point is
+ * x_hat = clamp(x_i + D, 0, 1), with D the predicted displacement of the
+ * overlay cell holding the origin x_i, and K_p is the overlay lookup of the
+ * cell holding x_hat.  When that cell has no element (-1), the fallback
+ * start[i] is used if given, else element 0.
+ *   origin: [n][2]; disp: [2][G][G] (x then y component); lookup: [G][G].
+ */
+int orc_cnnsns_start(int64_t n, const double* origin, int32_t G, const double* disp, const int32_t* lookup,
+                     const int32_t* fallback, int32_t* start_out)
+{
+    if (n < 0 || G <= 0) return ORC_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t cx = cell_of(origin[2 * i], G), cy = cell_of(origin[2 * i + 1], G);
+        double dx = disp[(0 * (int64_t)G + cy) * G + cx];
+        double dy = disp[(1 * (int64_t)G + cy) * G + cx];
+        double hx = origin[2 * i] + dx, hy = origin[2 * i + 1] + dy;
+        hx = hx < 0.0 ? 0.0 : (hx > 1.0 ? 1.0 : hx);
+        hy = hy < 0.0 ? 0.0 : (hy > 1.0 ? 1.0 : hy);
+        int32_t k = lookup[cell_of(hy, G) * G + cell_of(hx, G)];
+        if (k < 0) k = fallback ? fallback[i] : 0;
+        start_out[i] = k;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exhaustive containment (the definition of the host element).              */
+
+/*
+ * For each point, the smallest id of a triangle whose closed region contains
+ * it, testing every triangle (Sec. 2.2: x_p lies in K_l iff all barycentric
+ * coordinates are >= 0), or -1.  O(n * n_tri): small meshes only.
+ */
+int orc_brute_force(int64_t n_tri, const double* xy, const int32_t* tri, int64_t n, const double* xp,
+                    int32_t* host)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        host[i] = -1;
+        for (int64_t t = 0; t < n_tri; ++t) {
+            const double* v[3] = { xy + 2 * (int64_t)tri[3 * t], xy + 2 * (int64_t)tri[3 * t + 1],
+                                   xy + 2 * (int64_t)tri[3 * t + 2] };
+            double s[3];
+            bary_numerators(v, xp + 2 * i, s);
+            if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0) { host[i] = (int32_t)t; break; }
+        }
+    }
+    return ORC_OK;
+}
