@@ -1,0 +1,212 @@
+/*
+ * cnnsns.h - CNN-accelerated successive-neighbour-search particle location on
+ * unstructured 2D triangle meshes, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Luo et al., "A CNN-based particle tracking method for large-scale
+ * fluid simulations with Lagrangian-Eulerian approaches" (arXiv 2412.18379).
+ * For every Lagrangian point x_p the library finds its host element K_t, the
+ * mesh element whose closed region contains x_p (Sec. 2.1-2.2).  The search is
+ * the successive neighbour search (SNS, Alg. 1, eq. 6): from a start element,
+ * compute the barycentric coordinates of x_p, stop when all are >= 0,
+ * otherwise step to the neighbour across the edge with the smallest
+ * coordinate (eq. 5).  CNN-SNS (Alg. 2) starts the same walk from an element
+ * predicted by a CNN instead of the host element before movement.  The
+ * paper's elements are tetrahedra; here they are triangles (3 barycentric
+ * coordinates, 3 neighbours), and the CNN predicts, for every cell of a
+ * G x G overlay grid on the unit square (the auxiliary structured grid of
+ * Sec. 1 / Alg. 2), the displacement from a point's position before movement
+ * to its departure point, from the Eulerian velocity sampled on that grid.
+ *
+ * Conventions shared by every call:
+ *  - Every function is extern "C", never throws, and returns an int32 status:
+ *    CNNSNS_OK (0) or a negative error code.  cnnsns_last_error() returns a
+ *    thread-local message describing the last non-OK return of this thread.
+ *  - "host" pointers point to CPU memory, "device" pointers to GPU memory of
+ *    the device that was current when the mesh was built.  The library never
+ *    takes ownership of caller memory; caller buffers passed to asynchronous
+ *    calls must stay valid until the stream has been synchronised (predict,
+ *    locate) or the job is complete (submit).
+ *  - Streams are hipStream_t passed as void* (NULL = the null stream).
+ *  - Element ids are the caller's triangle indices (0-based).
+ *  - Geometry is FP64 everywhere: the walk's containment and direction tests
+ *    are exact IEEE double evaluations with no fused multiply-add, so results
+ *    are bitwise reproducible and independent of batching.
+ */
+#ifndef CNNSNS_H
+#define CNNSNS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Call-level status codes. */
+enum {
+    CNNSNS_OK = 0,
+    CNNSNS_EINVAL = -1, /* invalid argument (null pointer, negative size, bad enum, ...) */
+    CNNSNS_ENOMEM = -2, /* device or host allocation failed, or a memory budget is exceeded */
+    CNNSNS_EHIP = -3,   /* a HIP runtime call failed */
+    CNNSNS_EMESH = -4,  /* the mesh is invalid (see cnnsns_build_mesh) */
+    CNNSNS_EBUSY = -5,  /* the serving queue is full; retry later */
+};
+
+/* Per-point outcome of a walk (not an error). */
+enum {
+    CNNSNS_FOUND = 0,    /* host[i] contains x_p (all barycentric coordinates >= 0) */
+    CNNSNS_OUTSIDE = 1,  /* the walk reached a boundary edge (neighbour -1): x_p lies outside
+                            the mesh (Alg. 1's second exit); host[i] is the last element */
+    CNNSNS_MAXITER = 2,  /* max_iter iterations were used up; host[i] is the element reached */
+    CNNSNS_BADSTART = 3, /* the start element id was outside [0, n_tri); host[i] = -1, iters 0 */
+};
+
+/* CNN arithmetic precision for cnnsns_predict / the serving loop. */
+enum {
+    CNNSNS_F32 = 0,     /* FP32 operands, FP32 accumulation */
+    CNNSNS_BF16 = 1,    /* BF16 operands and activations, FP32 accumulation */
+    CNNSNS_FP8E4M3 = 2, /* FP8 e4m3 weights and activations with per-channel scales, FP32 accumulation */
+};
+
+typedef struct cnnsns_mesh_s* cnnsns_mesh;
+typedef struct cnnsns_server_s* cnnsns_server;
+
+/*
+ * Weights of the displacement CNN: four 3x3 convolution layers with channel
+ * counts 2 -> 32 -> 32 -> 32 -> 2, stride 1, zero "same" padding (the padding
+ * layer of Sec. 2.3), bias, and ReLU between layers (Sec. 2.3: after layers
+ * 1-3, none after the last).  The operation is cross-correlation:
+ *   y[o][r][c] = b[o] + sum_i sum_{dy,dx=-1..1} w[o][i][dy+1][dx+1] * x[i][r+dy][c+dx].
+ * w[l] is a DEVICE pointer to FP32 [C_out][C_in][3][3] (OIHW), b[l] a DEVICE
+ * pointer to FP32 [C_out].  Lower precisions are derived from these FP32
+ * weights by the library on each call.
+ */
+typedef struct {
+    const float* w[4];
+    const float* b[4];
+} cnnsns_cnn;
+
+/*
+ * Build a device-resident mesh: the element list {K_l} and the neighbour
+ * table {m_j^l} that the SNS walk reads (Sec. 2.2, eq. 6), plus the overlay
+ * lookup lookup[cy][cx] = the smallest id of an element whose closed region
+ * contains the cell centre ((cx + 1/2)/G, (cy + 1/2)/G), or -1 when none does
+ * (the ASG overlay of Sec. 1 / Alg. 2, over the unit square).
+ *
+ *   xy           HOST FP64 [n_nodes][2] node coordinates.
+ *   tri          HOST int32 [n_tri][3] node indices per triangle, 0-based, any
+ *                orientation (the library orders each triangle counter-clockwise;
+ *                neighbour j of a triangle is across the edge opposite its
+ *                j-th counter-clockwise vertex).
+ *   overlay_side G >= 1, or 0 to choose 2^ceil(log2(sqrt(n_tri))).
+ *   stream       stream for the upload and build kernels; the call waits for it.
+ *   out          receives the handle (owned by the library until cnnsns_destroy_mesh).
+ *
+ * The inputs are copied; the caller keeps its arrays.  Errors: EINVAL (null
+ * pointer, n_nodes < 3, n_tri < 1, overlay_side < 0 or > 65536), EMESH (a
+ * node index out of range, a zero-area triangle, an edge in more than two
+ * triangles, or two triangles that overlap across an edge), ENOMEM, EHIP.
+ */
+int cnnsns_build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, int64_t n_tri,
+                      int32_t overlay_side, void* stream, cnnsns_mesh* out);
+
+/*
+ * Facts about a built mesh; any output pointer may be NULL.  device_bytes is
+ * the device memory the handle holds; mean_diam the mean over triangles of
+ * the longest edge.
+ */
+int cnnsns_mesh_info(cnnsns_mesh m, int64_t* n_tri, int32_t* overlay_side, int64_t* device_bytes,
+                     double* mean_diam);
+
+/* Free a mesh and its device memory (synchronises the device first). NULL is a no-op. */
+int cnnsns_destroy_mesh(cnnsns_mesh m);
+
+/*
+ * CNN forward pass over the mesh's G x G overlay (the prediction step of
+ * Alg. 2, in the displacement-regression form described above):
+ *   vel   DEVICE FP32 [2][G][G], (u, v) at the cell centres, row = y index.
+ *   w     the weights (device pointers, see cnnsns_cnn).
+ *   precision  CNNSNS_F32, CNNSNS_BF16 or CNNSNS_FP8E4M3.
+ *   disp  DEVICE FP32 [2][G][G] output (caller-owned): predicted (dx, dy).
+ * Asynchronous on `stream`.  Errors: EINVAL, ENOMEM, EHIP.
+ */
+int cnnsns_predict(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t precision, float* disp,
+                   void* stream);
+
+/*
+ * Locate n points (Alg. 1 for every point; Alg. 2 when a displacement grid is
+ * given).  All arrays are DEVICE memory:
+ *   xp      FP64 [n][2] query points x_p (departure points).
+ *   start   int32 [n] start elements, or NULL.
+ *   origin  FP64 [n][2] positions before movement x_i, or NULL.
+ *   disp    FP32 [2][G][G] predicted displacements (from cnnsns_predict), or NULL.
+ *   max_iter  iteration cap per point; <= 0 selects 2^20.
+ *   host    int32 [n] output host element ids.
+ *   iters   int32 [n] output path lengths I_t (Alg. 1's counter; 1 when the
+ *           start contains x_p), or NULL.
+ *   status  uint8 [n] output per-point outcome (CNNSNS_FOUND ...), or NULL.
+ * Start element per point:
+ *   disp and origin given (CNN-SNS, Alg. 2): x_hat = clamp(x_i + D, 0, 1) with
+ *     D the displacement of the overlay cell holding x_i, and the start is the
+ *     overlay lookup of the cell holding x_hat; if that cell has no element,
+ *     start[i] when start is given, else element 0.  Cell of a coordinate:
+ *     min(G-1, max(0, floor(coord * G))).
+ *   else start given (plain SNS, Alg. 1 from K_m): start[i].
+ *   else (neither): the overlay lookup of the cell holding x_p itself (the
+ *     ASG locator of Sec. 1), element 0 where that cell has no element.
+ * Asynchronous on `stream`.  n == 0 is a no-op.  Errors: EINVAL (null mesh,
+ * xp or host, n < 0, disp without origin), EHIP.
+ */
+int cnnsns_locate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* start, const double* origin,
+                  const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status,
+                  void* stream);
+
+/*
+ * Serving loop: a host scheduler that takes CNN-SNS tracking jobs on
+ * resident meshes as they arrive and runs them with continuous batching.
+ * Each job is one CNN forward pass over its mesh's overlay (in `precision`)
+ * followed by the CNN-SNS locate of its points, exactly as cnnsns_predict +
+ * cnnsns_locate would compute them (results do not depend on what else is
+ * in flight).  Jobs are admitted in arrival order while their device
+ * footprint (the displacement grid and CNN activations) fits in
+ * hbm_budget_bytes and fewer than max_inflight jobs are running; admitted
+ * jobs run concurrently on several streams.
+ *   hbm_budget_bytes  budget for per-job device memory (> 0).
+ *   max_inflight      jobs on the device at once (>= 1).
+ *   queue_depth       jobs waiting for admission at most (>= 1).
+ *   w                 CNN weights (device pointers; copied at creation).
+ */
+int cnnsns_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int32_t queue_depth,
+                         int32_t precision, const cnnsns_cnn* w, cnnsns_server* out);
+
+/*
+ * Submit a job: locate n points of mesh m whose overlay velocity is vel
+ * (DEVICE FP32 [2][G][G]), with x_p = xp (DEVICE FP64 [n][2]) and positions
+ * before movement origin (DEVICE FP64 [n][2]); results go to host / iters
+ * (DEVICE int32 [n], iters may be NULL).  start (DEVICE int32 [n]) may be
+ * NULL; it is only the fallback for uncovered overlay cells.  Buffers must
+ * stay valid until the job completes.  Returns at once with *job_id.
+ * Errors: EINVAL, EBUSY (queue full), ENOMEM (the job alone exceeds the budget).
+ */
+int cnnsns_submit(cnnsns_server s, cnnsns_mesh m, const float* vel, int64_t n, const double* xp,
+                  const double* origin, const int32_t* start, int32_t* host, int32_t* iters, uint64_t* job_id);
+
+/*
+ * Completion of a job: *done = 1 when its results are in device memory.
+ * latency_ms (may be NULL) gets submit-to-completion time once done.
+ */
+int cnnsns_poll(cnnsns_server s, uint64_t job_id, int32_t* done, double* latency_ms);
+
+/* Block until the job is complete. */
+int cnnsns_wait(cnnsns_server s, uint64_t job_id, double* latency_ms);
+
+/* Drain every submitted job, then free the server.  NULL is a no-op. */
+int cnnsns_server_destroy(cnnsns_server s);
+
+/* Message for the last non-OK return on the calling thread ("" if none). */
+const char* cnnsns_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CNNSNS_H */

@@ -1,0 +1,231 @@
+"""Thin ctypes binding of libcnnsns.so (the C ABI in include/cnnsns.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory (``tensor.data_ptr()``) and streams
+(``torch.cuda.current_stream().cuda_stream``).  There is no fallback: if the
+library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcnnsns.so")
+
+OK, EINVAL, ENOMEM, EHIP, EMESH, EBUSY = 0, -1, -2, -3, -4, -5
+FOUND, OUTSIDE, MAXITER, BADSTART = 0, 1, 2, 3
+F32, BF16, FP8E4M3 = 0, 1, 2
+PRECISIONS = {"f32": F32, "bf16": BF16, "fp8": FP8E4M3}
+
+EXPORTS = (
+    "cnnsns_build_mesh", "cnnsns_mesh_info", "cnnsns_destroy_mesh", "cnnsns_predict", "cnnsns_locate",
+    "cnnsns_server_create", "cnnsns_submit", "cnnsns_poll", "cnnsns_wait", "cnnsns_server_destroy",
+    "cnnsns_last_error",
+)
+
+_lib = None
+
+
+class CnnsnsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class _Cnn(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p * 4), ("b", ctypes.c_void_p * 4)]
+
+
+def lib():
+    """Load libcnnsns.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        sig = {
+            "cnnsns_build_mesh": [vp, i64, vp, i64, i32, vp, ctypes.POINTER(vp)],
+            "cnnsns_mesh_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                 ctypes.POINTER(ctypes.c_double)],
+            "cnnsns_destroy_mesh": [vp],
+            "cnnsns_predict": [vp, vp, ctypes.POINTER(_Cnn), i32, vp, vp],
+            "cnnsns_locate": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp],
+            "cnnsns_server_create": [i64, i32, i32, i32, ctypes.POINTER(_Cnn), ctypes.POINTER(vp)],
+            "cnnsns_submit": [vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)],
+            "cnnsns_poll": [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
+            "cnnsns_wait": [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)],
+            "cnnsns_server_destroy": [vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.cnnsns_last_error.argtypes = []
+        L.cnnsns_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise CnnsnsError(rc, lib().cnnsns_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _need(t: Optional[torch.Tensor], dtype, shape=None, name="tensor"):
+    if t is None:
+        return
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Mesh:
+    """A device-resident mesh (cnnsns_build_mesh).  xy, tri are host numpy arrays."""
+
+    def __init__(self, xy, tri, overlay_side: int = 0, stream=None):
+        import numpy as np
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        if xy.ndim != 2 or xy.shape[1] != 2 or tri.ndim != 2 or tri.shape[1] != 3:
+            raise ValueError("xy must be [n,2] and tri [m,3]")
+        h = ctypes.c_void_p()
+        _check(lib().cnnsns_build_mesh(xy.ctypes.data, xy.shape[0], tri.ctypes.data, tri.shape[0],
+                                       int(overlay_side), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        n_tri, G, nbytes, diam = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().cnnsns_mesh_info(h, ctypes.byref(n_tri), ctypes.byref(G), ctypes.byref(nbytes),
+                                      ctypes.byref(diam)))
+        self.n_tri, self.G, self.device_bytes, self.mean_diam = n_tri.value, G.value, nbytes.value, diam.value
+
+    def close(self):
+        if self.handle:
+            _check(lib().cnnsns_destroy_mesh(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Weights:
+    """CNN weights as device tensors (FP32 OIHW + bias), kept alive with the struct."""
+
+    def __init__(self, ws: Sequence, bs: Sequence, device="cuda"):
+        self.w = [torch.as_tensor(w, dtype=torch.float32).to(device).contiguous() for w in ws]
+        self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in bs]
+        if len(self.w) != 4 or len(self.b) != 4:
+            raise ValueError("four layers expected")
+        chans = [self.w[0].shape[1]] + [w.shape[0] for w in self.w]
+        if chans != [2, 32, 32, 32, 2] or any(tuple(w.shape[2:]) != (3, 3) for w in self.w):
+            raise ValueError(f"expected a 2-32-32-32-2 3x3 net, got {chans}")
+        self.struct = _Cnn()
+        for l in range(4):
+            self.struct.w[l] = self.w[l].data_ptr()
+            self.struct.b[l] = self.b[l].data_ptr()
+
+
+def predict(mesh: Mesh, vel: torch.Tensor, weights: Weights, precision="f32", disp: torch.Tensor = None,
+            stream=None) -> torch.Tensor:
+    G = mesh.G
+    _need(vel, torch.float32, (2, G, G), "vel")
+    if disp is None:
+        disp = torch.empty((2, G, G), dtype=torch.float32, device=vel.device)
+    _need(disp, torch.float32, (2, G, G), "disp")
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().cnnsns_predict(mesh.handle, _ptr(vel), ctypes.byref(weights.struct), p, _ptr(disp),
+                                _stream(stream)))
+    return disp
+
+
+def locate(mesh: Mesh, xp: torch.Tensor, start: torch.Tensor = None, origin: torch.Tensor = None,
+           disp: torch.Tensor = None, max_iter: int = 0, host: torch.Tensor = None, iters: torch.Tensor = None,
+           status: torch.Tensor = None, want_iters=True, want_status=True, stream=None):
+    n = xp.shape[0]
+    _need(xp, torch.float64, (n, 2), "xp")
+    _need(start, torch.int32, (n,), "start")
+    _need(origin, torch.float64, (n, 2), "origin")
+    _need(disp, torch.float32, (2, mesh.G, mesh.G), "disp")
+    dev = xp.device
+    if host is None:
+        host = torch.empty(n, dtype=torch.int32, device=dev)
+    if iters is None and want_iters:
+        iters = torch.empty(n, dtype=torch.int32, device=dev)
+    if status is None and want_status:
+        status = torch.empty(n, dtype=torch.uint8, device=dev)
+    _need(host, torch.int32, (n,), "host")
+    _need(iters, torch.int32, (n,), "iters")
+    _need(status, torch.uint8, (n,), "status")
+    _check(lib().cnnsns_locate(mesh.handle, n, _ptr(xp), _ptr(start), _ptr(origin), _ptr(disp), int(max_iter),
+                               _ptr(host), _ptr(iters), _ptr(status), _stream(stream)))
+    return host, iters, status
+
+
+class Server:
+    """Serving loop (cnnsns_server_*)."""
+
+    def __init__(self, weights: Weights, hbm_budget_bytes: int, max_inflight: int = 4, queue_depth: int = 1024,
+                 precision="bf16"):
+        self.weights = weights
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        _check(lib().cnnsns_server_create(int(hbm_budget_bytes), int(max_inflight), int(queue_depth), p,
+                                          ctypes.byref(weights.struct), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, mesh: Mesh, vel, xp, origin, host, iters=None, start=None) -> int:
+        jid = ctypes.c_uint64()
+        _check(lib().cnnsns_submit(self.handle, mesh.handle, _ptr(vel), xp.shape[0], _ptr(xp), _ptr(origin),
+                                   _ptr(start), _ptr(host), _ptr(iters), ctypes.byref(jid)))
+        self._keep[jid.value] = (vel, xp, origin, host, iters, start)
+        return jid.value
+
+    def poll(self, job_id: int):
+        done, lat = ctypes.c_int32(), ctypes.c_double()
+        _check(lib().cnnsns_poll(self.handle, job_id, ctypes.byref(done), ctypes.byref(lat)))
+        if done.value:
+            self._keep.pop(job_id, None)
+            return lat.value
+        return None
+
+    def wait(self, job_id: int) -> float:
+        lat = ctypes.c_double()
+        _check(lib().cnnsns_wait(self.handle, job_id, ctypes.byref(lat)))
+        self._keep.pop(job_id, None)
+        return lat.value
+
+    def close(self):
+        if self.handle:
+            _check(lib().cnnsns_server_destroy(self.handle))
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

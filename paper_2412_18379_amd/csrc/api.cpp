@@ -1,0 +1,172 @@
+// The C ABI: argument checks, error codes and the thread-local error message.
+// Every exported function catches everything; nothing propagates to C.
+#include <hip/hip_runtime.h>
+
+#include <exception>
+#include <new>
+#include <string>
+
+#include "common.h"
+#include "serve.h"
+
+namespace cnnsns {
+
+static thread_local std::string g_last_error;
+
+void fail(int code, const std::string& msg)
+{
+    throw Error{ code, msg };
+}
+
+void hip_check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? CNNSNS_ENOMEM : CNNSNS_EHIP,
+             std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+template <class F>
+static int guarded(F&& f)
+{
+    try {
+        f();
+        g_last_error.clear();
+        return CNNSNS_OK;
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return CNNSNS_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return CNNSNS_EINVAL;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return CNNSNS_EINVAL;
+    }
+}
+
+// Run on the mesh's device, restoring the caller's current device afterwards.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev)
+    {
+        hip_check(hipGetDevice(&prev), "hipGetDevice");
+        if (prev != dev) hip_check(hipSetDevice(dev), "hipSetDevice");
+    }
+    ~DeviceScope()
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace cnnsns
+
+using namespace cnnsns;
+
+extern "C" {
+
+int cnnsns_build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, int64_t n_tri, int32_t overlay_side,
+                      void* stream, cnnsns_mesh* out)
+{
+    return guarded([&] {
+        if (!out) fail(CNNSNS_EINVAL, "build_mesh: out must not be NULL");
+        *out = nullptr;
+        *out = build_mesh(xy, n_nodes, tri, n_tri, overlay_side, static_cast<hipStream_t>(stream));
+    });
+}
+
+int cnnsns_mesh_info(cnnsns_mesh m, int64_t* n_tri, int32_t* overlay_side, int64_t* device_bytes, double* mean_diam)
+{
+    return guarded([&] {
+        if (!m) fail(CNNSNS_EINVAL, "mesh_info: NULL mesh");
+        if (n_tri) *n_tri = m->n_tri;
+        if (overlay_side) *overlay_side = m->G;
+        if (device_bytes) *device_bytes = m->device_bytes;
+        if (mean_diam) *mean_diam = m->mean_diam;
+    });
+}
+
+int cnnsns_destroy_mesh(cnnsns_mesh m)
+{
+    return guarded([&] { destroy_mesh(m); });
+}
+
+int cnnsns_predict(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t precision, float* disp, void* stream)
+{
+    return guarded([&] {
+        if (!m || !vel || !w || !disp) fail(CNNSNS_EINVAL, "predict: NULL argument");
+        for (int l = 0; l < 4; ++l)
+            if (!w->w[l] || !w->b[l]) fail(CNNSNS_EINVAL, "predict: NULL weight or bias pointer");
+        if (precision != CNNSNS_F32 && precision != CNNSNS_BF16 && precision != CNNSNS_FP8E4M3)
+            fail(CNNSNS_EINVAL, "predict: unknown precision");
+        DeviceScope ds(m->device);
+        run_predict(*m, vel, *w, precision, disp, static_cast<hipStream_t>(stream));
+    });
+}
+
+int cnnsns_locate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* start, const double* origin,
+                  const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status, void* stream)
+{
+    return guarded([&] {
+        if (!m) fail(CNNSNS_EINVAL, "locate: NULL mesh");
+        if (n < 0) fail(CNNSNS_EINVAL, "locate: n must be >= 0");
+        if (n == 0) return;
+        if (!xp || !host) fail(CNNSNS_EINVAL, "locate: xp and host must not be NULL");
+        if (disp && !origin) fail(CNNSNS_EINVAL, "locate: disp given without origin");
+        DeviceScope ds(m->device);
+        launch_locate(*m, n, xp, start, origin, disp, max_iter, host, iters, status, static_cast<hipStream_t>(stream));
+    });
+}
+
+int cnnsns_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int32_t queue_depth, int32_t precision,
+                         const cnnsns_cnn* w, cnnsns_server* out)
+{
+    return guarded([&] {
+        if (!out) fail(CNNSNS_EINVAL, "server_create: out must not be NULL");
+        *out = nullptr;
+        *out = server_create(hbm_budget_bytes, max_inflight, queue_depth, precision, w);
+    });
+}
+
+int cnnsns_submit(cnnsns_server s, cnnsns_mesh m, const float* vel, int64_t n, const double* xp, const double* origin,
+                  const int32_t* start, int32_t* host, int32_t* iters, uint64_t* job_id)
+{
+    return guarded([&] {
+        if (!s || !m || !vel || !xp || !origin || !host || !job_id) fail(CNNSNS_EINVAL, "submit: NULL argument");
+        if (n < 0) fail(CNNSNS_EINVAL, "submit: n must be >= 0");
+        *job_id = server_submit(s, m, vel, n, xp, origin, start, host, iters);
+    });
+}
+
+int cnnsns_poll(cnnsns_server s, uint64_t job_id, int32_t* done, double* latency_ms)
+{
+    return guarded([&] {
+        if (!s || !done) fail(CNNSNS_EINVAL, "poll: NULL argument");
+        *done = server_poll(s, job_id, latency_ms) ? 1 : 0;
+    });
+}
+
+int cnnsns_wait(cnnsns_server s, uint64_t job_id, double* latency_ms)
+{
+    return guarded([&] {
+        if (!s) fail(CNNSNS_EINVAL, "wait: NULL server");
+        server_wait(s, job_id, latency_ms);
+    });
+}
+
+int cnnsns_server_destroy(cnnsns_server s)
+{
+    return guarded([&] { server_destroy(s); });
+}
+
+const char* cnnsns_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+}  // extern "C"

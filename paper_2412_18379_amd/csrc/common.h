@@ -1,0 +1,63 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/cnnsns.h"
+
+namespace cnnsns {
+
+// One mesh element as the walk reads it: the three counter-clockwise vertex
+// coordinates and the three neighbour ids (neighbour j across the edge
+// opposite vertex j, -1 on the boundary), packed into one 64-byte aligned
+// record so that a hop is a single 64-byte gather.
+struct alignas(64) ElemRec {
+    double ax, ay, bx, by, cx, cy;
+    int32_t n0, n1, n2, pad;
+};
+static_assert(sizeof(ElemRec) == 64, "element record must be 64 bytes");
+
+// Error with a status code; thrown inside the library and turned into a
+// return code plus a thread-local message at the C boundary.
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+
+}  // namespace cnnsns
+
+struct cnnsns_mesh_s {
+    int device = 0;
+    int64_t n_nodes = 0;
+    int64_t n_tri = 0;
+    int32_t G = 0;
+    double mean_diam = 0.0;
+    cnnsns::ElemRec* rec = nullptr;  // device [n_tri]
+    int32_t* lookup = nullptr;       // device [G][G]
+    int64_t device_bytes = 0;
+};
+
+namespace cnnsns {
+
+// mesh.hip
+cnnsns_mesh build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, int64_t n_tri, int32_t G,
+                       hipStream_t stream);
+void destroy_mesh(cnnsns_mesh m);
+
+// sns_walk.hip
+enum StartMode { START_GIVEN = 0, START_CNN = 1, START_ASG = 2 };
+void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t* start,
+                   const double* origin, const float* disp, int32_t max_iter, int32_t* host, int32_t* iters,
+                   uint8_t* status, hipStream_t stream);
+
+// cnn.hip
+void run_predict(const cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
+                 hipStream_t stream);
+
+}  // namespace cnnsns

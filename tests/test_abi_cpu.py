@@ -1,0 +1,47 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments before touching the GPU (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cnnsns.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cnnsns_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2412_18379_amd import cnnsns
+    if not os.path.exists(cnnsns.LIB_PATH):
+        pytest.skip("libcnnsns.so not built")
+    return cnnsns.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 11
+    from paper_2412_18379_amd import cnnsns
+    assert set(names) == set(cnnsns.EXPORTS)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_argument_errors_without_gpu(L):
+    from paper_2412_18379_amd import cnnsns as C
+    out = ctypes.c_void_p()
+    assert L.cnnsns_build_mesh(None, 3, None, 1, 0, None, ctypes.byref(out)) == C.EINVAL
+    assert b"NULL" in L.cnnsns_last_error()
+    assert L.cnnsns_locate(None, 10, None, None, None, None, 0, None, None, None, None) == C.EINVAL
+    assert L.cnnsns_predict(None, None, None, 0, None, None) == C.EINVAL
+    assert L.cnnsns_mesh_info(None, None, None, None, None) == C.EINVAL
+    assert L.cnnsns_destroy_mesh(None) == C.OK
+    assert L.cnnsns_last_error() == b""
+    assert L.cnnsns_submit(None, None, None, 0, None, None, None, None, None, None) == C.EINVAL
+    assert L.cnnsns_server_destroy(None) == C.OK
