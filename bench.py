@@ -1,0 +1,274 @@
+"""Benchmark: points located per second, CNN-SNS vs plain SNS, on one MI355X.
+
+One step is one pass of the CNN-SNS hot path over the whole workload with all
+inputs resident in device memory: the CNN forward pass over the overlay grid
+(cnnsns_predict) followed by the CNN-SNS walk of every point
+(cnnsns_locate with the displacement grid).  The plain SNS walk from the
+element before movement, and the ASG start (overlay lookup at x_p), are timed
+beside it on the same inputs.
+
+Default workload: the 16M-triangle radially graded mesh with 8M departure
+points at ~150 element diameters and a 4096 x 4096 overlay, FP32 CNN.
+
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c4] [--precision f32|bf16|fp8]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBps": 8000.0, "f32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0, "fp8_TFLOPs": 5000.0}
+CNN_MACS_PER_PIXEL = 2 * 32 * 9 + 32 * 32 * 9 * 2 + 32 * 2 * 9  # 19,584
+REC_BYTES = 60  # algorithmic bytes of one element record: 6 FP64 coordinates + 3 int32 neighbours
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2412_18379_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, workload: str, sha: str):
+    """HBM traffic per launch measured with rocprofv3 counters for this exact kernel source, else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        db = json.load(f)
+    e = db.get(f"{kernel}@{workload}")
+    if not e or e.get("source_sha") != sha:
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def pct(a, q):
+    return float(np.percentile(a, q))
+
+
+def cpu_baseline(w, ws, bs, band_rows: int):
+    """The FP64 oracle on a bounded band of the same workload (host cores)."""
+    import oracle as O
+
+    threads = O.set_threads(0)
+    G = w.G
+    t = time.perf_counter()
+    tc, nbr = O.prepare_mesh(w.xy, w.tri)
+    lk = O.lookup(w.xy, tc, G)
+    setup_s = time.perf_counter() - t
+    r0 = max(0, G // 2 - band_rows // 2)
+    r1 = min(G, r0 + band_rows)
+    cy = np.clip(np.floor(w.origins[:, 1] * G), 0, G - 1).astype(np.int64)
+    sel = np.nonzero((cy >= r0) & (cy < r1))[0]
+    org, xp, st = w.origins[sel], w.xp[sel], w.start[sel]
+    t = time.perf_counter()
+    band = O.cnn_window(w.vel, ws, bs, r0, 0, r1 - r0, G)
+    t_cnn = time.perf_counter() - t
+    disp = np.zeros((2, G, G))
+    disp[:, r0:r1, :] = band
+    t = time.perf_counter()
+    s0 = O.cnnsns_start(org, disp, lk, st)
+    h, it, s = O.sns(w.xy, tc, nbr, xp, s0)
+    t_walk = time.perf_counter() - t
+    t = time.perf_counter()
+    ph, pit, ps = O.sns(w.xy, tc, nbr, xp, st)
+    t_plain = time.perf_counter() - t
+    n = len(sel)
+    return {
+        "value": n / (t_cnn + t_walk), "unit": "points/s", "cores": threads, "kind": "oracle",
+        "sample": (f"overlay rows [{r0},{r1}) of {G}: FP64 CNN on that band ({t_cnn:.2f}s) + CNN-SNS start and walk "
+                   f"of the {n} points whose origin lies in it ({t_walk:.2f}s); mesh prep and lookup untimed "
+                   f"({setup_s:.1f}s)"),
+        "plain_sns_value": n / t_plain, "plain_sns_s": t_plain, "mean_path_cnn_sns": float(it.mean()),
+        "mean_path_plain": float(pit.mean()),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4"])
+    ap.add_argument("--precision", default=None, choices=["f32", "bf16", "fp8"])
+    ap.add_argument("--weights", default="trained", choices=["trained", "he"])
+    ap.add_argument("--cpu-band-rows", type=int, default=0, help="oracle sample band (0: auto)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(points are independent; see the sharding note in the design document).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2412_18379_amd import cnnsns as C
+    from paper_2412_18379_amd import train as T
+    from paper_2412_18379_amd import workload as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    C.lib()
+    precision = args.precision or ("bf16" if args.workload == "c4" else "f32")
+    wl_name = "c2" if args.workload == "c4" else args.workload
+    t0 = time.perf_counter()
+    w = W.build(wl_name)
+    log(f"workload {args.workload}: {w.n_tri} triangles, {w.n_points} points, G={w.G} "
+        f"({time.perf_counter() - t0:.1f}s)")
+    trained = T.load(wl_name) if args.weights == "trained" else None
+    if trained is not None:
+        ws, bs = trained
+        weights_kind = "trained"
+    else:
+        ws, bs = W.he_weights(200)
+        weights_kind = "he-init seed 200"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    mesh = C.Mesh(w.xy, w.tri, overlay_side=w.G)
+    torch.cuda.synchronize()
+    log(f"mesh resident: {mesh.device_bytes / 2**20:.0f} MiB ({time.perf_counter() - t0:.1f}s)")
+    Wt = C.Weights(ws, bs, device=dev)
+    xp = torch.from_numpy(w.xp).to(dev)
+    origin = torch.from_numpy(w.origins).to(dev)
+    start = torch.from_numpy(w.start).to(dev)
+    vel = torch.from_numpy(w.vel).to(dev)
+    n = w.n_points
+    disp = torch.empty((2, w.G, w.G), dtype=torch.float32, device=dev)
+    host = torch.empty(n, dtype=torch.int32, device=dev)
+    iters = torch.empty(n, dtype=torch.int32, device=dev)
+    status = torch.empty(n, dtype=torch.uint8, device=dev)
+
+    def step():
+        C.predict(mesh, vel, Wt, precision, disp=disp)
+        C.locate(mesh, xp, origin=origin, disp=disp, host=host, iters=iters, status=status)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record(stream)
+        C.predict(mesh, vel, Wt, precision, disp=disp)
+        ev[k][1].record(stream)
+        C.locate(mesh, xp, origin=origin, disp=disp, host=host, iters=iters, status=status)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / K
+    pred_ms = np.array([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)])
+    loc_ms = np.array([ev[k][1].elapsed_time(ev[k][2]) for k in range(K)])
+    step_ms = pred_ms + loc_ms
+    it_c = iters.cpu().numpy()
+    st_c = status.cpu().numpy()
+    host_c = host.cpu().numpy()
+    log(f"CNN-SNS: {ms_step:.3f} ms/step (predict {pred_ms.mean():.3f} ms, locate {loc_ms.mean():.3f} ms), "
+        f"mean I_t {it_c.mean():.2f}")
+
+    # plain SNS and ASG-at-x_p legs on the same inputs
+    def timed_locate(**kw):
+        for _ in range(args.warmup):
+            C.locate(mesh, xp, host=host, iters=iters, status=status, **kw)
+        torch.cuda.synchronize()
+        e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        for k in range(K):
+            e[k][0].record(stream)
+            C.locate(mesh, xp, host=host, iters=iters, status=status, **kw)
+            e[k][1].record(stream)
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) for a, b in e]), iters.cpu().numpy(), host.cpu().numpy()
+
+    plain_ms, it_p, host_p = timed_locate(start=start)
+    log(f"plain SNS: {plain_ms.mean():.3f} ms, mean I_t {it_p.mean():.2f}")
+    asg_ms, it_a, host_a = timed_locate()
+    log(f"ASG start: {asg_ms.mean():.3f} ms, mean I_t {it_a.mean():.2f}")
+    same_host = float(np.mean(host_c == host_p))
+
+    value = n / (ms_step / 1e3)
+    G = w.G
+    cnn_flops = 2.0 * CNN_MACS_PER_PIXEL * G * G
+    cnn_peak = PEAK[{"f32": "f32_TFLOPs", "bf16": "bf16_TFLOPs", "fp8": "fp8_TFLOPs"}[precision]]
+    cnn_tf = cnn_flops / (pred_ms.mean() / 1e3) / 1e12
+    # walk algorithmic bytes: one element record per iteration plus per-point inputs and outputs
+    out_b = 4 + 4 + 1
+    bytes_cnn_walk = REC_BYTES * float(it_c.sum()) + n * (16 + 16 + 8 + 4 + out_b)
+    bytes_plain = REC_BYTES * float(it_p.sum()) + n * (16 + 4 + out_b)
+    gbps_cnn_walk = bytes_cnn_walk / (loc_ms.mean() / 1e3) / 1e9
+    gbps_plain = bytes_plain / (plain_ms.mean() / 1e3) / 1e9
+    cnn_sha = source_sha("cnn.hip")
+    walk_sha = source_sha("sns_walk.hip")
+    roofline = {
+        "kernel": "cnn forward (conv12 + conv34 kernels, one cnnsns_predict)",
+        "bound": "mfma", "achieved": round(cnn_tf, 3), "peak": cnn_peak, "unit": "TFLOP/s",
+        "frac": round(cnn_tf / cnn_peak, 4),
+        "traffic": traffic_for("cnn_forward", args.workload, cnn_sha),
+        "algorithmic_per_launch": f"{cnn_flops:.4e} FLOP (2 x 19584 MAC x G^2, G={G})",
+    }
+    roofline_sns = {
+        "kernel": "k_locate (plain SNS leg)", "bound": "hbm", "achieved": round(gbps_plain, 1),
+        "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": round(gbps_plain / PEAK["hbm_GBps"], 4),
+        "traffic": traffic_for("k_locate_plain", args.workload, walk_sha),
+        "algorithmic_per_launch": f"{bytes_plain:.4e} B (60 B x sum I_t + 29 B x n)",
+        "cnn_sns_leg": {"achieved": round(gbps_cnn_walk, 1), "frac": round(gbps_cnn_walk / PEAK["hbm_GBps"], 4),
+                        "algorithmic_per_launch": f"{bytes_cnn_walk:.4e} B (60 B x sum I_t + 69 B x n)"},
+    }
+    res = {
+        "metric": "points located/s CNN-SNS vs SNS (1 GPU); mean SNS path length; p99 latency",
+        "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32 CNN / f64 SNS", "bf16": "bf16 CNN / f64 SNS", "fp8": "fp8 CNN / f64 SNS"}[precision],
+        "data": "synthetic",
+        "config": {"workload": {"c2": "1M-triangle jittered Delaunay, 1M centroid points, ~20 diameters, G=1024",
+                                "c3": "16M-triangle graded jittered Delaunay, 8M node points, ~150 diameters, G=4096",
+                                "c4": "1M-triangle jittered Delaunay, 1M centroid points, ~20 diameters, G=1024, "
+                                      "BF16 CNN"}[args.workload],
+                   "n_triangles": w.n_tri, "n_points": n, "overlay": G, "cnn_precision": precision,
+                   "weights": weights_kind, "seeds": w.seeds, "mean_displacement_diameters":
+                       round(float(np.mean(np.hypot(*(w.xp - w.origins).T)) / w.dbar), 2)},
+        "plain_sns_points_per_s": round(n / (plain_ms.mean() / 1e3), 1),
+        "asg_start_points_per_s": round(n / (asg_ms.mean() / 1e3), 1),
+        "speedup_vs_plain_sns": round(float(plain_ms.mean() / step_ms.mean()), 3),
+        "mean_path_length": {"cnn_sns": round(float(it_c.mean()), 3), "plain_sns": round(float(it_p.mean()), 3),
+                             "asg_start": round(float(it_a.mean()), 3)},
+        "path_length_p50_p99_max": {"cnn_sns": [pct(it_c, 50), pct(it_c, 99), int(it_c.max())],
+                                    "plain_sns": [pct(it_p, 50), pct(it_p, 99), int(it_p.max())]},
+        "opt_path_length": round(1.0 - float(it_c.mean()) / float(it_p.mean()), 4),
+        "step_latency_ms": {"p50": round(pct(step_ms, 50), 4), "p99": round(pct(step_ms, 99), 4)},
+        "predict_ms": round(float(pred_ms.mean()), 4), "locate_ms": round(float(loc_ms.mean()), 4),
+        "plain_locate_ms": round(float(plain_ms.mean()), 4),
+        "host_agreement_cnn_vs_plain": same_host,
+        "status_found_frac": float(np.mean(st_c == C.FOUND)),
+        "roofline": roofline, "roofline_sns": roofline_sns,
+    }
+    if not args.no_cpu_baseline:
+        band = args.cpu_band_rows or {"c2": 256, "c3": 256, "c4": 256}[args.workload]
+        t0 = time.perf_counter()
+        cb = cpu_baseline(w, ws, bs, band)
+        log(f"cpu baseline: {cb['value']:.0f} points/s on {cb['cores']} threads ({time.perf_counter() - t0:.1f}s)")
+        res["cpu_baseline"] = cb
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

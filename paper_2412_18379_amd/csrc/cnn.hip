@@ -1,10 +1,443 @@
+// Displacement CNN over the G x G overlay grid: four 3x3 convolution layers
+// 2 -> 32 -> 32 -> 32 -> 2 with zero "same" padding, bias, and ReLU between
+// layers (the CNN of Sec. 2.3, here a per-cell displacement regressor fed
+// with the overlay velocity).  Cross-correlation with OIHW weights:
+//   y[o][r][c] = b[o] + sum_i sum_{dy,dx} w[o][i][dy+1][dx+1] x[i][r+dy][c+dx].
+//
+// Two fused FP32 kernels per forward pass, both persistent (one block of 4
+// wavefronts per compute unit, one wavefront per SIMD so each may hold 512
+// registers) looping over tiles:
+//   conv12: conv1 (K = 18 padded to 20) on the matrix cores into LDS on the
+//           16 x 32 tile plus a one-pixel border, then conv2 as an implicit
+//           GEMM (pixels x 32 output channels, K = 9 taps x 32 channels);
+//           writes the 32-channel activation, pixel-major ([G][G][32]).
+//   conv34: conv3 as an implicit GEMM on a 16 x 32 region (the 14 x 30 output
+//           tile plus a one-pixel border), kept in LDS, then conv4 (N = 2) on
+//           the vector ALU; writes the 2-channel displacement.
+// LDS tiles are pixel-major with a 36-float pixel stride: a lane fetches 4
+// channels of one pixel with one conflict-free 16-byte read, which feeds 4
+// matrix instructions.  The next tile's input is fetched into registers while
+// the current tile computes.
 #include "common.h"
 
 namespace cnnsns {
+namespace {
 
-void run_predict(const cnnsns_mesh_s&, const float*, const cnnsns_cnn&, int32_t, float*, hipStream_t)
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;  // 4 wavefronts
+constexpr int kWaves = kThreads / 64;
+constexpr int RH = 16, RW = 32;          // MFMA region per block
+constexpr int IH = RH + 2, IW = RW + 2;  // its input tile (one-pixel border)
+constexpr int NIN = IH * IW;             // 612 input pixels
+constexpr int NREG = RH * RW;            // 512 region pixels
+constexpr int C = 32;                    // hidden channels
+constexpr int PS = 36;                   // LDS floats per pixel (32 channels + 4 pad)
+constexpr int OH34 = RH - 2, OW34 = RW - 2;  // conv34 output tile (region minus its border)
+constexpr int WSW = 9 * 2 * 2 * 64 * 4;  // swizzled 32->32 weights (floats)
+constexpr int MB = 8;                    // M-blocks (16 pixels) per wavefront: 4 region rows
+constexpr int VH = IH + 2, VW = IW + 2;  // velocity tile (two-pixel border) 20 x 36
+constexpr int VEL_PER_THREAD = (2 * VH * VW + kThreads - 1) / kThreads;
+constexpr int CHUNKS = NIN * C / 4;      // float4 chunks of an input tile
+constexpr int CHUNKS_PER_THREAD = (CHUNKS + kThreads - 1) / kThreads;
+constexpr int L1_MBLOCKS = (NIN + 15) / 16;
+
+static_assert(WSW == C * C * 9, "swizzle covers the whole layer");
+static_assert(NREG * PS <= NIN * PS, "output tile aliases the input tile");
+static_assert(kWaves * 4 == RH, "each wavefront takes four region rows");
+
+// Matrix-core operand order for a 32->32 layer (v_mfma_f32_16x16x4f32).  For
+// tap t, N-block nb and k-step s (0..7), lane l holds B = W[16 nb + l%16]
+// [8 (l/16) + s][t]; the A operand of lane l is input channel 8 (l/16) + s of
+// its pixel, so one 32-byte run of a pixel's channels serves 8 k-steps.
+// wsw[(((t * 2 + nb) * 2 + h) * 64 + l) * 4 + j] holds k-step s = 4h + j, so a
+// lane reads its B operands as float4s.
+__global__ void k_swizzle32(const float* __restrict__ w, float* __restrict__ wsw)
 {
-    fail(CNNSNS_EINVAL, "predict: CNN kernels not available in this build");
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= WSW) return;
+    int j = k & 3, l = (k >> 2) & 63, h = (k >> 8) & 1, nb = (k >> 9) & 1, t = k >> 10;
+    int o = nb * 16 + (l & 15), ci = 8 * (l >> 4) + 4 * h + j;
+    wsw[k] = w[(o * C + ci) * 9 + t];
+}
+
+__device__ __forceinline__ void load_tap(const float* __restrict__ s_in, const float* __restrict__ s_w, int wave,
+                                         int lane, int t, v4f (&a)[MB][2], v4f (&b)[2][2])
+{
+    const int i = lane & 15, q = lane >> 4;
+    const int ty = t / 3, tx = t % 3;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        const int P = (4 * wave + (mb >> 1) + ty) * IW + (mb & 1) * 16 + i + tx;
+        const v4f* src = reinterpret_cast<const v4f*>(s_in + P * PS + 8 * q);
+        a[mb][0] = src[0];
+        a[mb][1] = src[1];
+    }
+    const v4f* ws = reinterpret_cast<const v4f*>(s_w);
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) b[nb][h] = ws[((t * 2 + nb) * 2 + h) * 64 + lane];
+}
+
+// conv 32 -> 32 over the block's 16 x 32 region on the matrix cores.  s_in
+// holds the 32-channel input on the 18 x 34 tile around the region.  Wave w
+// covers region rows 4w .. 4w+3; M-block mb is row 4w + mb/2, columns
+// 16 (mb%2) .. +15.  Result acc[mb][nb][r]: region pixel
+// (4w + mb/2, 16 (mb%2) + 4 (l/16) + r), output channel 16 nb + l%16.
+// The operands of tap t+1 are read while the 128 instructions of tap t issue.
+__device__ __forceinline__ void conv32_mfma(const float* __restrict__ s_in, const float* __restrict__ s_w, int wave,
+                                            int lane, v4f (&acc)[MB][2])
+{
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        acc[mb][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
+        acc[mb][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
+    }
+    v4f a[2][MB][2], b[2][2][2];
+    load_tap(s_in, s_w, wave, lane, 0, a[0], b[0]);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < 9) load_tap(s_in, s_w, wave, lane, t + 1, a[cur ^ 1], b[cur ^ 1]);
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[cur][mb][s >> 2][s & 3],
+                                                                      b[cur][nb][s >> 2][s & 3], acc[mb][nb], 0, 0, 0);
+        if (t + 1 < 9) {
+            // spread the 20 reads of the next tap over this tap's 128 matrix instructions
+#pragma unroll
+            for (int k = 0; k < 20; ++k) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);  // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+        }
+    }
+}
+
+// Block loads of the swizzled 32->32 weights into LDS.
+__device__ __forceinline__ void load_wsw(const float* __restrict__ wsw, float* __restrict__ s_w)
+{
+    const v4f* src = reinterpret_cast<const v4f*>(wsw);
+    v4f* dst = reinterpret_cast<v4f*>(s_w);
+    for (int k = threadIdx.x; k < WSW / 4; k += kThreads) dst[k] = src[k];
+}
+
+// Persistent tile loop.  Tiles (row-major) are split into 8 contiguous
+// ranges, one per XCD: workgroups are dispatched to the 8 XCDs round-robin
+// by id, so the blocks of one XCD walk one range together and neighbouring
+// tiles, whose halos overlap, are read through the same L2.
+struct TileIter {
+    int t, step, end;
+    __device__ explicit TileIter(int ntiles)
+    {
+        const int nx = 8;
+        const int xcd = blockIdx.x % nx, slot = blockIdx.x / nx, per = gridDim.x / nx;
+        t = (int)((int64_t)ntiles * xcd / nx) + slot;
+        end = (int)((int64_t)ntiles * (xcd + 1) / nx);
+        step = per;
+    }
+};
+
+// conv1 + ReLU (matrix cores, into LDS) then conv2 + ReLU -> act2 [G][G][32].
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_conv12_f32(
+    int32_t G, int tiles_x, int ntiles, const float* __restrict__ vel, const float* __restrict__ w1,
+    const float* __restrict__ b1, const float* __restrict__ wsw2, const float* __restrict__ b2,
+    float* __restrict__ act2)
+{
+    __shared__ __attribute__((aligned(16))) float s_in[NIN * PS];
+    __shared__ __attribute__((aligned(16))) float s_w[WSW];
+    __shared__ float s_vel[2 * VH * VW];
+    __shared__ float s_b2[C];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, q = lane >> 4;
+    const int64_t GG = (int64_t)G * G;
+
+    TileIter it(ntiles);
+    if (it.t >= it.end) return;
+
+    load_wsw(wsw2, s_w);
+    if (tid < C) s_b2[tid] = b2[tid];
+    // conv1 B operands: k-step s, slot q holds k = 4s + q = 9 ci + tap (zero for k >= 18)
+    float bw1[5][2], bias1[2];
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            const int k = 4 * s + q, o = nb * 16 + i;
+            bw1[s][nb] = k < 18 ? w1[(o * 2 + k / 9) * 9 + k % 9] : 0.f;
+        }
+    bias1[0] = b1[i];
+    bias1[1] = b1[16 + i];
+
+    float pv[VEL_PER_THREAD];
+    auto fetch_vel = [&](int t) {
+        const int y0 = (t / tiles_x) * RH, x0 = (t % tiles_x) * RW;
+#pragma unroll
+        for (int k = 0; k < VEL_PER_THREAD; ++k) {
+            const int e = tid + k * kThreads;
+            float v = 0.f;
+            if (e < 2 * VH * VW) {
+                const int c = e / (VH * VW), rem = e % (VH * VW);
+                const int gy = y0 - 2 + rem / VW, gx = x0 - 2 + rem % VW;
+                if (gy >= 0 && gy < G && gx >= 0 && gx < G) v = vel[c * GG + (int64_t)gy * G + gx];
+            }
+            pv[k] = v;
+        }
+    };
+    auto stash_vel = [&]() {
+#pragma unroll
+        for (int k = 0; k < VEL_PER_THREAD; ++k) {
+            const int e = tid + k * kThreads;
+            if (e < 2 * VH * VW) s_vel[e] = pv[k];
+        }
+    };
+    fetch_vel(it.t);
+    stash_vel();
+    __syncthreads();
+
+    for (; it.t < it.end; it.t += it.step) {
+        const int y0 = (it.t / tiles_x) * RH, x0 = (it.t % tiles_x) * RW;
+
+        // conv1 on the 18 x 34 input tile of conv2; zero outside the grid (conv2's padding)
+        for (int mb = wave; mb < L1_MBLOCKS; mb += kWaves) {
+            const int p = min(mb * 16 + i, NIN - 1);
+            const int py = p / IW, px = p % IW;
+            v4f d0 = v4f{ 0.f, 0.f, 0.f, 0.f }, d1 = d0;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                const int k = 4 * s + q;
+                const int ci = k / 9, t = k % 9;
+                const float a = k < 18 ? s_vel[ci * VH * VW + (py + t / 3) * VW + px + t % 3] : 0.f;
+                d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw1[s][0], d0, 0, 0, 0);
+                d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw1[s][1], d1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pp = mb * 16 + 4 * q + r;
+                if (pp < NIN) {
+                    const int gy = y0 - 1 + pp / IW, gx = x0 - 1 + pp % IW;
+                    const bool in = gy >= 0 && gy < G && gx >= 0 && gx < G;
+                    s_in[pp * PS + i] = in ? fmaxf(d0[r] + bias1[0], 0.f) : 0.f;
+                    s_in[pp * PS + 16 + i] = in ? fmaxf(d1[r] + bias1[1], 0.f) : 0.f;
+                }
+            }
+        }
+        __syncthreads();
+
+        const int next = it.t + it.step;
+        if (next < it.end) fetch_vel(next);  // lands while conv2 runs
+
+        v4f acc[MB][2];
+        conv32_mfma(s_in, s_w, wave, lane, acc);
+        __syncthreads();  // s_in is reused for the output tile; s_vel is free
+
+        if (next < it.end) stash_vel();
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int o = nb * 16 + i;
+                    const int p = (4 * wave + (mb >> 1)) * RW + (mb & 1) * 16 + 4 * q + r;
+                    s_in[p * PS + o] = fmaxf(acc[mb][nb][r] + s_b2[o], 0.f);
+                }
+        __syncthreads();
+        for (int e = tid; e < NREG * (C / 4); e += kThreads) {
+            const int p = e >> 3, part = e & 7;
+            const int gy = y0 + p / RW, gx = x0 + p % RW;
+            if (gy < G && gx < G)
+                *reinterpret_cast<v4f*>(act2 + ((int64_t)gy * G + gx) * C + part * 4) =
+                    *reinterpret_cast<const v4f*>(s_in + p * PS + part * 4);
+        }
+        __syncthreads();
+    }
+}
+
+// conv3 + ReLU on the tile plus a one-pixel border (in LDS), then conv4 -> disp [2][G][G].
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_conv34_f32(
+    int32_t G, int tiles_x, int ntiles, const float* __restrict__ act2, const float* __restrict__ wsw3,
+    const float* __restrict__ b3, const float* __restrict__ w4, const float* __restrict__ b4,
+    float* __restrict__ disp)
+{
+    __shared__ __attribute__((aligned(16))) float s_in[NIN * PS];
+    __shared__ __attribute__((aligned(16))) float s_w[WSW];
+    __shared__ __attribute__((aligned(16))) float s_w4[9 * 2 * C];  // [tap][out][in]
+    __shared__ float s_b3[C], s_b4[2];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, q = lane >> 4;
+    const int64_t GG = (int64_t)G * G;
+
+    TileIter it(ntiles);
+    if (it.t >= it.end) return;
+
+    load_wsw(wsw3, s_w);
+    for (int k = tid; k < 9 * 2 * C; k += kThreads) {
+        const int t = k / (2 * C), o = (k / C) % 2, c = k % C;
+        s_w4[k] = w4[(o * C + c) * 9 + t];
+    }
+    if (tid < C) s_b3[tid] = b3[tid];
+    if (tid < 2) s_b4[tid] = b4[tid];
+
+    // next tile's input, as float4 chunks (8 per pixel) of the 18 x 34 tile
+    v4f pa[CHUNKS_PER_THREAD];
+    auto fetch_act = [&](int t) {
+        const int y0 = (t / tiles_x) * OH34 - 1, x0 = (t % tiles_x) * OW34 - 1;  // conv3 region origin
+#pragma unroll
+        for (int k = 0; k < CHUNKS_PER_THREAD; ++k) {
+            const int e = tid + k * kThreads;
+            const int p = e >> 3, part = e & 7;
+            const int gy = y0 - 1 + p / IW, gx = x0 - 1 + p % IW;
+            v4f v = v4f{ 0.f, 0.f, 0.f, 0.f };
+            if (e < CHUNKS && gy >= 0 && gy < G && gx >= 0 && gx < G)
+                v = *reinterpret_cast<const v4f*>(act2 + ((int64_t)gy * G + gx) * C + part * 4);
+            pa[k] = v;
+        }
+    };
+    auto stash_act = [&]() {
+#pragma unroll
+        for (int k = 0; k < CHUNKS_PER_THREAD; ++k) {
+            const int e = tid + k * kThreads;
+            if (e < CHUNKS) *reinterpret_cast<v4f*>(s_in + (e >> 3) * PS + (e & 7) * 4) = pa[k];
+        }
+    };
+    fetch_act(it.t);
+    stash_act();
+    __syncthreads();
+
+    for (; it.t < it.end; it.t += it.step) {
+        const int ty0 = (it.t / tiles_x) * OH34, tx0 = (it.t % tiles_x) * OW34;  // output tile origin
+        const int y0 = ty0 - 1, x0 = tx0 - 1;                                      // conv3 region origin
+
+        const int next = it.t + it.step;
+        if (next < it.end) fetch_act(next);  // lands while conv3 and conv4 run
+
+        v4f acc[MB][2];
+        conv32_mfma(s_in, s_w, wave, lane, acc);
+        __syncthreads();
+
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int o = nb * 16 + i;
+                    const int row = 4 * wave + (mb >> 1), col = (mb & 1) * 16 + 4 * q + r;
+                    const int gy = y0 + row, gx = x0 + col;
+                    const bool in = gy >= 0 && gy < G && gx >= 0 && gx < G;  // conv4's zero padding
+                    s_in[(row * RW + col) * PS + o] = in ? fmaxf(acc[mb][nb][r] + s_b3[o], 0.f) : 0.f;
+                }
+        __syncthreads();
+
+        {
+            // conv4: thread tid takes output pixels tid and tid + kThreads of the 14 x 30 tile;
+            // each weight read from LDS serves both
+            static_assert(OH34 * OW34 <= 2 * kThreads, "two conv4 pixels per thread");
+            const int e0 = tid, e1 = min(tid + kThreads, OH34 * OW34 - 1);
+            const int oy0 = e0 / OW34, ox0 = e0 % OW34, oy1 = e1 / OW34, ox1 = e1 % OW34;
+            float d00 = s_b4[0], d01 = s_b4[1], d10 = s_b4[0], d11 = s_b4[1];
+#pragma unroll 1
+            for (int t = 0; t < 9; ++t) {
+                const v4f* p0 = reinterpret_cast<const v4f*>(s_in + ((oy0 + t / 3) * RW + ox0 + t % 3) * PS);
+                const v4f* p1 = reinterpret_cast<const v4f*>(s_in + ((oy1 + t / 3) * RW + ox1 + t % 3) * PS);
+                const v4f* wt = reinterpret_cast<const v4f*>(s_w4 + t * 2 * C);  // wave-uniform: broadcast
+#pragma unroll
+                for (int part = 0; part < C / 4; ++part) {
+                    const v4f x0 = p0[part], x1 = p1[part], u0 = wt[part], u1 = wt[C / 4 + part];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        d00 += u0[j] * x0[j];
+                        d01 += u1[j] * x0[j];
+                        d10 += u0[j] * x1[j];
+                        d11 += u1[j] * x1[j];
+                    }
+                }
+            }
+            const int gy0 = ty0 + oy0, gx0 = tx0 + ox0, gy1 = ty0 + oy1, gx1 = tx0 + ox1;
+            if (gy0 < G && gx0 < G) {
+                disp[(int64_t)gy0 * G + gx0] = d00;
+                disp[GG + (int64_t)gy0 * G + gx0] = d01;
+            }
+            if (tid + kThreads < OH34 * OW34 && gy1 < G && gx1 < G) {
+                disp[(int64_t)gy1 * G + gx1] = d10;
+                disp[GG + (int64_t)gy1 * G + gx1] = d11;
+            }
+        }
+        __syncthreads();
+        if (next < it.end) stash_act();
+        __syncthreads();
+    }
+}
+
+inline unsigned cdiv(int64_t a, int64_t b)
+{
+    return (unsigned)((a + b - 1) / b);
+}
+
+// One block per compute unit (the LDS footprint allows one), a multiple of the 8 XCDs.
+unsigned persistent_grid(int ntiles)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    }
+    int g = cus < ntiles ? cus : ntiles;
+    g = (g + 7) / 8 * 8;
+    return (unsigned)(g < 8 ? 8 : g);
+}
+
+}  // namespace
+
+size_t cnn_workspace_bytes(int32_t G, int32_t precision)
+{
+    (void)precision;
+    return sizeof(float) * (2 * (size_t)WSW + (size_t)C * (size_t)G * (size_t)G);
+}
+
+void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp, void* ws,
+             hipStream_t stream)
+{
+    if (precision != CNNSNS_F32) fail(CNNSNS_EINVAL, "predict: only FP32 is available in this build");
+    float* wsw2 = static_cast<float*>(ws);
+    float* wsw3 = wsw2 + WSW;
+    float* act2 = wsw3 + WSW;
+    k_swizzle32<<<cdiv(WSW, 256), 256, 0, stream>>>(w.w[1], wsw2);
+    k_swizzle32<<<cdiv(WSW, 256), 256, 0, stream>>>(w.w[2], wsw3);
+    const int tx12 = (int)cdiv(G, RW), n12 = tx12 * (int)cdiv(G, RH);
+    const int tx34 = (int)cdiv(G, OW34), n34 = tx34 * (int)cdiv(G, OH34);
+    k_conv12_f32<<<persistent_grid(n12), kThreads, 0, stream>>>(G, tx12, n12, vel, w.w[0], w.b[0], wsw2, w.b[1], act2);
+    k_conv34_f32<<<persistent_grid(n34), kThreads, 0, stream>>>(G, tx34, n34, act2, wsw3, w.b[2], w.w[3], w.b[3],
+                                                               disp);
+    hip_check(hipGetLastError(), "predict launch");
+}
+
+void run_predict(cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
+                 hipStream_t stream)
+{
+    const size_t need = cnn_workspace_bytes(m.G, precision);
+    {
+        std::lock_guard<std::mutex> lock(m.ws_mutex);
+        if (m.cnn_ws_bytes < need) {
+            if (m.cnn_ws) {
+                hip_check(hipDeviceSynchronize(), "predict workspace");
+                hip_check(hipFree(m.cnn_ws), "predict workspace free");
+                m.cnn_ws = nullptr;
+                m.cnn_ws_bytes = 0;
+            }
+            hip_check(hipMalloc(&m.cnn_ws, need), "predict workspace allocation");
+            m.cnn_ws_bytes = need;
+        }
+    }
+    run_cnn(m.G, vel, w, precision, disp, m.cnn_ws, stream);
 }
 
 }  // namespace cnnsns

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "../../include/cnnsns.h"
@@ -41,6 +42,10 @@ struct cnnsns_mesh_s {
     cnnsns::ElemRec* rec = nullptr;  // device [n_tri]
     int32_t* lookup = nullptr;       // device [G][G]
     int64_t device_bytes = 0;
+    // CNN workspace, allocated on the first cnnsns_predict of this mesh
+    std::mutex ws_mutex;
+    void* cnn_ws = nullptr;
+    size_t cnn_ws_bytes = 0;
 };
 
 namespace cnnsns {
@@ -57,7 +62,10 @@ void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const in
                    uint8_t* status, hipStream_t stream);
 
 // cnn.hip
-void run_predict(const cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
+size_t cnn_workspace_bytes(int32_t G, int32_t precision);
+void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp, void* ws,
+             hipStream_t stream);
+void run_predict(cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
                  hipStream_t stream);
 
 }  // namespace cnnsns

@@ -116,34 +116,76 @@ __global__ void k_lookup_finish(int64_t n, int32_t* p)
     if (k < n && p[k] == INT_MAX) p[k] = -1;
 }
 
-// Rasterise one triangle over the cell centres inside its bounding box
-// (grown by one cell; the containment test decides), keeping the smallest
-// containing id per cell.  Containment is the closed barycentric test with
-// the same numerators the walk uses.
-__global__ void k_lookup_raster(int64_t n_tri, const ElemRec* __restrict__ rec, int32_t G, int32_t* lookup)
+// Overlay cells tested for one triangle: the cell centres inside its bounding
+// box, grown by one cell (a conservative superset; the containment test
+// decides).  Returns false when the box misses the grid.
+struct CellBox {
+    int32_t cx0, cy0, cx1, cy1;
+};
+__device__ __forceinline__ CellBox cell_box(const ElemRec& r, int32_t G)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tri) return;
-    const ElemRec r = rec[t];
     const double g = (double)G;
     double xmin = fmin(r.ax, fmin(r.bx, r.cx)), xmax = fmax(r.ax, fmax(r.bx, r.cx));
     double ymin = fmin(r.ay, fmin(r.by, r.cy)), ymax = fmax(r.ay, fmax(r.by, r.cy));
     double fx0 = floor(xmin * g - 0.5) - 1.0, fx1 = ceil(xmax * g - 0.5) + 1.0;
     double fy0 = floor(ymin * g - 0.5) - 1.0, fy1 = ceil(ymax * g - 0.5) + 1.0;
-    int32_t cx0 = fx0 < 0.0 ? 0 : (fx0 > g - 1.0 ? G : (int32_t)fx0);
-    int32_t cy0 = fy0 < 0.0 ? 0 : (fy0 > g - 1.0 ? G : (int32_t)fy0);
-    int32_t cx1 = fx1 > g - 1.0 ? G - 1 : (fx1 < 0.0 ? -1 : (int32_t)fx1);
-    int32_t cy1 = fy1 > g - 1.0 ? G - 1 : (fy1 < 0.0 ? -1 : (int32_t)fy1);
-    for (int32_t cy = cy0; cy <= cy1; ++cy) {
-        const double py = ((double)cy + 0.5) / g;
-        const double ady = r.ay - py, bdy = r.by - py, cdy = r.cy - py;
-        for (int32_t cx = cx0; cx <= cx1; ++cx) {
-            const double px = ((double)cx + 0.5) / g;
-            const double adx = r.ax - px, bdx = r.bx - px, cdx = r.cx - px;
-            const double s0 = bdx * cdy - bdy * cdx;
-            const double s1 = cdx * ady - cdy * adx;
-            const double s2 = adx * bdy - ady * bdx;
-            if (s0 >= 0.0 && s1 >= 0.0 && s2 >= 0.0) atomicMin(&lookup[(int64_t)cy * G + cx], (int32_t)t);
+    CellBox b;
+    b.cx0 = fx0 < 0.0 ? 0 : (fx0 > g - 1.0 ? G : (int32_t)fx0);
+    b.cy0 = fy0 < 0.0 ? 0 : (fy0 > g - 1.0 ? G : (int32_t)fy0);
+    b.cx1 = fx1 > g - 1.0 ? G - 1 : (fx1 < 0.0 ? -1 : (int32_t)fx1);
+    b.cy1 = fy1 > g - 1.0 ? G - 1 : (fy1 < 0.0 ? -1 : (int32_t)fy1);
+    return b;
+}
+
+// Closed containment of the centre of cell (cx, cy), with the same
+// barycentric numerators the walk uses.
+__device__ __forceinline__ bool holds_centre(const ElemRec& r, int32_t cx, int32_t cy, int32_t G)
+{
+    const double g = (double)G;
+    const double px = ((double)cx + 0.5) / g, py = ((double)cy + 0.5) / g;
+    const double adx = r.ax - px, bdx = r.bx - px, cdx = r.cx - px;
+    const double ady = r.ay - py, bdy = r.by - py, cdy = r.cy - py;
+    const double s0 = bdx * cdy - bdy * cdx;
+    const double s1 = cdx * ady - cdy * adx;
+    const double s2 = adx * bdy - ady * bdx;
+    return s0 >= 0.0 && s1 >= 0.0 && s2 >= 0.0;
+}
+
+constexpr int64_t kBigBox = 256;  // cells; larger boxes go to the block-parallel pass
+
+// Rasterise one triangle per thread over its cell box, keeping the smallest
+// containing id per cell.  Triangles with large boxes (a coarse mesh under a
+// fine overlay) are listed for k_lookup_raster_big instead.
+__global__ void k_lookup_raster(int64_t n_tri, const ElemRec* __restrict__ rec, int32_t G, int32_t* lookup,
+                                int32_t* big, unsigned* n_big)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tri) return;
+    const ElemRec r = rec[t];
+    const CellBox b = cell_box(r, G);
+    if (b.cx1 < b.cx0 || b.cy1 < b.cy0) return;
+    if ((int64_t)(b.cx1 - b.cx0 + 1) * (b.cy1 - b.cy0 + 1) > kBigBox) {
+        big[atomicAdd(n_big, 1u)] = (int32_t)t;
+        return;
+    }
+    for (int32_t cy = b.cy0; cy <= b.cy1; ++cy)
+        for (int32_t cx = b.cx0; cx <= b.cx1; ++cx)
+            if (holds_centre(r, cx, cy, G)) atomicMin(&lookup[(int64_t)cy * G + cx], (int32_t)t);
+}
+
+// Listed triangles: blockIdx.y picks the triangle, all blocks along x and
+// their threads stride over its cells.
+__global__ void k_lookup_raster_big(const ElemRec* __restrict__ rec, const int32_t* __restrict__ big, unsigned n_big,
+                                    int32_t G, int32_t* lookup)
+{
+    for (unsigned k = blockIdx.y; k < n_big; k += gridDim.y) {
+        const int32_t t = big[k];
+        const ElemRec r = rec[t];
+        const CellBox b = cell_box(r, G);
+        const int64_t w = b.cx1 - b.cx0 + 1, n = w * (b.cy1 - b.cy0 + 1);
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+            const int32_t cy = b.cy0 + (int32_t)(c / w), cx = b.cx0 + (int32_t)(c % w);
+            if (holds_centre(r, cx, cy, G)) atomicMin(&lookup[(int64_t)cy * G + cx], t);
         }
     }
 }
@@ -235,7 +277,17 @@ cnnsns_mesh build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, in
         k_pack<<<grid_for(n_tri), kBlock, 0, stream>>>(n_tri, d_xy.p, d_tri.p, d_nbr.p, d_rec.p);
         const int64_t ncell = (int64_t)G * G;
         k_fill_i32<<<grid_for(ncell), kBlock, 0, stream>>>(ncell, d_lookup.p, INT_MAX);
-        k_lookup_raster<<<grid_for(n_tri), kBlock, 0, stream>>>(n_tri, d_rec.p, G, d_lookup.p);
+        DevBuf<int32_t> d_big((size_t)n_tri);
+        DevBuf<unsigned> d_nbig(1);
+        hip_check(hipMemsetAsync(d_nbig.p, 0, sizeof(unsigned), stream), "memset");
+        k_lookup_raster<<<grid_for(n_tri), kBlock, 0, stream>>>(n_tri, d_rec.p, G, d_lookup.p, d_big.p, d_nbig.p);
+        unsigned n_big = 0;
+        hip_check(hipMemcpyAsync(&n_big, d_nbig.p, sizeof(unsigned), hipMemcpyDeviceToHost, stream), "copy n_big");
+        hip_check(hipStreamSynchronize(stream), "lookup raster");
+        if (n_big > 0) {
+            const dim3 grid(64, n_big < 4096u ? n_big : 4096u);
+            k_lookup_raster_big<<<grid, kBlock, 0, stream>>>(d_rec.p, d_big.p, n_big, G, d_lookup.p);
+        }
         k_lookup_finish<<<grid_for(ncell), kBlock, 0, stream>>>(ncell, d_lookup.p);
         hip_check(hipGetLastError(), "mesh build kernels");
         int err = 0;
@@ -268,6 +320,7 @@ void destroy_mesh(cnnsns_mesh m)
     (void)hipDeviceSynchronize();
     (void)hipFree(m->rec);
     (void)hipFree(m->lookup);
+    if (m->cnn_ws) (void)hipFree(m->cnn_ws);
     (void)hipSetDevice(cur);
     delete m;
 }

@@ -1,0 +1,129 @@
+"""GPU parity of cnnsns_predict (the displacement CNN) against the FP64 oracle,
+and end-to-end CNN-SNS (Alg. 2) through the C ABI.
+
+FP32 bar, per output channel c:  |y - y_ref| <= 1e-5 |y_ref| + 1e-5 max_c |y_ref|
+(a relative error of 1e-5 with an absolute floor at 1e-5 of the channel's
+largest magnitude, since a pure elementwise relative error is undefined where
+an output crosses zero).
+"""
+import numpy as np
+import pytest
+import torch
+
+from exact import edge_distances
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def C():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_18379_amd import cnnsns
+    cnnsns.lib()
+    return cnnsns
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _within(got, ref, rel=REL, scale=None):
+    """Channel-wise tolerance check; returns the worst ratio error/tolerance."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if scale is None:
+        scale = np.abs(ref).reshape(ref.shape[0], -1).max(axis=1)
+    shape = (ref.shape[0],) + (1,) * (ref.ndim - 1)
+    tol = rel * np.abs(ref) + rel * scale.reshape(shape) + 1e-30
+    return float((np.abs(got - ref) / tol).max())
+
+
+def _square_mesh(C, G):
+    """A two-triangle mesh of the unit square with an overlay of side G."""
+    xy = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], dtype=np.float64)
+    tri = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    return C.Mesh(xy, tri, overlay_side=G)
+
+
+@pytest.mark.parametrize("G,seed", [(1, 1), (2, 2), (3, 3), (37, 4), (64, 5), (100, 6), (131, 7)])
+def test_cnn_f32_full_grid(C, oracle_mod, wl, G, seed):
+    print(f"[cnn f32] G={G} seed={seed}", flush=True)
+    rng = np.random.default_rng(seed)
+    vel = rng.standard_normal((2, G, G)).astype(np.float32)
+    ws, bs = wl.random_weights(seed)
+    mesh = _square_mesh(C, G)
+    W = C.Weights(ws, bs)
+    disp = C.predict(mesh, _dev(vel), W, "f32")
+    torch.cuda.synchronize()
+    ref = oracle_mod.cnn_forward(vel, ws, bs)
+    assert _within(disp.cpu().numpy(), ref) <= 1.0
+
+
+def test_cnn_constructed_weights_exact(C, oracle_mod, wl):
+    """Pass-through weights: the net computes -dt u, every product exact; GPU = FP32 rounding of the oracle."""
+    from test_oracle_lookup_cnn import constructed_weights
+    w = wl.build("c1")
+    ws, bs = constructed_weights(w.dt)
+    mesh = C.Mesh(w.xy, w.tri, overlay_side=w.G)
+    disp = C.predict(mesh, _dev(w.vel), C.Weights(ws, bs), "f32")
+    ref = oracle_mod.cnn_forward(w.vel, ws, bs)
+    assert np.array_equal(disp.cpu().numpy(), ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("name,nsample", [("c2", 3000), ("c3", 1500)])
+def test_cnn_f32_full_size_sampled(C, oracle_mod, wl, name, nsample):
+    """At the benchmark's overlay sizes: sampled pixels (including the borders and corners) one by one."""
+    cfg = wl.CONFIGS[name]
+    G = cfg["G"]
+    fld = wl.FourierVortices(cfg["field_seed"], norm_G=G)
+    vel = wl.overlay_velocity(fld, G)
+    ws, bs = wl.he_weights(200)
+    mesh = _square_mesh(C, G)
+    disp = C.predict(mesh, _dev(vel), C.Weights(ws, bs), "f32").cpu().numpy()
+    rng = np.random.default_rng(11)
+    rows = np.concatenate([rng.integers(0, G, nsample), [0, 0, G - 1, G - 1, 0, G - 1, 5, G // 2]])
+    cols = np.concatenate([rng.integers(0, G, nsample), [0, G - 1, 0, G - 1, G // 2, 3, 0, G - 1]])
+    ref = oracle_mod.cnn_pixels(vel, ws, bs, rows, cols).T  # [2][k]
+    # channel scale from a dense oracle window (the largest magnitudes of a 64 x 64 patch)
+    scale = np.abs(oracle_mod.cnn_window(vel, ws, bs, 0, 0, 64, 64)).reshape(2, -1).max(axis=1)
+    scale = np.maximum(scale, np.abs(ref).max(axis=1))
+    assert _within(disp[:, rows, cols], ref, scale=scale) <= 1.0
+
+
+def test_cnnsns_end_to_end(C, oracle_mod, wl):
+    """GPU predict + locate against oracle CNN + oracle Alg. 2: the same hosts; CNN-SNS shortens the walks."""
+    from test_oracle_lookup_cnn import constructed_weights
+    w = wl.build("c2")
+    ws, bs = constructed_weights(w.dt)
+    mesh = C.Mesh(w.xy, w.tri, overlay_side=w.G)
+    disp = C.predict(mesh, _dev(w.vel), C.Weights(ws, bs), "f32")
+    h, it, st = C.locate(mesh, _dev(w.xp), origin=_dev(w.origins), disp=disp)
+    h, it, st = h.cpu().numpy(), it.cpu().numpy(), st.cpu().numpy()
+    tc, nbr = oracle_mod.prepare_mesh(w.xy, w.tri)
+    lk = oracle_mod.lookup(w.xy, tc, w.G)
+    dref = oracle_mod.cnn_forward(w.vel, ws, bs)
+    s0, oh, oi, os_ = oracle_mod.cnnsns(w.xy, tc, nbr, lk, w.origins, w.xp, dref)
+    far = edge_distances(w.xy, tc, oh, w.xp) > 1e-9
+    assert np.array_equal(h[far], oh[far])
+    assert np.all(st == C.FOUND)
+    # the same start wherever the two displacement grids pick the same cell
+    ph, pi, ps = oracle_mod.sns(w.xy, tc, nbr, w.xp, w.start)
+    assert np.array_equal(h[far], ph[far])
+    assert it.mean() < 0.2 * pi.mean()
+    assert abs(it.mean() - oi.mean()) < 0.01 * oi.mean()
+
+
+def test_predict_errors(C):
+    mesh = _square_mesh(C, 8)
+    ws = [np.zeros((32, 2, 3, 3)), np.zeros((32, 32, 3, 3)), np.zeros((32, 32, 3, 3)), np.zeros((2, 32, 3, 3))]
+    bs = [np.zeros(32), np.zeros(32), np.zeros(32), np.zeros(2)]
+    W = C.Weights(ws, bs)
+    vel = torch.zeros((2, 8, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(C.CnnsnsError) as e:
+        C.predict(mesh, vel, W, 7)
+    assert e.value.code == C.EINVAL
+    out = C.predict(mesh, vel, W, "f32")
+    assert torch.count_nonzero(out) == 0

@@ -80,7 +80,8 @@ def test_unordered_points_and_flipped_triangles(C, oracle_mod, wl):
 
 def test_lookup_via_one_iteration_asg(C, oracle_mod, wl):
     """ASG start at the cell centres with one iteration returns the lookup itself."""
-    for n_side, G in [(40, 64), (40, 37), (200, 512)]:
+    # the last two cases put triangles over hundreds of cells (the block-parallel raster path)
+    for n_side, G in [(40, 64), (40, 37), (200, 512), (12, 700), (3, 1024)]:
         xy, tri = wl.mesh(n_side, 4, graded=True)
         mesh = C.Mesh(xy, tri, overlay_side=G)
         tc, nbr = oracle_mod.prepare_mesh(xy, tri)
