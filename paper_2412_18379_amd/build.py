@@ -25,6 +25,7 @@ SOURCES = {
     "mesh.hip": ["-ffp-contract=off"],
     "sns_walk.hip": ["-ffp-contract=off"],
     "cnn.hip": [],
+    "cnn_bf16.hip": [],
     "api.cpp": [],
     "serve.cpp": [],
 }

@@ -399,14 +399,19 @@ unsigned persistent_grid(int ntiles)
 
 size_t cnn_workspace_bytes(int32_t G, int32_t precision)
 {
-    (void)precision;
+    if (precision == CNNSNS_BF16) return cnn_bf16_workspace_bytes();
     return sizeof(float) * (2 * (size_t)WSW + (size_t)C * (size_t)G * (size_t)G);
 }
 
 void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp, void* ws,
              hipStream_t stream)
 {
-    if (precision != CNNSNS_F32) fail(CNNSNS_EINVAL, "predict: only FP32 is available in this build");
+    if (precision == CNNSNS_BF16) {
+        cnn_bf16_pack(w, ws, stream);
+        cnn_bf16_forward(G, vel, ws, w, disp, persistent_grid(1 << 30), stream);
+        return;
+    }
+    if (precision != CNNSNS_F32) fail(CNNSNS_EINVAL, "predict: FP8 is not available in this build");
     float* wsw2 = static_cast<float*>(ws);
     float* wsw3 = wsw2 + WSW;
     float* act2 = wsw3 + WSW;

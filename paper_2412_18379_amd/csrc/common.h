@@ -65,6 +65,11 @@ void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const in
 size_t cnn_workspace_bytes(int32_t G, int32_t precision);
 void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp, void* ws,
              hipStream_t stream);
+// cnn_bf16.hip
+size_t cnn_bf16_workspace_bytes();
+void cnn_bf16_pack(const cnnsns_cnn& w, void* packed, hipStream_t stream);
+void cnn_bf16_forward(int32_t G, const float* vel, const void* packed, const cnnsns_cnn& w, float* disp,
+                      unsigned grid, hipStream_t stream);
 void run_predict(cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
                  hipStream_t stream);
 

@@ -127,3 +127,80 @@ def test_predict_errors(C):
     assert e.value.code == C.EINVAL
     out = C.predict(mesh, vel, W, "f32")
     assert torch.count_nonzero(out) == 0
+
+
+# ---------------------------------------------------------------------------- BF16
+# BF16 bar: every layer rounds its inputs and weights to bf16 (relative error
+# <= 2^-9 each, round to nearest even) and accumulates in FP32, so four
+# layers carry about 4 x 2^-8 ~ 1.6% of the channel scale at worst with
+# norm-preserving weights; the test allows 3% of the channel maximum per
+# element and 0.5% on average.  Host elements must not change at all.
+BF16_MAX, BF16_MEAN = 0.03, 0.005
+
+
+def _bf16_errors(got, ref):
+    scale = np.abs(ref).reshape(ref.shape[0], -1).max(axis=1).reshape(-1, *([1] * (ref.ndim - 1)))
+    e = np.abs(np.asarray(got, np.float64) - ref) / scale
+    return float(e.max()), float(e.mean())
+
+
+@pytest.mark.parametrize("G,seed", [(1, 1), (5, 2), (37, 4), (100, 6), (131, 7)])
+def test_cnn_bf16_full_grid(C, oracle_mod, wl, G, seed):
+    print(f"[cnn bf16] G={G} seed={seed}", flush=True)
+    rng = np.random.default_rng(seed)
+    vel = rng.standard_normal((2, G, G)).astype(np.float32)
+    ws, bs = wl.random_weights(seed)
+    mesh = _square_mesh(C, G)
+    disp = C.predict(mesh, _dev(vel), C.Weights(ws, bs), "bf16").cpu().numpy()
+    ref = oracle_mod.cnn_forward(vel, ws, bs)
+    emax, emean = _bf16_errors(disp, ref)
+    assert emax <= BF16_MAX and emean <= BF16_MEAN, (emax, emean)
+
+
+def test_cnn_bf16_constructed_weights(C, oracle_mod, wl):
+    """Pass-through weights: each output is one bf16 product, within 2 bf16 roundings of the oracle."""
+    from test_oracle_lookup_cnn import constructed_weights
+    w = wl.build("c1")
+    ws, bs = constructed_weights(w.dt)
+    mesh = C.Mesh(w.xy, w.tri, overlay_side=w.G)
+    disp = C.predict(mesh, _dev(w.vel), C.Weights(ws, bs), "bf16").cpu().numpy().astype(np.float64)
+    ref = oracle_mod.cnn_forward(w.vel, ws, bs)
+    assert np.all(np.abs(disp - ref) <= 2.0 ** -7 * np.abs(ref) + 1e-30)
+
+
+def test_cnn_bf16_full_size_sampled(C, oracle_mod, wl):
+    G = 4096
+    fld = wl.FourierVortices(30, norm_G=G)
+    vel = wl.overlay_velocity(fld, G)
+    ws, bs = wl.he_weights(200)
+    mesh = _square_mesh(C, G)
+    disp = C.predict(mesh, _dev(vel), C.Weights(ws, bs), "bf16").cpu().numpy()
+    rng = np.random.default_rng(3)
+    rows = np.concatenate([rng.integers(0, G, 1000), [0, G - 1, 0, G - 1]])
+    cols = np.concatenate([rng.integers(0, G, 1000), [0, 0, G - 1, G - 1]])
+    ref = oracle_mod.cnn_pixels(vel, ws, bs, rows, cols).T
+    win = oracle_mod.cnn_window(vel, ws, bs, 0, 0, 64, 64)
+    scale = np.maximum(np.abs(win).reshape(2, -1).max(axis=1), np.abs(ref).max(axis=1))[:, None]
+    e = np.abs(disp[:, rows, cols] - ref) / scale
+    assert e.max() <= BF16_MAX and e.mean() <= BF16_MEAN, (e.max(), e.mean())
+
+
+def test_cnnsns_bf16_hosts_unchanged(C, oracle_mod, wl):
+    """The BF16 CNN can only move the start: hosts equal plain SNS (oracle) for every point off the edges."""
+    from paper_2412_18379_amd import train as T
+    w = wl.build("c2")
+    tr = T.load("c2")
+    ws, bs = tr if tr is not None else wl.he_weights(200)
+    mesh = C.Mesh(w.xy, w.tri, overlay_side=w.G)
+    disp = C.predict(mesh, _dev(w.vel), C.Weights(ws, bs), "bf16")
+    h, it, st = C.locate(mesh, _dev(w.xp), origin=_dev(w.origins), disp=disp)
+    h, it, st = h.cpu().numpy(), it.cpu().numpy(), st.cpu().numpy()
+    tc, nbr = oracle_mod.prepare_mesh(w.xy, w.tri)
+    ph, pi, ps = oracle_mod.sns(w.xy, tc, nbr, w.xp, w.start)
+    far = edge_distances(w.xy, tc, ph, w.xp) > 1e-9
+    assert np.all(st == C.FOUND)
+    assert np.array_equal(h[far], ph[far])
+    # and with the same displacement grid the oracle's Alg. 2 gives the same starts and walks
+    lk = oracle_mod.lookup(w.xy, tc, w.G)
+    s0, oh, oi, os_ = oracle_mod.cnnsns(w.xy, tc, nbr, lk, w.origins, w.xp, disp.cpu().numpy().astype(np.float64))
+    assert np.array_equal(h, oh) and np.array_equal(it, oi)
