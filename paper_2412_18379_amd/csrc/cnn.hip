@@ -397,6 +397,11 @@ unsigned persistent_grid(int ntiles)
 
 }  // namespace
 
+unsigned cnn_persistent_grid()
+{
+    return persistent_grid(1 << 30);
+}
+
 size_t cnn_workspace_bytes(int32_t G, int32_t precision)
 {
     if (precision == CNNSNS_BF16) return cnn_bf16_workspace_bytes();

@@ -62,6 +62,7 @@ void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const in
                    uint8_t* status, hipStream_t stream);
 
 // cnn.hip
+unsigned cnn_persistent_grid();  // one block per compute unit
 size_t cnn_workspace_bytes(int32_t G, int32_t precision);
 void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp, void* ws,
              hipStream_t stream);

@@ -1,6 +1,8 @@
 // Serving loop: continuous batching of CNN-SNS jobs on resident meshes.
 #pragma once
 
+#include <memory>
+
 #include "common.h"
 
 namespace cnnsns {
