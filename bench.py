@@ -17,6 +17,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import faulthandler
 import hashlib
 import json
 import os
@@ -59,6 +60,18 @@ def traffic_for(kernel: str, workload: str, sha: str):
     return e.get("hbm_bytes_per_launch")
 
 
+def _off_edge(w, host, pts, eps=1e-9):
+    """Points farther than eps from every edge of their (oracle) host element."""
+    V = w.xy[w.tri[host]]
+    best = np.full(len(pts), np.inf)
+    for k in range(3):
+        a, b = V[:, k], V[:, (k + 1) % 3]
+        d = b - a
+        t = np.clip(np.einsum("ij,ij->i", pts - a, d) / np.einsum("ij,ij->i", d, d), 0.0, 1.0)
+        best = np.minimum(best, np.hypot(*(a + t[:, None] * d - pts).T))
+    return best > eps
+
+
 def pct(a, q):
     return float(np.percentile(a, q))
 
@@ -98,15 +111,124 @@ def cpu_baseline(w, ws, bs, band_rows: int):
                    f"({setup_s:.1f}s)"),
         "plain_sns_value": n / t_plain, "plain_sns_s": t_plain, "mean_path_cnn_sns": float(it.mean()),
         "mean_path_plain": float(pit.mean()),
+        "_band": (r0, r1, band), "_sel": sel, "_plain_host": ph,
     }
 
 
+def bench_served(args):
+    """Served mix: resident meshes of uneven size, CNN-SNS jobs arriving as a Poisson process,
+    continuous batching by the library's server (BF16 CNN, FP64 walk)."""
+    import torch
+
+    from paper_2412_18379_amd import cnnsns as C
+    from paper_2412_18379_amd import train as T
+    from paper_2412_18379_amd import workload as W
+
+    t0 = time.perf_counter()
+    specs = W.served_mix_specs(n_meshes=args.mix_meshes, seed=5)
+    meshes = []
+    for spec in specs:
+        w = W.build_served(spec)
+        m = C.Mesh(w.xy, w.tri, overlay_side=w.G)
+        meshes.append(dict(w=w, mesh=m, xp=torch.from_numpy(w.xp).cuda(), origin=torch.from_numpy(w.origins).cuda(),
+                           start=torch.from_numpy(w.start).cuda(), vel=torch.from_numpy(w.vel).cuda()))
+    torch.cuda.synchronize()
+    n_tri = sum(d["w"].n_tri for d in meshes)
+    n_pts = np.array([d["w"].n_points for d in meshes])
+    log(f"served mix: {len(meshes)} meshes, {n_tri} triangles, {n_pts.sum()} points "
+        f"({time.perf_counter() - t0:.1f}s)")
+    tr = T.load("c5")
+    ws, bs = tr if tr is not None else W.he_weights(200)
+    Wt = C.Weights(ws, bs)
+    prec = args.precision or "bf16"
+
+    # each job alone (reference for the alone-vs-mix check) and plain SNS over the mix
+    ref = []
+    for d in meshes:
+        disp = C.predict(d["mesh"], d["vel"], Wt, prec)
+        h, it, _ = C.locate(d["mesh"], d["xp"], origin=d["origin"], disp=disp)
+        ref.append((h, it))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plain_it = []
+    for d in meshes:
+        plain_it.append(C.locate(d["mesh"], d["xp"], start=d["start"])[1])
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    cnn_it = np.concatenate([r[1].cpu().numpy() for r in ref])
+    plain_it = np.concatenate([x.cpu().numpy() for x in plain_it])
+
+    budget = 4 << 30
+    srv = C.Server(Wt, hbm_budget_bytes=budget, max_inflight=8, queue_depth=1 << 16, precision=prec)
+
+    def run(order, arrivals=None):
+        outs, ids = [], []
+        tstart = time.perf_counter()
+        for k, mi in enumerate(order):
+            d = meshes[mi]
+            if arrivals is not None:
+                while time.perf_counter() - tstart < arrivals[k]:
+                    pass
+            h = torch.empty(d["w"].n_points, dtype=torch.int32, device="cuda")
+            it = torch.empty(d["w"].n_points, dtype=torch.int32, device="cuda")
+            ids.append(srv.submit(d["mesh"], d["vel"], d["xp"], d["origin"], h, it))
+            outs.append((mi, h, it))
+        lat = np.array([srv.wait(i) for i in ids])
+        wall = time.perf_counter() - tstart
+        return outs, lat, wall
+
+    run(list(range(min(16, len(meshes)))))  # warm-up
+    order = list(range(len(meshes)))
+    outs, lat_sat, wall_sat = run(order)
+    same = all(torch.equal(h, ref[mi][0]) and torch.equal(it, ref[mi][1]) for mi, h, it in outs)
+    mu = len(order) / wall_sat
+    log(f"saturation: {mu:.1f} jobs/s, {n_pts.sum() / wall_sat:.4g} points/s, alone == mix: {same}")
+    rng = np.random.default_rng(5)
+    legs = {}
+    for frac in (0.5, 0.9):
+        lam = frac * mu
+        order = rng.integers(0, len(meshes), size=args.mix_jobs).tolist()
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(order)))
+        arrivals -= arrivals[0]
+        outs, lat, wall = run(order, arrivals)
+        pts = int(n_pts[order].sum())
+        legs[f"{frac:.1f}mu"] = {"rate_jobs_per_s": round(lam, 2), "jobs": len(order),
+                                 "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                                 "points_per_s": round(pts / wall, 1), "wall_s": round(wall, 3)}
+        log(f"lambda = {frac} mu: p50 {legs[f'{frac:.1f}mu']['p50_ms']} ms, p99 {legs[f'{frac:.1f}mu']['p99_ms']} ms")
+    srv.close()
+    hi = legs["0.9mu"]
+    res = {
+        "metric": "points located/s CNN-SNS vs SNS (1 GPU); mean SNS path length; p99 latency",
+        "value": hi["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": args.mix_jobs, "warmup": 16,
+        "ms_per_step": round(1e3 * hi["wall_s"] / args.mix_jobs, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": f"{prec} CNN / f64 SNS", "data": "synthetic",
+        "config": {"workload": f"served mix: {len(meshes)} resident meshes, triangles log-uniform in [1e4, 4e6], "
+                               f"Poisson arrivals, continuous batching", "n_meshes": len(meshes),
+                   "n_triangles": n_tri, "points_per_pass": int(n_pts.sum()), "hbm_budget_bytes": budget,
+                   "max_inflight": 8, "weights": "trained (mix)" if tr is not None else "he-init"},
+        "saturation": {"jobs_per_s": round(mu, 2), "points_per_s": round(float(n_pts.sum()) / wall_sat, 1),
+                       "p50_ms": round(float(np.percentile(lat_sat, 50)), 3),
+                       "p99_ms": round(float(np.percentile(lat_sat, 99)), 3)},
+        "poisson": legs, "alone_equals_mix": bool(same),
+        "mean_path_length": {"cnn_sns": round(float(cnn_it.mean()), 3), "plain_sns": round(float(plain_it.mean()), 3)},
+        "plain_sns_points_per_s_sequential": round(float(n_pts.sum()) / (plain_ms / 1e3), 1),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
+    faulthandler.enable()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--mix-meshes", type=int, default=64, help="served mix: number of meshes")
+    ap.add_argument("--mix-jobs", type=int, default=512, help="served mix: jobs per arrival rate")
     ap.add_argument("--precision", default=None, choices=["f32", "bf16", "fp8"])
     ap.add_argument("--weights", default="trained", choices=["trained", "he"])
     ap.add_argument("--cpu-band-rows", type=int, default=0, help="oracle sample band (0: auto)")
@@ -125,6 +247,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     C.lib()
+    if args.workload == "c5":
+        # Switched off: one run of this served-mix benchmark ended in a host
+        # segmentation fault after the meshes were built, with no GPU fault;
+        # the cause has not been found (the serving loop passes its GPU parity
+        # tests and its scheduler passes host sanitizer tests), so it stays off
+        # until it is.
+        sys.exit("bench.py: the served-mix workload (c5) is switched off until the cause of a host crash "
+                 "in it is found")
     precision = args.precision or ("bf16" if args.workload == "c4" else "f32")
     wl_name = "c2" if args.workload == "c4" else args.workload
     t0 = time.perf_counter()
@@ -259,11 +389,30 @@ def main():
         "status_found_frac": float(np.mean(st_c == C.FOUND)),
         "roofline": roofline, "roofline_sns": roofline_sns,
     }
+    if precision != "f32":
+        # the same step with the FP32 CNN: how much the lower precision lengthens the walks
+        disp32 = C.predict(mesh, vel, Wt, "f32")
+        _, it32, _ = C.locate(mesh, xp, origin=origin, disp=disp32)
+        it32 = it32.cpu().numpy()
+        res["precision_report"] = {"mean_path_f32_cnn": round(float(it32.mean()), 4),
+                                   "mean_path_change": round(float(it_c.mean() - it32.mean()), 4)}
     if not args.no_cpu_baseline:
         band = args.cpu_band_rows or {"c2": 256, "c3": 256, "c4": 256}[args.workload]
         t0 = time.perf_counter()
         cb = cpu_baseline(w, ws, bs, band)
         log(f"cpu baseline: {cb['value']:.0f} points/s on {cb['cores']} threads ({time.perf_counter() - t0:.1f}s)")
+        r0, r1, ref_band = cb.pop("_band")
+        sel, oracle_host = cb.pop("_sel"), cb.pop("_plain_host")
+        # host elements of the band's points against the oracle (points on an edge may take either element)
+        far = _off_edge(w, oracle_host, w.xp[sel])
+        res["host_agreement_with_oracle_band"] = float(np.mean(host_c[sel][far] == oracle_host[far]))
+        if precision != "f32":
+            got = disp.cpu().numpy()[:, r0:r1, :].astype(np.float64)
+            err = np.hypot(*(got - ref_band)) / w.dbar
+            res["precision_report"].update({
+                "disp_error_vs_fp64_oracle_diameters": {"max": round(float(err.max()), 5),
+                                                        "mean": round(float(err.mean()), 6)},
+                "error_sample": f"overlay rows [{r0},{r1}) of {G} (the oracle's CNN band)"})
         res["cpu_baseline"] = cb
     else:
         res["cpu_baseline"] = None

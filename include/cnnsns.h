@@ -183,8 +183,9 @@ int cnnsns_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int32_t
  * (DEVICE FP32 [2][G][G]), with x_p = xp (DEVICE FP64 [n][2]) and positions
  * before movement origin (DEVICE FP64 [n][2]); results go to host / iters
  * (DEVICE int32 [n], iters may be NULL).  start (DEVICE int32 [n]) may be
- * NULL; it is only the fallback for uncovered overlay cells.  Buffers must
- * stay valid until the job completes.  Returns at once with *job_id.
+ * NULL; it is only the fallback for uncovered overlay cells.  With n == 0
+ * the point buffers may be NULL (the job is the forward pass alone).  Buffers
+ * must stay valid until the job completes.  Returns at once with *job_id.
  * Errors: EINVAL, EBUSY (queue full), ENOMEM (the job alone exceeds the budget).
  */
 int cnnsns_submit(cnnsns_server s, cnnsns_mesh m, const float* vel, int64_t n, const double* xp,

@@ -137,8 +137,9 @@ int cnnsns_submit(cnnsns_server s, cnnsns_mesh m, const float* vel, int64_t n, c
                   const int32_t* start, int32_t* host, int32_t* iters, uint64_t* job_id)
 {
     return guarded([&] {
-        if (!s || !m || !vel || !xp || !origin || !host || !job_id) fail(CNNSNS_EINVAL, "submit: NULL argument");
+        if (!s || !m || !vel || !job_id) fail(CNNSNS_EINVAL, "submit: NULL argument");
         if (n < 0) fail(CNNSNS_EINVAL, "submit: n must be >= 0");
+        if (n > 0 && (!xp || !origin || !host)) fail(CNNSNS_EINVAL, "submit: NULL point buffer");
         *job_id = server_submit(s, m, vel, n, xp, origin, start, host, iters);
     });
 }

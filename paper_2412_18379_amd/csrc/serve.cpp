@@ -168,6 +168,17 @@ void launch_batch(cnnsns_server_s& s, const std::vector<uint64_t>& ids)
 {
     Batch b;
     b.jobs = ids;
+    struct Guard {  // frees the batch's graph objects unless it was handed to the running list
+        Batch& b;
+        bool armed = true;
+        ~Guard()
+        {
+            if (!armed) return;
+            if (b.exec) (void)hipGraphExecDestroy(b.exec);
+            if (b.graph) (void)hipGraphDestroy(b.graph);
+            if (b.done) (void)hipEventDestroy(b.done);
+        }
+    } guard{ b };
     const size_t nb = std::min(ids.size(), s.branch.size());
     hip_check(hipStreamBeginCapture(s.capture, hipStreamCaptureModeRelaxed), "begin capture");
     try {
@@ -186,11 +197,16 @@ void launch_batch(cnnsns_server_s& s, const std::vector<uint64_t>& ids)
         throw;
     }
     hip_check(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "graph instantiate");
+    hip_check(hipEventCreateWithFlags(&b.done, hipEventDisableTiming), "event");
     hipStream_t st = s.streams[s.next_stream++ % s.streams.size()];
     hip_check(hipGraphLaunch(b.exec, st), "graph launch");
-    hip_check(hipEventCreateWithFlags(&b.done, hipEventDisableTiming), "event");
-    hip_check(hipEventRecord(b.done, st), "event record");
+    if (hipEventRecord(b.done, st) != hipSuccess) {
+        // the graph is running: its jobs' memory may only be released once it has finished
+        (void)hipStreamSynchronize(st);
+        fail(CNNSNS_EHIP, "serve: cannot record the completion event of a batch");
+    }
     s.running.push_back(b);
+    guard.armed = false;
 }
 
 void release_batch(cnnsns_server_s& s, Batch& b, Clock::time_point now, int err)

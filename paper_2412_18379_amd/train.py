@@ -102,6 +102,74 @@ def make_training_set(name: str, n_t: int = 3):
     return np.stack(vels), np.stack(tgts), np.stack(masks), dt, dbar
 
 
+def make_mix_training_set(n_meshes: int = 6, seed: int = 7):
+    """Served-mix training data: meshes and flows disjoint from the benchmark's
+    (mesh seeds 5000+k of the served_mix_specs(seed=7) list), with the one-step
+    displacement field as input.  Each sample is weighted by 1 / (its mean
+    displacement)^2 so that small and large displacements count alike."""
+    specs = W.served_mix_specs(n_meshes=n_meshes, seed=seed, lo=1e4, hi=6e5)
+    samples = []
+    for k, spec in enumerate(specs):
+        spec = dict(spec, seed=7000 + k, field_seed=8000 + k)
+        w = W.build_served(spec)
+        fu, fv = w.flow(w.origins[:, 0], w.origins[:, 1])
+        raw = np.stack([w.origins[:, 0] - w.dt * fu, w.origins[:, 1] - w.dt * fv], axis=1)
+        t, m = cell_targets(w.origins, raw, w.G)
+        scale = float(np.mean(np.hypot(w.dt * fu, w.dt * fv)))
+        samples.append((w.vel / scale, (t / scale).astype(np.float32), m, scale))
+    return samples
+
+
+def train_mix(steps: int = 3000, crop: int = 64, batch: int = 8, lr: float = 2e-3, seed: int = 0,
+              threads: int = 0, verbose: bool = True):
+    """One net for the served mix: input dt u (displacement per step), output the displacement.
+    Inputs and targets of a mesh are divided by its mean displacement during training (the
+    map to learn, D = -dt u, commutes with that scaling)."""
+    if threads:
+        torch.set_num_threads(threads)
+    torch.manual_seed(seed)
+    rng = np.random.default_rng(seed)
+    samples = make_mix_training_set()
+    R = 4
+    padded = []
+    for vin, tgt, m, sc in samples:
+        G = vin.shape[-1]
+        padded.append((np.pad(vin, ((0, 0), (R, R), (R, R))), np.pad(tgt, ((0, 0), (R, R), (R, R))),
+                       np.pad(m.astype(np.float32), ((R, R), (R, R))),
+                       np.pad(np.ones((G, G), np.float32), ((R, R), (R, R))), G))
+    net = Net()
+    opt = torch.optim.Adam(net.parameters(), lr=lr)
+    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, steps)
+    t0 = time.time()
+    for it in range(steps):
+        xs, ys, ms, ins = [], [], [], []
+        for _ in range(batch):
+            pv, pt, pm, pin, G = padded[rng.integers(0, len(padded))]
+            cs = min(crop, G)
+            r = int(np.clip(rng.integers(0, G) - cs // 2, 0, G - cs))
+            c = int(np.clip(rng.integers(0, G) - cs // 2, 0, G - cs))
+            xs.append(pv[:, r:r + cs + 2 * R, c:c + cs + 2 * R])
+            ys.append(pt[:, r + R:r + R + cs, c + R:c + R + cs])
+            ms.append(pm[r + R:r + R + cs, c + R:c + R + cs])
+            ins.append(pin[r:r + cs + 2 * R, c:c + cs + 2 * R])
+        x = torch.from_numpy(np.stack(xs))
+        y = torch.from_numpy(np.stack(ys))
+        m = torch.from_numpy(np.stack(ms)).unsqueeze(1)
+        inside = torch.from_numpy(np.stack(ins)).unsqueeze(1)
+        out = net(x, inside)[:, :, R:R + cs, R:R + cs]
+        loss = ((out - y) ** 2 * m).sum() / (2 * m.sum().clamp(min=1.0))
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        sched.step()
+        if verbose and (it % 200 == 0 or it == steps - 1):
+            print(f"step {it:5d} loss {loss.item():.3e} rms error {np.sqrt(loss.item()):.4f} of the mean "
+                  f"displacement ({time.time() - t0:.0f}s)", flush=True)
+    ws = [np.ascontiguousarray(c.weight.detach().numpy().astype(np.float32)) for c in net.convs]
+    bs = [np.ascontiguousarray(c.bias.detach().numpy().astype(np.float32)) for c in net.convs]
+    return ws, bs, dict(final_loss=loss.item(), steps=steps, crop=crop, batch=batch, lr=lr)
+
+
 def train(name: str, steps: int = 1500, crop: int = 64, batch: int = 8, lr: float = 2e-3, seed: int = 0,
           threads: int = 0, verbose: bool = True, edge_frac: float = 0.25, edge_weight: float = 10.0):
     if threads:
@@ -224,6 +292,10 @@ if __name__ == "__main__":
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--eval-only", action="store_true")
     a = ap.parse_args()
+    if a.workload == "c5":
+        ws, bs, meta = train_mix(steps=a.steps, crop=a.crop, batch=a.batch, threads=a.threads)
+        print("saved", save(a.workload, ws, bs, meta))
+        raise SystemExit(0)
     if a.eval_only:
         ws, bs = load(a.workload)
     else:

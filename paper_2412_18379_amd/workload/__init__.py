@@ -324,7 +324,12 @@ def served_mix_specs(n_meshes: int = 64, seed: int = 5, lo: float = 1e4, hi: flo
 
 def build_served(spec: dict) -> Workload:
     """One served-mix mesh: dt = 20 dbar / mean|u| of the U = 1 field, so that the
-    displacement grows with U (about 10 to 80 element diameters)."""
+    displacement grows with U (about 10 to 80 element diameters).
+
+    Meshes of the mix have different time steps, so the overlay input of a
+    served job is the displacement over one step, dt u, sampled at the cell
+    centres (FP32 [2][G][G]); one shared network maps it to the start
+    displacement whatever the mesh."""
     xy, tri = mesh(spec["n_side"], spec["seed"])
     G = spec["G"]
     fld1 = FourierVortices(spec["field_seed"], U=1.0, norm_G=G)
@@ -334,8 +339,9 @@ def build_served(spec: dict) -> Workload:
     dt = 20.0 * dbar / float(np.mean(np.hypot(u, v)))
     xp = departure_points(xy, fld, dt)
     start = node_start_elements(xy.shape[0], tri)
+    vel = np.ascontiguousarray((overlay_velocity(fld, G).astype(np.float64) * dt).astype(np.float32))
     return Workload(name=f"mix{spec['seed']}", n_side=spec["n_side"], xy=xy, tri=tri, origins=xy, xp=xp,
-                    start=start, G=G, vel=overlay_velocity(fld, G), dt=dt, dbar=dbar, flow=fld,
+                    start=start, G=G, vel=vel, dt=dt, dbar=dbar, flow=fld,
                     seeds=dict(mesh=spec["seed"], field=spec["field_seed"]))
 
 
