@@ -39,25 +39,33 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def source_sha(*names):
-    h = hashlib.sha256()
-    for n in names:
-        with open(os.path.join(ROOT, "paper_2412_18379_amd", "csrc", n), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+def traffic_for(group: str, workload: str):
+    """HBM bytes per launch of a kernel group, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the
+    current source of its kernels (scaled by a copy of known size), else None."""
+    from paper_2412_18379_amd import profiling as P
 
-
-def traffic_for(kernel: str, workload: str, sha: str):
-    """HBM traffic per launch measured with rocprofv3 counters for this exact kernel source, else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         db = json.load(f)
-    e = db.get(f"{kernel}@{workload}")
-    if not e or e.get("source_sha") != sha:
+    e = db.get(f"{group}@{workload}")
+    if not e or e.get("source_sha") != P.source_sha(*P.SOURCES[group]):
         return None
     return e.get("hbm_bytes_per_launch")
+
+
+def copy_probe(nbytes: int, reps: int = 3):
+    """A device-to-device copy of nbytes (the calibration run for the HBM byte counters)."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
 
 
 def _off_edge(w, host, pts, eps=1e-9):
@@ -233,6 +241,9 @@ def main():
     ap.add_argument("--weights", default="trained", choices=["trained", "he"])
     ap.add_argument("--cpu-band-rows", type=int, default=0, help="oracle sample band (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16-variant", action="store_true", help="skip the BF16 CNN leg of an FP32 run")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device copy of BYTES (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -246,6 +257,8 @@ def main():
     from paper_2412_18379_amd import workload as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
     C.lib()
     if args.workload == "c5":
         # Switched off: one run of this served-mix benchmark ended in a host
@@ -344,19 +357,17 @@ def main():
     bytes_plain = REC_BYTES * float(it_p.sum()) + n * (16 + 4 + out_b)
     gbps_cnn_walk = bytes_cnn_walk / (loc_ms.mean() / 1e3) / 1e9
     gbps_plain = bytes_plain / (plain_ms.mean() / 1e3) / 1e9
-    cnn_sha = source_sha("cnn.hip")
-    walk_sha = source_sha("sns_walk.hip")
     roofline = {
         "kernel": "cnn forward (conv12 + conv34 kernels, one cnnsns_predict)",
         "bound": "mfma", "achieved": round(cnn_tf, 3), "peak": cnn_peak, "unit": "TFLOP/s",
         "frac": round(cnn_tf / cnn_peak, 4),
-        "traffic": traffic_for("cnn_forward", args.workload, cnn_sha),
+        "traffic": traffic_for(f"cnn_forward_{precision}", args.workload),
         "algorithmic_per_launch": f"{cnn_flops:.4e} FLOP (2 x 19584 MAC x G^2, G={G})",
     }
     roofline_sns = {
         "kernel": "k_locate (plain SNS leg)", "bound": "hbm", "achieved": round(gbps_plain, 1),
         "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": round(gbps_plain / PEAK["hbm_GBps"], 4),
-        "traffic": traffic_for("k_locate_plain", args.workload, walk_sha),
+        "traffic": traffic_for("k_locate_plain", args.workload),
         "algorithmic_per_launch": f"{bytes_plain:.4e} B (60 B x sum I_t + 29 B x n)",
         "cnn_sns_leg": {"achieved": round(gbps_cnn_walk, 1), "frac": round(gbps_cnn_walk / PEAK["hbm_GBps"], 4),
                         "algorithmic_per_launch": f"{bytes_cnn_walk:.4e} B (60 B x sum I_t + 69 B x n)"},
@@ -389,6 +400,47 @@ def main():
         "status_found_frac": float(np.mean(st_c == C.FOUND)),
         "roofline": roofline, "roofline_sns": roofline_sns,
     }
+    disp_bf = None
+    if precision == "f32" and not args.no_bf16_variant:
+        # the same step with the BF16 CNN (precision variant): time, walk lengths, hosts
+        disp_bf = torch.empty_like(disp)
+        host_b = torch.empty_like(host)
+        iters_b = torch.empty_like(iters)
+
+        def step_bf():
+            C.predict(mesh, vel, Wt, "bf16", disp=disp_bf)
+            C.locate(mesh, xp, origin=origin, disp=disp_bf, host=host_b, iters=iters_b, status=status)
+
+        for _ in range(args.warmup):
+            step_bf()
+        torch.cuda.synchronize()
+        eb = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+        t0 = time.perf_counter()
+        for k in range(K):
+            eb[k][0].record(stream)
+            C.predict(mesh, vel, Wt, "bf16", disp=disp_bf)
+            eb[k][1].record(stream)
+            C.locate(mesh, xp, origin=origin, disp=disp_bf, host=host_b, iters=iters_b, status=status)
+            eb[k][2].record(stream)
+        torch.cuda.synchronize()
+        wall_b = time.perf_counter() - t0
+        pb = np.array([eb[k][0].elapsed_time(eb[k][1]) for k in range(K)])
+        lb = np.array([eb[k][1].elapsed_time(eb[k][2]) for k in range(K)])
+        it_b = iters_b.cpu().numpy()
+        res["bf16_variant"] = {
+            "points_per_s": round(n / wall_b * K, 1), "ms_per_step": round(wall_b * 1e3 / K, 4),
+            "predict_ms": round(float(pb.mean()), 4), "locate_ms": round(float(lb.mean()), 4),
+            "speedup_vs_plain_sns": round(float(plain_ms.mean() / (pb + lb).mean()), 3),
+            "mean_path_length": round(float(it_b.mean()), 3),
+            "mean_path_change_vs_f32": round(float(it_b.mean() - it_c.mean()), 4),
+            "host_agreement_with_f32_path": float(np.mean(host_b.cpu().numpy() == host_c)),
+            "cnn_roofline": {"achieved": round(cnn_flops / (pb.mean() / 1e3) / 1e12, 3),
+                             "peak": PEAK["bf16_TFLOPs"], "unit": "TFLOP/s",
+                             "frac": round(cnn_flops / (pb.mean() / 1e3) / 1e12 / PEAK["bf16_TFLOPs"], 4),
+                             "traffic": traffic_for("cnn_forward_bf16", args.workload)},
+        }
+        log(f"BF16 CNN-SNS: {res['bf16_variant']['ms_per_step']:.3f} ms/step (predict {pb.mean():.3f} ms), "
+            f"mean I_t {it_b.mean():.2f}")
     if precision != "f32":
         # the same step with the FP32 CNN: how much the lower precision lengthens the walks
         disp32 = C.predict(mesh, vel, Wt, "f32")
@@ -397,7 +449,7 @@ def main():
         res["precision_report"] = {"mean_path_f32_cnn": round(float(it32.mean()), 4),
                                    "mean_path_change": round(float(it_c.mean() - it32.mean()), 4)}
     if not args.no_cpu_baseline:
-        band = args.cpu_band_rows or {"c2": 256, "c3": 256, "c4": 256}[args.workload]
+        band = args.cpu_band_rows or {"c2": 1024, "c3": 768, "c4": 1024}[args.workload]
         t0 = time.perf_counter()
         cb = cpu_baseline(w, ws, bs, band)
         log(f"cpu baseline: {cb['value']:.0f} points/s on {cb['cores']} threads ({time.perf_counter() - t0:.1f}s)")
@@ -406,13 +458,26 @@ def main():
         # host elements of the band's points against the oracle (points on an edge may take either element)
         far = _off_edge(w, oracle_host, w.xp[sel])
         res["host_agreement_with_oracle_band"] = float(np.mean(host_c[sel][far] == oracle_host[far]))
-        if precision != "f32":
-            got = disp.cpu().numpy()[:, r0:r1, :].astype(np.float64)
+        def disp_error(dgpu):
+            got = dgpu.cpu().numpy()[:, r0:r1, :].astype(np.float64)
             err = np.hypot(*(got - ref_band)) / w.dbar
-            res["precision_report"].update({
-                "disp_error_vs_fp64_oracle_diameters": {"max": round(float(err.max()), 5),
-                                                        "mean": round(float(err.mean()), 6)},
-                "error_sample": f"overlay rows [{r0},{r1}) of {G} (the oracle's CNN band)"})
+            return {"max": round(float(err.max()), 6), "mean": round(float(err.mean()), 7)}
+
+        sample = f"overlay rows [{r0},{r1}) of {G} (the oracle's CNN band)"
+        if precision != "f32":
+            res["precision_report"].update({"disp_error_vs_fp64_oracle_diameters": disp_error(disp),
+                                            "error_sample": sample})
+        else:
+            # full-size parity of the timed FP32 forward pass on the band: the bar per channel c is
+            # |y - y_ref| <= 1e-5 |y_ref| + 1e-5 max_c |y_ref|
+            got = disp.cpu().numpy()[:, r0:r1, :].astype(np.float64)
+            scale = np.abs(ref_band).reshape(2, -1).max(axis=1)[:, None, None]
+            ratio = float((np.abs(got - ref_band) / (1e-5 * np.abs(ref_band) + 1e-5 * scale + 1e-30)).max())
+            res["f32_parity_on_band"] = {"worst_error_over_tolerance": round(ratio, 4), "pass": ratio <= 1.0,
+                                         "sample": sample}
+            if disp_bf is not None:
+                res["bf16_variant"]["disp_error_vs_fp64_oracle_diameters"] = disp_error(disp_bf)
+                res["bf16_variant"]["error_sample"] = sample
         res["cpu_baseline"] = cb
     else:
         res["cpu_baseline"] = None
