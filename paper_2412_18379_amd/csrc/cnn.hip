@@ -8,16 +8,21 @@
 // wavefronts per compute unit, one wavefront per SIMD so each may hold 512
 // registers) looping over tiles:
 //   conv12: conv1 (K = 18 padded to 20) on the matrix cores into LDS on the
-//           16 x 32 tile plus a one-pixel border, then conv2 as an implicit
-//           GEMM (pixels x 32 output channels, K = 9 taps x 32 channels);
-//           writes the 32-channel activation, pixel-major ([G][G][32]).
-//   conv34: conv3 as an implicit GEMM on a 16 x 32 region (the 14 x 30 output
-//           tile plus a one-pixel border), kept in LDS, then conv4 (N = 2) on
-//           the vector ALU; writes the 2-channel displacement.
-// LDS tiles are pixel-major with a 36-float pixel stride: a lane fetches 4
-// channels of one pixel with one conflict-free 16-byte read, which feeds 4
-// matrix instructions.  The next tile's input is fetched into registers while
-// the current tile computes.
+//           16 x 32 tile plus a one-pixel border, then conv2; writes the
+//           32-channel activation, pixel-major ([G][G][32]).
+//   conv34: conv3 on a 16 x 32 region (the 14 x 30 output tile plus a
+//           one-pixel border), kept in LDS, then conv4 (N = 2) on the vector
+//           ALU; writes the 2-channel displacement.
+// The two 32 -> 32 layers use the Winograd minimal filtering algorithm
+// F(2x2, 3x3) (Lavin and Gray, 2016): per 2 x 2 output block and channel
+// pair, 16 products in a transformed domain replace 36 direct ones, so the
+// layer becomes 16 independent 32 x 32 channel contractions, run in FP32 on
+// the matrix cores (v_mfma_f32_16x16x4f32).  Transforms are exact-coefficient
+// FP32 additions; the transformed weights are computed once per call in FP64
+// and rounded to FP32.  LDS tiles are pixel-major with a 36-float pixel
+// stride, so a lane fetches 4 channels of one pixel with one 16-byte read.
+// The next tile's input is fetched into registers while the current tile
+// computes.
 #include "common.h"
 
 namespace cnnsns {
@@ -34,98 +39,149 @@ constexpr int NREG = RH * RW;            // 512 region pixels
 constexpr int C = 32;                    // hidden channels
 constexpr int PS = 36;                   // LDS floats per pixel (32 channels + 4 pad)
 constexpr int OH34 = RH - 2, OW34 = RW - 2;  // conv34 output tile (region minus its border)
-constexpr int WSW = 9 * 2 * 2 * 64 * 4;  // swizzled 32->32 weights (floats)
-constexpr int MB = 8;                    // M-blocks (16 pixels) per wavefront: 4 region rows
+constexpr int NU = 16 * 2 * 2 * 64 * 4;  // Winograd-domain 32->32 weights (floats)
 constexpr int VH = IH + 2, VW = IW + 2;  // velocity tile (two-pixel border) 20 x 36
 constexpr int VEL_PER_THREAD = (2 * VH * VW + kThreads - 1) / kThreads;
 constexpr int CHUNKS = NIN * C / 4;      // float4 chunks of an input tile
 constexpr int CHUNKS_PER_THREAD = (CHUNKS + kThreads - 1) / kThreads;
 constexpr int L1_MBLOCKS = (NIN + 15) / 16;
 
-static_assert(WSW == C * C * 9, "swizzle covers the whole layer");
+static_assert(NU == 16 * C * C, "transformed weights cover the whole layer");
 static_assert(NREG * PS <= NIN * PS, "output tile aliases the input tile");
-static_assert(kWaves * 4 == RH, "each wavefront takes four region rows");
+static_assert(kWaves * 4 == RH, "each wavefront takes two rows of 2 x 2 output blocks");
+static_assert(RW == 32, "a row of 2 x 2 output blocks is one 16-row matrix block");
 
-// Matrix-core operand order for a 32->32 layer (v_mfma_f32_16x16x4f32).  For
-// tap t, N-block nb and k-step s (0..7), lane l holds B = W[16 nb + l%16]
-// [8 (l/16) + s][t]; the A operand of lane l is input channel 8 (l/16) + s of
-// its pixel, so one 32-byte run of a pixel's channels serves 8 k-steps.
-// wsw[(((t * 2 + nb) * 2 + h) * 64 + l) * 4 + j] holds k-step s = 4h + j, so a
-// lane reads its B operands as float4s.
-__global__ void k_swizzle32(const float* __restrict__ w, float* __restrict__ wsw)
+// Winograd F(2x2, 3x3) for one 2 x 2 output block:
+//   Y = A^T [ (G g G^T) (.) (B^T d B) ] A
+// with d the 4 x 4 input patch, g the 3 x 3 filter, and
+//   B^T = [1 0 -1 0; 0 1 1 0; 0 -1 1 0; 0 1 0 -1],
+//   G   = [1 0 0; 1/2 1/2 1/2; 1/2 -1/2 1/2; 0 0 1],
+//   A^T = [1 1 1 0; 0 1 -1 -1].
+// Summed over input channels, the 16 elementwise products of position
+// (xi, nu) form a contraction M[xi][nu] = U[xi][nu] V[xi][nu] over channels,
+// U = G g G^T per (output, input) channel pair.
+//
+// Matrix-core operand order (v_mfma_f32_16x16x4f32): the 16 blocks of a
+// matrix row are the 16 output blocks of one block row; lane l holds block
+// l%16 and input channel 8 (l/16) + 4h + j in k-step j of channel half h.
+// u[(((xn * 2 + nb) * 2 + h) * 64 + l) * 4 + j] holds
+//   U[xn = 4 xi + nu][output channel 16 nb + l%16][input channel 8 (l/16) + 4h + j],
+// so a lane reads the B operands of four k-steps as one float4.
+__global__ void k_wino_weights(const float* __restrict__ w, float* __restrict__ u)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= WSW) return;
-    int j = k & 3, l = (k >> 2) & 63, h = (k >> 8) & 1, nb = (k >> 9) & 1, t = k >> 10;
-    int o = nb * 16 + (l & 15), ci = 8 * (l >> 4) + 4 * h + j;
-    wsw[k] = w[(o * C + ci) * 9 + t];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NU) return;
+    const int j = k & 3, l = (k >> 2) & 63, h = (k >> 8) & 1, nb = (k >> 9) & 1, xn = k >> 10;
+    const int xi = xn >> 2, nu = xn & 3;
+    const int o = nb * 16 + (l & 15), ci = 8 * (l >> 4) + 4 * h + j;
+    const double gm[4][3] = { { 1.0, 0.0, 0.0 }, { 0.5, 0.5, 0.5 }, { 0.5, -0.5, 0.5 }, { 0.0, 0.0, 1.0 } };
+    const float* g = w + (o * C + ci) * 9;
+    double acc = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) acc += gm[xi][a] * (double)g[a * 3 + b] * gm[nu][b];
+    u[k] = (float)acc;
 }
 
-__device__ __forceinline__ void load_tap(const float* __restrict__ s_in, const float* __restrict__ s_w, int wave,
-                                         int lane, int t, v4f (&a)[MB][2], v4f (&b)[2][2])
+// The 4 x 4 input patch of output block (ty, tx) of the region, channels
+// 8 g + 4 h .. +3, from the input tile in LDS (region pixel (y, x) is tile
+// pixel (y + 1, x + 1), so the patch starts at tile pixel (2 ty, 2 tx)).
+__device__ __forceinline__ void wino_patch(const float* __restrict__ s_in, int ty, int tx, int g, int h,
+                                           v4f (&d)[4][4])
 {
-    const int i = lane & 15, q = lane >> 4;
-    const int ty = t / 3, tx = t % 3;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-        const int P = (4 * wave + (mb >> 1) + ty) * IW + (mb & 1) * 16 + i + tx;
-        const v4f* src = reinterpret_cast<const v4f*>(s_in + P * PS + 8 * q);
-        a[mb][0] = src[0];
-        a[mb][1] = src[1];
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            d[a][b] = *reinterpret_cast<const v4f*>(s_in + ((2 * ty + a) * IW + 2 * tx + b) * PS + 8 * g + 4 * h);
+}
+
+// d <- B^T d B, in place (four channels at once).
+__device__ __forceinline__ void wino_input_transform(v4f (&d)[4][4])
+{
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const v4f t0 = d[0][b] - d[2][b], t1 = d[1][b] + d[2][b], t2 = d[2][b] - d[1][b], t3 = d[1][b] - d[3][b];
+        d[0][b] = t0;
+        d[1][b] = t1;
+        d[2][b] = t2;
+        d[3][b] = t3;
     }
-    const v4f* ws = reinterpret_cast<const v4f*>(s_w);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const v4f t0 = d[a][0] - d[a][2], t1 = d[a][1] + d[a][2], t2 = d[a][2] - d[a][1], t3 = d[a][1] - d[a][3];
+        d[a][0] = t0;
+        d[a][1] = t1;
+        d[a][2] = t2;
+        d[a][3] = t3;
+    }
+}
+
+// conv 32 -> 32 (no bias) for one row of 2 x 2 output blocks of the block's
+// 16 x 32 region: block row ty, region rows 2 ty and 2 ty + 1.  s_in holds the
+// 32-channel input on the 18 x 34 tile around the region, s_u the transformed
+// weights.  Result y[nb][r][2a + b]: region pixel (2 ty + a, 2 (4 (l/16) + r) + b),
+// output channel 16 nb + l%16.
+__device__ __forceinline__ void conv32_wino(const float* __restrict__ s_in, const float* __restrict__ s_u, int ty,
+                                            int lane, float (&y)[2][4][4])
+{
+    const int tx = lane & 15, g = lane >> 4;
+    const v4f* su = reinterpret_cast<const v4f*>(s_u) + lane;
+    v4f acc[16][2];
+#pragma unroll
+    for (int xn = 0; xn < 16; ++xn) {
+        acc[xn][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
+        acc[xn][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        v4f d[4][4];
+        wino_patch(s_in, ty, tx, g, h, d);
+        wino_input_transform(d);
+        // four transformed positions at a time: 8 independent accumulators between
+        // two updates of the same one, and the next group's weights read meanwhile
+#pragma unroll
+        for (int grp = 0; grp < 4; ++grp) {
+            v4f b[4][2];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                b[x][0] = su[(((4 * grp + x) * 2 + 0) * 2 + h) * 64];
+                b[x][1] = su[(((4 * grp + x) * 2 + 1) * 2 + h) * 64];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const int xn = 4 * grp + x;
+                    const float a = d[xn >> 2][xn & 3][j];
+                    acc[xn][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[x][0][j], acc[xn][0], 0, 0, 0);
+                    acc[xn][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[x][1][j], acc[xn][1], 0, 0, 0);
+                }
+        }
+    }
+    // Y = A^T M A for each of the lane's 4 blocks and 2 output channels
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) b[nb][h] = ws[((t * 2 + nb) * 2 + h) * 64 + lane];
-}
-
-// conv 32 -> 32 over the block's 16 x 32 region on the matrix cores.  s_in
-// holds the 32-channel input on the 18 x 34 tile around the region.  Wave w
-// covers region rows 4w .. 4w+3; M-block mb is row 4w + mb/2, columns
-// 16 (mb%2) .. +15.  Result acc[mb][nb][r]: region pixel
-// (4w + mb/2, 16 (mb%2) + 4 (l/16) + r), output channel 16 nb + l%16.
-// The operands of tap t+1 are read while the 128 instructions of tap t issue.
-__device__ __forceinline__ void conv32_mfma(const float* __restrict__ s_in, const float* __restrict__ s_w, int wave,
-                                            int lane, v4f (&acc)[MB][2])
-{
+        for (int r = 0; r < 4; ++r) {
+            float m0[4], m1[4];
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-        acc[mb][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
-        acc[mb][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
-    }
-    v4f a[2][MB][2], b[2][2][2];
-    load_tap(s_in, s_w, wave, lane, 0, a[0], b[0]);
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int cur = t & 1;
-        if (t + 1 < 9) load_tap(s_in, s_w, wave, lane, t + 1, a[cur ^ 1], b[cur ^ 1]);
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[cur][mb][s >> 2][s & 3],
-                                                                      b[cur][nb][s >> 2][s & 3], acc[mb][nb], 0, 0, 0);
-        if (t + 1 < 9) {
-            // spread the 20 reads of the next tap over this tap's 128 matrix instructions
-#pragma unroll
-            for (int k = 0; k < 20; ++k) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);  // MFMA
-                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+            for (int nu = 0; nu < 4; ++nu) {
+                m0[nu] = acc[nu][nb][r] + acc[4 + nu][nb][r] + acc[8 + nu][nb][r];
+                m1[nu] = acc[4 + nu][nb][r] - acc[8 + nu][nb][r] - acc[12 + nu][nb][r];
             }
-            __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+            y[nb][r][0] = m0[0] + m0[1] + m0[2];
+            y[nb][r][1] = m0[1] - m0[2] - m0[3];
+            y[nb][r][2] = m1[0] + m1[1] + m1[2];
+            y[nb][r][3] = m1[1] - m1[2] - m1[3];
         }
-    }
 }
 
-// Block loads of the swizzled 32->32 weights into LDS.
-__device__ __forceinline__ void load_wsw(const float* __restrict__ wsw, float* __restrict__ s_w)
+// Block loads of the transformed 32->32 weights into LDS.
+__device__ __forceinline__ void load_u(const float* __restrict__ u, float* __restrict__ s_u)
 {
-    const v4f* src = reinterpret_cast<const v4f*>(wsw);
-    v4f* dst = reinterpret_cast<v4f*>(s_w);
-    for (int k = threadIdx.x; k < WSW / 4; k += kThreads) dst[k] = src[k];
+    const v4f* src = reinterpret_cast<const v4f*>(u);
+    v4f* dst = reinterpret_cast<v4f*>(s_u);
+    for (int k = threadIdx.x; k < NU / 4; k += kThreads) dst[k] = src[k];
 }
 
 // Persistent tile loop.  Tiles (row-major) are split into 8 contiguous
@@ -147,11 +203,11 @@ struct TileIter {
 // conv1 + ReLU (matrix cores, into LDS) then conv2 + ReLU -> act2 [G][G][32].
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_conv12_f32(
     int32_t G, int tiles_x, int ntiles, const float* __restrict__ vel, const float* __restrict__ w1,
-    const float* __restrict__ b1, const float* __restrict__ wsw2, const float* __restrict__ b2,
+    const float* __restrict__ b1, const float* __restrict__ u2, const float* __restrict__ b2,
     float* __restrict__ act2)
 {
     __shared__ __attribute__((aligned(16))) float s_in[NIN * PS];
-    __shared__ __attribute__((aligned(16))) float s_w[WSW];
+    __shared__ __attribute__((aligned(16))) float s_u[NU];
     __shared__ float s_vel[2 * VH * VW];
     __shared__ float s_b2[C];
 
@@ -161,7 +217,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     TileIter it(ntiles);
     if (it.t >= it.end) return;
 
-    load_wsw(wsw2, s_w);
+    load_u(u2, s_u);
     if (tid < C) s_b2[tid] = b2[tid];
     // conv1 B operands: k-step s, slot q holds k = 4s + q = 9 ci + tap (zero for k >= 18)
     float bw1[5][2], bias1[2];
@@ -233,21 +289,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         const int next = it.t + it.step;
         if (next < it.end) fetch_vel(next);  // lands while conv2 runs
 
-        v4f acc[MB][2];
-        conv32_mfma(s_in, s_w, wave, lane, acc);
-        __syncthreads();  // s_in is reused for the output tile; s_vel is free
-
-        if (next < it.end) stash_vel();
+        // Two rounds of block rows, ty = wave and wave + 4.  The first round reads
+        // tile rows 0 .. 9 and the second rows 8 .. 17, so after the first round the
+        // outputs of region rows 0 .. 7 (output pixels 0 .. 255, pixel-major at
+        // stride PS) can overwrite tile rows 0 .. 7; the rest waits for the second.
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+        for (int round = 0; round < 2; ++round) {
+            float y[2][4][4];
+            conv32_wino(s_in, s_u, wave + 4 * round, lane, y);
+            __syncthreads();
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int o = nb * 16 + i;
-                    const int p = (4 * wave + (mb >> 1)) * RW + (mb & 1) * 16 + 4 * q + r;
-                    s_in[p * PS + o] = fmaxf(acc[mb][nb][r] + s_b2[o], 0.f);
-                }
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int o = nb * 16 + i;
+                        const int p = (2 * (wave + 4 * round) + (e >> 1)) * RW + 2 * (4 * q + r) + (e & 1);
+                        s_in[p * PS + o] = fmaxf(y[nb][r][e] + s_b2[o], 0.f);
+                    }
+        }
+        if (next < it.end) stash_vel();  // s_vel is free since the first round's barrier
         __syncthreads();
         for (int e = tid; e < NREG * (C / 4); e += kThreads) {
             const int p = e >> 3, part = e & 7;
@@ -262,12 +324,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 
 // conv3 + ReLU on the tile plus a one-pixel border (in LDS), then conv4 -> disp [2][G][G].
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_conv34_f32(
-    int32_t G, int tiles_x, int ntiles, const float* __restrict__ act2, const float* __restrict__ wsw3,
+    int32_t G, int tiles_x, int ntiles, const float* __restrict__ act2, const float* __restrict__ u3,
     const float* __restrict__ b3, const float* __restrict__ w4, const float* __restrict__ b4,
     float* __restrict__ disp)
 {
     __shared__ __attribute__((aligned(16))) float s_in[NIN * PS];
-    __shared__ __attribute__((aligned(16))) float s_w[WSW];
+    __shared__ __attribute__((aligned(16))) float s_u[NU];
     __shared__ __attribute__((aligned(16))) float s_w4[9 * 2 * C];  // [tap][out][in]
     __shared__ float s_b3[C], s_b4[2];
 
@@ -277,7 +339,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     TileIter it(ntiles);
     if (it.t >= it.end) return;
 
-    load_wsw(wsw3, s_w);
+    load_u(u3, s_u);
     for (int k = tid; k < 9 * 2 * C; k += kThreads) {
         const int t = k / (2 * C), o = (k / C) % 2, c = k % C;
         s_w4[k] = w4[(o * C + c) * 9 + t];
@@ -316,24 +378,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         const int y0 = ty0 - 1, x0 = tx0 - 1;                                      // conv3 region origin
 
         const int next = it.t + it.step;
-        if (next < it.end) fetch_act(next);  // lands while conv3 and conv4 run
 
-        v4f acc[MB][2];
-        conv32_mfma(s_in, s_w, wave, lane, acc);
-        __syncthreads();
-
+        // two rounds of block rows (see conv12): the first round's outputs overwrite
+        // tile rows 0 .. 7, which the second round no longer reads
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+        for (int round = 0; round < 2; ++round) {
+            float y[2][4][4];
+            conv32_wino(s_in, s_u, wave + 4 * round, lane, y);
+            __syncthreads();
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int o = nb * 16 + i;
-                    const int row = 4 * wave + (mb >> 1), col = (mb & 1) * 16 + 4 * q + r;
-                    const int gy = y0 + row, gx = x0 + col;
-                    const bool in = gy >= 0 && gy < G && gx >= 0 && gx < G;  // conv4's zero padding
-                    s_in[(row * RW + col) * PS + o] = in ? fmaxf(acc[mb][nb][r] + s_b3[o], 0.f) : 0.f;
-                }
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int o = nb * 16 + i;
+                        const int row = 2 * (wave + 4 * round) + (e >> 1), col = 2 * (4 * q + r) + (e & 1);
+                        const int gy = y0 + row, gx = x0 + col;
+                        const bool in = gy >= 0 && gy < G && gx >= 0 && gx < G;  // conv4's zero padding
+                        s_in[(row * RW + col) * PS + o] = in ? fmaxf(y[nb][r][e] + s_b3[o], 0.f) : 0.f;
+                    }
+        }
+        if (next < it.end) fetch_act(next);  // lands while conv4 runs
         __syncthreads();
 
         {
@@ -405,7 +471,7 @@ unsigned cnn_persistent_grid()
 size_t cnn_workspace_bytes(int32_t G, int32_t precision)
 {
     if (precision == CNNSNS_BF16) return cnn_bf16_workspace_bytes();
-    return sizeof(float) * (2 * (size_t)WSW + (size_t)C * (size_t)G * (size_t)G);
+    return sizeof(float) * (2 * (size_t)NU + (size_t)C * (size_t)G * (size_t)G);
 }
 
 void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp, void* ws,
@@ -417,15 +483,15 @@ void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision
         return;
     }
     if (precision != CNNSNS_F32) fail(CNNSNS_EINVAL, "predict: FP8 is not available in this build");
-    float* wsw2 = static_cast<float*>(ws);
-    float* wsw3 = wsw2 + WSW;
-    float* act2 = wsw3 + WSW;
-    k_swizzle32<<<cdiv(WSW, 256), 256, 0, stream>>>(w.w[1], wsw2);
-    k_swizzle32<<<cdiv(WSW, 256), 256, 0, stream>>>(w.w[2], wsw3);
+    float* u2 = static_cast<float*>(ws);
+    float* u3 = u2 + NU;
+    float* act2 = u3 + NU;
+    k_wino_weights<<<cdiv(NU, 256), 256, 0, stream>>>(w.w[1], u2);
+    k_wino_weights<<<cdiv(NU, 256), 256, 0, stream>>>(w.w[2], u3);
     const int tx12 = (int)cdiv(G, RW), n12 = tx12 * (int)cdiv(G, RH);
     const int tx34 = (int)cdiv(G, OW34), n34 = tx34 * (int)cdiv(G, OH34);
-    k_conv12_f32<<<persistent_grid(n12), kThreads, 0, stream>>>(G, tx12, n12, vel, w.w[0], w.b[0], wsw2, w.b[1], act2);
-    k_conv34_f32<<<persistent_grid(n34), kThreads, 0, stream>>>(G, tx34, n34, act2, wsw3, w.b[2], w.w[3], w.b[3],
+    k_conv12_f32<<<persistent_grid(n12), kThreads, 0, stream>>>(G, tx12, n12, vel, w.w[0], w.b[0], u2, w.b[1], act2);
+    k_conv34_f32<<<persistent_grid(n34), kThreads, 0, stream>>>(G, tx34, n34, act2, u3, w.b[2], w.w[3], w.b[3],
                                                                disp);
     hip_check(hipGetLastError(), "predict launch");
 }

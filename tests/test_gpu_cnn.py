@@ -63,14 +63,18 @@ def test_cnn_f32_full_grid(C, oracle_mod, wl, G, seed):
 
 
 def test_cnn_constructed_weights_exact(C, oracle_mod, wl):
-    """Pass-through weights: the net computes -dt u, every product exact; GPU = FP32 rounding of the oracle."""
+    """Pass-through weights: the net computes -dt u with every direct product exact.  The 32 -> 32
+    layers run as Winograd F(2x2, 3x3), whose transforms add and subtract, so each output may carry
+    a few FP32 roundings: within 2^-20 of the channel maximum plus 2^-22 relative (about 1e-6,
+    ten times tighter than the FP32 bar)."""
     from test_oracle_lookup_cnn import constructed_weights
     w = wl.build("c1")
     ws, bs = constructed_weights(w.dt)
     mesh = C.Mesh(w.xy, w.tri, overlay_side=w.G)
-    disp = C.predict(mesh, _dev(w.vel), C.Weights(ws, bs), "f32")
+    disp = C.predict(mesh, _dev(w.vel), C.Weights(ws, bs), "f32").cpu().numpy().astype(np.float64)
     ref = oracle_mod.cnn_forward(w.vel, ws, bs)
-    assert np.array_equal(disp.cpu().numpy(), ref.astype(np.float32))
+    scale = np.abs(ref).reshape(2, -1).max(axis=1)[:, None, None]
+    assert np.all(np.abs(disp - ref) <= 2.0 ** -20 * scale + 2.0 ** -22 * np.abs(ref))
 
 
 @pytest.mark.parametrize("name,nsample", [("c2", 3000), ("c3", 1500)])
