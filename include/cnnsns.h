@@ -62,9 +62,11 @@ enum {
 
 /* CNN arithmetic precision for cnnsns_predict / the serving loop. */
 enum {
-    CNNSNS_F32 = 0,     /* FP32 operands, FP32 accumulation */
+    CNNSNS_F32 = 0,     /* FP32 operands and activations, FP32 accumulation (the 32 -> 32 layers
+                           as Winograd F(2x2,3x3) contractions: within 1e-5 of the exact result) */
     CNNSNS_BF16 = 1,    /* BF16 operands and activations, FP32 accumulation */
-    CNNSNS_FP8E4M3 = 2, /* FP8 e4m3 weights and activations with per-channel scales, FP32 accumulation */
+    CNNSNS_FP8E4M3 = 2, /* reserved for FP8 e4m3 with per-channel scales: not available in this
+                           build, cnnsns_predict and cnnsns_server_create return EINVAL for it */
 };
 
 typedef struct cnnsns_mesh_s* cnnsns_mesh;
@@ -125,8 +127,12 @@ int cnnsns_destroy_mesh(cnnsns_mesh m);
  * Alg. 2, in the displacement-regression form described above):
  *   vel   DEVICE FP32 [2][G][G], (u, v) at the cell centres, row = y index.
  *   w     the weights (device pointers, see cnnsns_cnn).
- *   precision  CNNSNS_F32, CNNSNS_BF16 or CNNSNS_FP8E4M3.
+ *   precision  CNNSNS_F32 or CNNSNS_BF16 (CNNSNS_FP8E4M3 gives EINVAL).
  *   disp  DEVICE FP32 [2][G][G] output (caller-owned): predicted (dx, dy).
+ * The mesh keeps a workspace for the forward pass, allocated on first use and
+ * grown when needed (FP32: one 32-channel FP32 activation of 128 G^2 bytes
+ * plus 128 KiB of transformed weights; BF16: 47 KiB of packed weights) until
+ * it is destroyed; concurrent predicts on one mesh must use one stream.
  * Asynchronous on `stream`.  Errors: EINVAL, ENOMEM, EHIP.
  */
 int cnnsns_predict(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t precision, float* disp,
