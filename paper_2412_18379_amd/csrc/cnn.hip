@@ -11,8 +11,10 @@
 //           16 x 32 tile plus a one-pixel border, then conv2; writes the
 //           32-channel activation, pixel-major ([G][G][32]).
 //   conv34: conv3 on a 16 x 32 region (the 14 x 30 output tile plus a
-//           one-pixel border), kept in LDS, then conv4 (N = 2) on the vector
-//           ALU; writes the 2-channel displacement.
+//           one-pixel border), kept in LDS, then conv4 (N = 2): per region
+//           pixel, its 18 (output channel, tap) contributions on the matrix
+//           cores, then a 9-term sum per output pixel; writes the 2-channel
+//           displacement.
 // The two 32 -> 32 layers use the Winograd minimal filtering algorithm
 // F(2x2, 3x3) (Lavin and Gray, 2016): per 2 x 2 output block and channel
 // pair, 16 products in a transformed domain replace 36 direct ones, so the
@@ -45,6 +47,7 @@ constexpr int VEL_PER_THREAD = (2 * VH * VW + kThreads - 1) / kThreads;
 constexpr int CHUNKS = NIN * C / 4;      // float4 chunks of an input tile
 constexpr int CHUNKS_PER_THREAD = (CHUNKS + kThreads - 1) / kThreads;
 constexpr int L1_MBLOCKS = (NIN + 15) / 16;
+constexpr int NIN_PAD = L1_MBLOCKS * 16;     // conv1's 39 M-blocks write whole blocks
 
 static_assert(NU == 16 * C * C, "transformed weights cover the whole layer");
 static_assert(NREG * PS <= NIN * PS, "output tile aliases the input tile");
@@ -95,24 +98,46 @@ __device__ __forceinline__ void wino_patch(const float* __restrict__ s_in, int t
             d[a][b] = *reinterpret_cast<const v4f*>(s_in + ((2 * ty + a) * IW + 2 * tx + b) * PS + 8 * g + 4 * h);
 }
 
-// d <- B^T d B, in place (four channels at once).
+// d <- B^T d B, in place (four channels at once), in four parts: the row
+// pass over columns 2 part, 2 part + 1 (parts 0, 1), then the column pass over
+// rows 2 (part - 2), 2 (part - 2) + 1 (parts 2, 3).
+__device__ __forceinline__ void wino_input_transform_part(v4f (&d)[4][4], int part)
+{
+    if (part < 2) {
+#pragma unroll
+        for (int b = 2 * part; b < 2 * part + 2; ++b) {
+            const v4f t0 = d[0][b] - d[2][b], t1 = d[1][b] + d[2][b], t2 = d[2][b] - d[1][b], t3 = d[1][b] - d[3][b];
+            d[0][b] = t0;
+            d[1][b] = t1;
+            d[2][b] = t2;
+            d[3][b] = t3;
+        }
+    } else {
+#pragma unroll
+        for (int a = 2 * (part - 2); a < 2 * (part - 2) + 2; ++a) {
+            const v4f t0 = d[a][0] - d[a][2], t1 = d[a][1] + d[a][2], t2 = d[a][2] - d[a][1], t3 = d[a][1] - d[a][3];
+            d[a][0] = t0;
+            d[a][1] = t1;
+            d[a][2] = t2;
+            d[a][3] = t3;
+        }
+    }
+}
+
 __device__ __forceinline__ void wino_input_transform(v4f (&d)[4][4])
 {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const v4f t0 = d[0][b] - d[2][b], t1 = d[1][b] + d[2][b], t2 = d[2][b] - d[1][b], t3 = d[1][b] - d[3][b];
-        d[0][b] = t0;
-        d[1][b] = t1;
-        d[2][b] = t2;
-        d[3][b] = t3;
-    }
+    for (int part = 0; part < 4; ++part) wino_input_transform_part(d, part);
+}
+
+// B operands of four transformed positions (xn = 4 grp .. 4 grp + 3) for
+// channel half h: b[x][nb][j] = U[4 grp + x][16 nb + l%16][8 (l/16) + 4h + j].
+__device__ __forceinline__ void wino_weights(const v4f* __restrict__ su, int grp, int h, v4f (&b)[4][2])
+{
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const v4f t0 = d[a][0] - d[a][2], t1 = d[a][1] + d[a][2], t2 = d[a][2] - d[a][1], t3 = d[a][1] - d[a][3];
-        d[a][0] = t0;
-        d[a][1] = t1;
-        d[a][2] = t2;
-        d[a][3] = t3;
+    for (int x = 0; x < 4; ++x) {
+        b[x][0] = su[(((4 * grp + x) * 2 + 0) * 2 + h) * 64];
+        b[x][1] = su[(((4 * grp + x) * 2 + 1) * 2 + h) * 64];
     }
 }
 
@@ -121,6 +146,15 @@ __device__ __forceinline__ void wino_input_transform(v4f (&d)[4][4])
 // 32-channel input on the 18 x 34 tile around the region, s_u the transformed
 // weights.  Result y[nb][r][2a + b]: region pixel (2 ty + a, 2 (4 (l/16) + r) + b),
 // output channel 16 nb + l%16.
+//
+// The contraction runs in 8 groups (2 channel halves x 4 groups of 4
+// transformed positions), 32 matrix instructions each, with 8 independent
+// accumulators between two updates of one.  Every LDS read is issued one group
+// ahead of its use (the next group's weights, and during the first group the
+// second half's input patch; scheduling barriers keep the compiler from
+// sinking them), and the second half's input transform is spread between the
+// matrix instructions of the fourth group, so a single wave per SIMD keeps the
+// matrix core fed.
 __device__ __forceinline__ void conv32_wino(const float* __restrict__ s_in, const float* __restrict__ s_u, int ty,
                                             int lane, float (&y)[2][4][4])
 {
@@ -132,30 +166,46 @@ __device__ __forceinline__ void conv32_wino(const float* __restrict__ s_in, cons
         acc[xn][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
         acc[xn][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
     }
+    v4f d[4][4], dn[4][4], bc[4][2], bn[4][2];
+    wino_patch(s_in, ty, tx, g, 0, d);
+    wino_weights(su, 0, 0, bc);
+    wino_input_transform(d);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        v4f d[4][4];
-        wino_patch(s_in, ty, tx, g, h, d);
-        wino_input_transform(d);
-        // four transformed positions at a time: 8 independent accumulators between
-        // two updates of the same one, and the next group's weights read meanwhile
 #pragma unroll
         for (int grp = 0; grp < 4; ++grp) {
-            v4f b[4][2];
+            const bool last = h == 1 && grp == 3;
+            if (!last) wino_weights(su, (grp + 1) & 3, grp == 3 ? h + 1 : h, bn);
+            if (h == 0 && grp == 0) wino_patch(s_in, ty, tx, g, 1, dn);
+            // keep these reads a whole group ahead of their use
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                b[x][0] = su[(((4 * grp + x) * 2 + 0) * 2 + h) * 64];
-                b[x][1] = su[(((4 * grp + x) * 2 + 1) * 2 + h) * 64];
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j) {
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
                     const int xn = 4 * grp + x;
                     const float a = d[xn >> 2][xn & 3][j];
-                    acc[xn][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[x][0][j], acc[xn][0], 0, 0, 0);
-                    acc[xn][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[x][1][j], acc[xn][1], 0, 0, 0);
+                    acc[xn][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bc[x][0][j], acc[xn][0], 0, 0, 0);
+                    acc[xn][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bc[x][1][j], acc[xn][1], 0, 0, 0);
                 }
+                if (h == 0 && grp == 3) {
+                    // the second half's input transform, between the matrix instructions
+                    __builtin_amdgcn_sched_barrier(0);
+                    wino_input_transform_part(dn, j);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                bc[x][0] = bn[x][0];
+                bc[x][1] = bn[x][1];
+            }
+        }
+        if (h == 0) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) d[a][b] = dn[a][b];
         }
     }
     // Y = A^T M A for each of the lane's 4 blocks and 2 output channels
@@ -206,7 +256,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     const float* __restrict__ b1, const float* __restrict__ u2, const float* __restrict__ b2,
     float* __restrict__ act2)
 {
-    __shared__ __attribute__((aligned(16))) float s_in[NIN * PS];
+    __shared__ __attribute__((aligned(16))) float s_in[NIN_PAD * PS];
     __shared__ __attribute__((aligned(16))) float s_u[NU];
     __shared__ float s_vel[2 * VH * VW];
     __shared__ float s_b2[C];
@@ -230,6 +280,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         }
     bias1[0] = b1[i];
     bias1[1] = b1[16 + i];
+    // conv1 A operands: k-step s of lane (i, q) reads s_vel at the pixel's base plus a
+    // per-lane constant offset (channel k / 9, tap k % 9); slots k >= 18 read the pixel
+    // itself and are zeroed by a select
+    int l1_off[5];
+    bool l1_on[5];
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+        const int k = 4 * s + q, t = k % 9;
+        l1_on[s] = k < 18;
+        l1_off[s] = k < 18 ? (k / 9) * VH * VW + (t / 3) * VW + t % 3 : VW + 1;
+    }
 
     float pv[VEL_PER_THREAD];
     auto fetch_vel = [&](int t) {
@@ -263,24 +324,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         // conv1 on the 18 x 34 input tile of conv2; zero outside the grid (conv2's padding)
         for (int mb = wave; mb < L1_MBLOCKS; mb += kWaves) {
             const int p = min(mb * 16 + i, NIN - 1);
-            const int py = p / IW, px = p % IW;
+            const int py = p / IW, base = py * VW + (p - py * IW);
             v4f d0 = v4f{ 0.f, 0.f, 0.f, 0.f }, d1 = d0;
 #pragma unroll
             for (int s = 0; s < 5; ++s) {
-                const int k = 4 * s + q;
-                const int ci = k / 9, t = k % 9;
-                const float a = k < 18 ? s_vel[ci * VH * VW + (py + t / 3) * VW + px + t % 3] : 0.f;
+                const float v = s_vel[base + l1_off[s]];
+                const float a = l1_on[s] ? v : 0.f;
                 d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw1[s][0], d0, 0, 0, 0);
                 d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw1[s][1], d1, 0, 0, 0);
             }
+            // result rows 4q .. 4q+3 of the block: tile pixels pp0 .. pp0+3 (the last block's
+            // pixels past the tile land in the padding of s_in)
+            const int pp0 = mb * 16 + 4 * q;
+            int oy = pp0 / IW, ox = pp0 - oy * IW;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int pp = mb * 16 + 4 * q + r;
-                if (pp < NIN) {
-                    const int gy = y0 - 1 + pp / IW, gx = x0 - 1 + pp % IW;
-                    const bool in = gy >= 0 && gy < G && gx >= 0 && gx < G;
-                    s_in[pp * PS + i] = in ? fmaxf(d0[r] + bias1[0], 0.f) : 0.f;
-                    s_in[pp * PS + 16 + i] = in ? fmaxf(d1[r] + bias1[1], 0.f) : 0.f;
+                const int gy = y0 - 1 + oy, gx = x0 - 1 + ox;
+                const bool in = (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G;
+                s_in[(pp0 + r) * PS + i] = in ? fmaxf(d0[r] + bias1[0], 0.f) : 0.f;
+                s_in[(pp0 + r) * PS + 16 + i] = in ? fmaxf(d1[r] + bias1[1], 0.f) : 0.f;
+                if (++ox == IW) {
+                    ox = 0;
+                    ++oy;
                 }
             }
         }
@@ -330,8 +395,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 {
     __shared__ __attribute__((aligned(16))) float s_in[NIN * PS];
     __shared__ __attribute__((aligned(16))) float s_u[NU];
-    __shared__ __attribute__((aligned(16))) float s_w4[9 * 2 * C];  // [tap][out][in]
-    __shared__ float s_b3[C], s_b4[2];
+    __shared__ float s_b3[C];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, q = lane >> 4;
     const int64_t GG = (int64_t)G * G;
@@ -340,12 +404,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     if (it.t >= it.end) return;
 
     load_u(u3, s_u);
-    for (int k = tid; k < 9 * 2 * C; k += kThreads) {
-        const int t = k / (2 * C), o = (k / C) % 2, c = k % C;
-        s_w4[k] = w4[(o * C + c) * 9 + t];
-    }
     if (tid < C) s_b3[tid] = b3[tid];
-    if (tid < 2) s_b4[tid] = b4[tid];
+    // conv4 B operands: k-step s of lane (i, q) is channel 8q + s; column n = 16 nb + i is
+    // (output channel n / 9, tap n % 9) for n < 18, zero beyond
+    float bw4[8][2];
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            const int n = 16 * nb + i, c = 8 * q + s;
+            bw4[s][nb] = n < 18 ? w4[((n / 9) * C + c) * 9 + n % 9] : 0.f;
+        }
+    const float bias4[2] = { b4[0], b4[1] };
 
     // next tile's input, as float4 chunks (8 per pixel) of the 18 x 34 tile
     v4f pa[CHUNKS_PER_THREAD];
@@ -353,7 +423,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         const int y0 = (t / tiles_x) * OH34 - 1, x0 = (t % tiles_x) * OW34 - 1;  // conv3 region origin
 #pragma unroll
         for (int k = 0; k < CHUNKS_PER_THREAD; ++k) {
-            const int e = tid + k * kThreads;
+            // an empty asm keeps the compiler from precomputing all 20 (row, column)
+            // pairs outside the tile loop, which would hold 40 registers throughout
+            int e = tid + k * kThreads;
+            asm volatile("" : "+v"(e));
             const int p = e >> 3, part = e & 7;
             const int gy = y0 - 1 + p / IW, gx = x0 - 1 + p % IW;
             v4f v = v4f{ 0.f, 0.f, 0.f, 0.f };
@@ -402,38 +475,42 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         if (next < it.end) fetch_act(next);  // lands while conv4 runs
         __syncthreads();
 
-        {
-            // conv4: thread tid takes output pixels tid and tid + kThreads of the 14 x 30 tile;
-            // each weight read from LDS serves both
-            static_assert(OH34 * OW34 <= 2 * kThreads, "two conv4 pixels per thread");
-            const int e0 = tid, e1 = min(tid + kThreads, OH34 * OW34 - 1);
-            const int oy0 = e0 / OW34, ox0 = e0 % OW34, oy1 = e1 / OW34, ox1 = e1 % OW34;
-            float d00 = s_b4[0], d01 = s_b4[1], d10 = s_b4[0], d11 = s_b4[1];
-#pragma unroll 1
+        // conv4 as a contraction on the matrix cores: for every region pixel p,
+        // Z[p][9 o + t] = sum_c act3[p][c] w4[o][c][t] (32 blocks of 16 pixels, 8 per
+        // wave), written over the pixel's own channels: a block's pixels are read
+        // only by the wave that computes the block, before its results exist.
+        for (int mb = wave; mb < NREG / 16; mb += kWaves) {
+            const float* px = s_in + (mb * 16 + i) * PS + 8 * q;
+            const v4f a0 = *reinterpret_cast<const v4f*>(px), a1 = *reinterpret_cast<const v4f*>(px + 4);
+            v4f z0 = v4f{ 0.f, 0.f, 0.f, 0.f }, z1 = z0;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const float a = s < 4 ? a0[s] : a1[s - 4];
+                z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw4[s][0], z0, 0, 0, 0);
+                z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw4[s][1], z1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float* zp = s_in + (mb * 16 + 4 * q + r) * PS;
+                zp[i] = z0[r];
+                if (i < 2) zp[16 + i] = z1[r];
+            }
+        }
+        __syncthreads();
+        // then each output pixel sums its 9 taps: disp[o] = b4[o] + sum_t Z[pixel + tap t][9 o + t]
+        for (int e = tid; e < OH34 * OW34; e += kThreads) {
+            const int oy = e / OW34, ox = e - oy * OW34;
+            float d0 = bias4[0], d1 = bias4[1];
+#pragma unroll
             for (int t = 0; t < 9; ++t) {
-                const v4f* p0 = reinterpret_cast<const v4f*>(s_in + ((oy0 + t / 3) * RW + ox0 + t % 3) * PS);
-                const v4f* p1 = reinterpret_cast<const v4f*>(s_in + ((oy1 + t / 3) * RW + ox1 + t % 3) * PS);
-                const v4f* wt = reinterpret_cast<const v4f*>(s_w4 + t * 2 * C);  // wave-uniform: broadcast
-#pragma unroll
-                for (int part = 0; part < C / 4; ++part) {
-                    const v4f x0 = p0[part], x1 = p1[part], u0 = wt[part], u1 = wt[C / 4 + part];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        d00 += u0[j] * x0[j];
-                        d01 += u1[j] * x0[j];
-                        d10 += u0[j] * x1[j];
-                        d11 += u1[j] * x1[j];
-                    }
-                }
+                const float* zp = s_in + ((oy + t / 3) * RW + ox + t % 3) * PS;
+                d0 += zp[t];
+                d1 += zp[9 + t];
             }
-            const int gy0 = ty0 + oy0, gx0 = tx0 + ox0, gy1 = ty0 + oy1, gx1 = tx0 + ox1;
-            if (gy0 < G && gx0 < G) {
-                disp[(int64_t)gy0 * G + gx0] = d00;
-                disp[GG + (int64_t)gy0 * G + gx0] = d01;
-            }
-            if (tid + kThreads < OH34 * OW34 && gy1 < G && gx1 < G) {
-                disp[(int64_t)gy1 * G + gx1] = d10;
-                disp[GG + (int64_t)gy1 * G + gx1] = d11;
+            const int gy = ty0 + oy, gx = tx0 + ox;
+            if (gy < G && gx < G) {
+                disp[(int64_t)gy * G + gx] = d0;
+                disp[GG + (int64_t)gy * G + gx] = d1;
             }
         }
         __syncthreads();
