@@ -131,7 +131,7 @@ int cnnsns_destroy_mesh(cnnsns_mesh m);
  *   disp  DEVICE FP32 [2][G][G] output (caller-owned): predicted (dx, dy).
  * The mesh keeps a workspace for the forward pass, allocated on first use and
  * grown when needed (FP32: one 32-channel FP32 activation of 128 G^2 bytes
- * plus 128 KiB of transformed weights; BF16: 47 KiB of packed weights) until
+ * plus 128 KiB of transformed weights; BF16: 40 KiB of packed weights) until
  * it is destroyed; concurrent predicts on one mesh must use one stream.
  * Asynchronous on `stream`.  Errors: EINVAL, ENOMEM, EHIP.
  */

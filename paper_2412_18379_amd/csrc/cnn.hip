@@ -64,12 +64,16 @@ static_assert(RW == 32, "a row of 2 x 2 output blocks is one 16-row matrix block
 // (xi, nu) form a contraction M[xi][nu] = U[xi][nu] V[xi][nu] over channels,
 // U = G g G^T per (output, input) channel pair.
 //
-// Matrix-core operand order (v_mfma_f32_16x16x4f32): the 16 blocks of a
-// matrix row are the 16 output blocks of one block row; lane l holds block
-// l%16 and input channel 8 (l/16) + 4h + j in k-step j of channel half h.
+// Matrix-core operand order (v_mfma_f32_16x16x4f32, D = A B with A the
+// weights and B the transformed inputs): A row = output channel, B column =
+// one of the 16 output blocks of a block row, k = input channel.  Lane l
+// supplies output channel 16 nb + l%16 (A) and block l%16 (B), both for input
+// channel 8 (l/16) + 4h + j in k-step j of channel half h, and receives
+// output channels 16 nb + 4 (l/16) + r (r = 0..3) of block l%16, four
+// consecutive channels of one block.
 // u[(((xn * 2 + nb) * 2 + h) * 64 + l) * 4 + j] holds
 //   U[xn = 4 xi + nu][output channel 16 nb + l%16][input channel 8 (l/16) + 4h + j],
-// so a lane reads the B operands of four k-steps as one float4.
+// so a lane reads the A operands of four k-steps as one float4.
 __global__ void k_wino_weights(const float* __restrict__ w, float* __restrict__ u)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -130,7 +134,7 @@ __device__ __forceinline__ void wino_input_transform(v4f (&d)[4][4])
     for (int part = 0; part < 4; ++part) wino_input_transform_part(d, part);
 }
 
-// B operands of four transformed positions (xn = 4 grp .. 4 grp + 3) for
+// Weight operands of four transformed positions (xn = 4 grp .. 4 grp + 3) for
 // channel half h: b[x][nb][j] = U[4 grp + x][16 nb + l%16][8 (l/16) + 4h + j].
 __device__ __forceinline__ void wino_weights(const v4f* __restrict__ su, int grp, int h, v4f (&b)[4][2])
 {
@@ -144,8 +148,8 @@ __device__ __forceinline__ void wino_weights(const v4f* __restrict__ su, int grp
 // conv 32 -> 32 (no bias) for one row of 2 x 2 output blocks of the block's
 // 16 x 32 region: block row ty, region rows 2 ty and 2 ty + 1.  s_in holds the
 // 32-channel input on the 18 x 34 tile around the region, s_u the transformed
-// weights.  Result y[nb][r][2a + b]: region pixel (2 ty + a, 2 (4 (l/16) + r) + b),
-// output channel 16 nb + l%16.
+// weights.  Result y[e][nb][r], e = 2a + b: region pixel (2 ty + a, 2 (l%16) + b),
+// output channel 16 nb + 4 (l/16) + r.
 //
 // The contraction runs in 8 groups (2 channel halves x 4 groups of 4
 // transformed positions), 32 matrix instructions each, with 8 independent
@@ -156,7 +160,7 @@ __device__ __forceinline__ void wino_weights(const v4f* __restrict__ su, int grp
 // matrix instructions of the fourth group, so a single wave per SIMD keeps the
 // matrix core fed.
 __device__ __forceinline__ void conv32_wino(const float* __restrict__ s_in, const float* __restrict__ s_u, int ty,
-                                            int lane, float (&y)[2][4][4])
+                                            int lane, v4f (&y)[4][2])
 {
     const int tx = lane & 15, g = lane >> 4;
     const v4f* su = reinterpret_cast<const v4f*>(s_u) + lane;
@@ -185,8 +189,8 @@ __device__ __forceinline__ void conv32_wino(const float* __restrict__ s_in, cons
                 for (int x = 0; x < 4; ++x) {
                     const int xn = 4 * grp + x;
                     const float a = d[xn >> 2][xn & 3][j];
-                    acc[xn][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bc[x][0][j], acc[xn][0], 0, 0, 0);
-                    acc[xn][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bc[x][1][j], acc[xn][1], 0, 0, 0);
+                    acc[xn][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][0][j], a, acc[xn][0], 0, 0, 0);
+                    acc[xn][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][1][j], a, acc[xn][1], 0, 0, 0);
                 }
                 if (h == 0 && grp == 3) {
                     // the second half's input transform, between the matrix instructions
@@ -208,22 +212,20 @@ __device__ __forceinline__ void conv32_wino(const float* __restrict__ s_in, cons
                 for (int b = 0; b < 4; ++b) d[a][b] = dn[a][b];
         }
     }
-    // Y = A^T M A for each of the lane's 4 blocks and 2 output channels
+    // Y = A^T M A for the lane's block and 8 output channels (4 at a time)
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+    for (int nb = 0; nb < 2; ++nb) {
+        v4f m0[4], m1[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            float m0[4], m1[4];
-#pragma unroll
-            for (int nu = 0; nu < 4; ++nu) {
-                m0[nu] = acc[nu][nb][r] + acc[4 + nu][nb][r] + acc[8 + nu][nb][r];
-                m1[nu] = acc[4 + nu][nb][r] - acc[8 + nu][nb][r] - acc[12 + nu][nb][r];
-            }
-            y[nb][r][0] = m0[0] + m0[1] + m0[2];
-            y[nb][r][1] = m0[1] - m0[2] - m0[3];
-            y[nb][r][2] = m1[0] + m1[1] + m1[2];
-            y[nb][r][3] = m1[1] - m1[2] - m1[3];
+        for (int nu = 0; nu < 4; ++nu) {
+            m0[nu] = acc[nu][nb] + acc[4 + nu][nb] + acc[8 + nu][nb];
+            m1[nu] = acc[4 + nu][nb] - acc[8 + nu][nb] - acc[12 + nu][nb];
         }
+        y[0][nb] = m0[0] + m0[1] + m0[2];
+        y[1][nb] = m0[1] - m0[2] - m0[3];
+        y[2][nb] = m1[0] + m1[1] + m1[2];
+        y[3][nb] = m1[1] - m1[2] - m1[3];
+    }
 }
 
 // Block loads of the transformed 32->32 weights into LDS.
@@ -259,7 +261,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     __shared__ __attribute__((aligned(16))) float s_in[NIN_PAD * PS];
     __shared__ __attribute__((aligned(16))) float s_u[NU];
     __shared__ float s_vel[2 * VH * VW];
-    __shared__ float s_b2[C];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, q = lane >> 4;
     const int64_t GG = (int64_t)G * G;
@@ -268,7 +269,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     if (it.t >= it.end) return;
 
     load_u(u2, s_u);
-    if (tid < C) s_b2[tid] = b2[tid];
+    // conv2 biases of the lane's output channels 16 nb + 4q + r
+    v4f bias2[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bias2[nb][r] = b2[16 * nb + 4 * q + r];
     // conv1 B operands: k-step s, slot q holds k = 4s + q = 9 ci + tap (zero for k >= 18)
     float bw1[5][2], bias1[2];
 #pragma unroll
@@ -321,20 +327,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     for (; it.t < it.end; it.t += it.step) {
         const int y0 = (it.t / tiles_x) * RH, x0 = (it.t % tiles_x) * RW;
 
-        // conv1 on the 18 x 34 input tile of conv2; zero outside the grid (conv2's padding)
-        for (int mb = wave; mb < L1_MBLOCKS; mb += kWaves) {
+        // conv1 on the 18 x 34 input tile of conv2; zero outside the grid (conv2's padding).
+        // Two 16-pixel blocks at a time (four independent accumulation chains).
+        auto conv1_block = [&](int mb, v4f& d0, v4f& d1) {
             const int p = min(mb * 16 + i, NIN - 1);
             const int py = p / IW, base = py * VW + (p - py * IW);
-            v4f d0 = v4f{ 0.f, 0.f, 0.f, 0.f }, d1 = d0;
+            float a[5];
 #pragma unroll
             for (int s = 0; s < 5; ++s) {
                 const float v = s_vel[base + l1_off[s]];
-                const float a = l1_on[s] ? v : 0.f;
-                d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw1[s][0], d0, 0, 0, 0);
-                d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw1[s][1], d1, 0, 0, 0);
+                a[s] = l1_on[s] ? v : 0.f;
             }
-            // result rows 4q .. 4q+3 of the block: tile pixels pp0 .. pp0+3 (the last block's
-            // pixels past the tile land in the padding of s_in)
+            d0 = v4f{ 0.f, 0.f, 0.f, 0.f };
+            d1 = d0;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bw1[s][0], d0, 0, 0, 0);
+                d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bw1[s][1], d1, 0, 0, 0);
+            }
+        };
+        // result rows 4q .. 4q+3 of a block: tile pixels pp0 .. pp0+3 (the last block's
+        // pixels past the tile land in the padding of s_in)
+        auto conv1_store = [&](int mb, const v4f& d0, const v4f& d1) {
             const int pp0 = mb * 16 + 4 * q;
             int oy = pp0 / IW, ox = pp0 - oy * IW;
 #pragma unroll
@@ -348,6 +362,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
                     ++oy;
                 }
             }
+        };
+        for (int mb = wave; mb < L1_MBLOCKS; mb += 2 * kWaves) {
+            const bool two = mb + kWaves < L1_MBLOCKS;  // wave-uniform
+            v4f d00, d01, d10, d11;
+            conv1_block(mb, d00, d01);
+            conv1_block(two ? mb + kWaves : mb, d10, d11);
+            conv1_store(mb, d00, d01);
+            if (two) conv1_store(mb + kWaves, d10, d11);
         }
         __syncthreads();
 
@@ -360,19 +382,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         // stride PS) can overwrite tile rows 0 .. 7; the rest waits for the second.
 #pragma unroll
         for (int round = 0; round < 2; ++round) {
-            float y[2][4][4];
+            v4f y[4][2];
             conv32_wino(s_in, s_u, wave + 4 * round, lane, y);
             __syncthreads();
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
+            for (int e = 0; e < 4; ++e) {
+                const int p = (2 * (wave + 4 * round) + (e >> 1)) * RW + 2 * i + (e & 1);
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int nb = 0; nb < 2; ++nb) {
+                    v4f v = y[e][nb] + bias2[nb];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int o = nb * 16 + i;
-                        const int p = (2 * (wave + 4 * round) + (e >> 1)) * RW + 2 * (4 * q + r) + (e & 1);
-                        s_in[p * PS + o] = fmaxf(y[nb][r][e] + s_b2[o], 0.f);
-                    }
+                    for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
+                    *reinterpret_cast<v4f*>(s_in + p * PS + 16 * nb + 4 * q) = v;
+                }
+            }
         }
         if (next < it.end) stash_vel();  // s_vel is free since the first round's barrier
         __syncthreads();
@@ -395,7 +418,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 {
     __shared__ __attribute__((aligned(16))) float s_in[NIN * PS];
     __shared__ __attribute__((aligned(16))) float s_u[NU];
-    __shared__ float s_b3[C];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, q = lane >> 4;
     const int64_t GG = (int64_t)G * G;
@@ -404,7 +426,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     if (it.t >= it.end) return;
 
     load_u(u3, s_u);
-    if (tid < C) s_b3[tid] = b3[tid];
+    // conv3 biases of the lane's output channels 16 nb + 4q + r
+    v4f bias3[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bias3[nb][r] = b3[16 * nb + 4 * q + r];
     // conv4 B operands: k-step s of lane (i, q) is channel 8q + s; column n = 16 nb + i is
     // (output channel n / 9, tap n % 9) for n < 18, zero beyond
     float bw4[8][2];
@@ -421,18 +448,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     v4f pa[CHUNKS_PER_THREAD];
     auto fetch_act = [&](int t) {
         const int y0 = (t / tiles_x) * OH34 - 1, x0 = (t % tiles_x) * OW34 - 1;  // conv3 region origin
+        // chunk e = tid + 256 k is pixel (tid >> 3) + 32 k, channels 4 (tid & 7) .. +3; the
+        // pixel's (row, column) in the 18 x 34 tile advance by 32 columns per k.  The empty
+        // asm keeps the compiler from precomputing all 20 positions outside the tile loop.
+        int row = 0, col = tid >> 3;
+        asm volatile("" : "+v"(col));
+        const int part = tid & 7;
 #pragma unroll
         for (int k = 0; k < CHUNKS_PER_THREAD; ++k) {
-            // an empty asm keeps the compiler from precomputing all 20 (row, column)
-            // pairs outside the tile loop, which would hold 40 registers throughout
-            int e = tid + k * kThreads;
-            asm volatile("" : "+v"(e));
-            const int p = e >> 3, part = e & 7;
-            const int gy = y0 - 1 + p / IW, gx = x0 - 1 + p % IW;
+            const int gy = y0 - 1 + row, gx = x0 - 1 + col;
             v4f v = v4f{ 0.f, 0.f, 0.f, 0.f };
-            if (e < CHUNKS && gy >= 0 && gy < G && gx >= 0 && gx < G)
+            if (tid + k * kThreads < CHUNKS && (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G)
                 v = *reinterpret_cast<const v4f*>(act2 + ((int64_t)gy * G + gx) * C + part * 4);
             pa[k] = v;
+            col += kThreads / 8;
+            if (col >= IW) {
+                col -= IW;
+                ++row;
+            }
         }
     };
     auto stash_act = [&]() {
@@ -456,21 +489,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         // tile rows 0 .. 7, which the second round no longer reads
 #pragma unroll
         for (int round = 0; round < 2; ++round) {
-            float y[2][4][4];
+            v4f y[4][2];
             conv32_wino(s_in, s_u, wave + 4 * round, lane, y);
             __syncthreads();
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
+            for (int e = 0; e < 4; ++e) {
+                const int row = 2 * (wave + 4 * round) + (e >> 1), col = 2 * i + (e & 1);
+                const int gy = y0 + row, gx = x0 + col;
+                const bool in = (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G;  // conv4's zero padding
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int nb = 0; nb < 2; ++nb) {
+                    v4f v = y[e][nb] + bias3[nb];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int o = nb * 16 + i;
-                        const int row = 2 * (wave + 4 * round) + (e >> 1), col = 2 * (4 * q + r) + (e & 1);
-                        const int gy = y0 + row, gx = x0 + col;
-                        const bool in = gy >= 0 && gy < G && gx >= 0 && gx < G;  // conv4's zero padding
-                        s_in[(row * RW + col) * PS + o] = in ? fmaxf(y[nb][r][e] + s_b3[o], 0.f) : 0.f;
-                    }
+                    for (int r = 0; r < 4; ++r) v[r] = in ? fmaxf(v[r], 0.f) : 0.f;
+                    *reinterpret_cast<v4f*>(s_in + (row * RW + col) * PS + 16 * nb + 4 * q) = v;
+                }
+            }
         }
         if (next < it.end) fetch_act(next);  // lands while conv4 runs
         __syncthreads();
@@ -479,22 +513,31 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         // Z[p][9 o + t] = sum_c act3[p][c] w4[o][c][t] (32 blocks of 16 pixels, 8 per
         // wave), written over the pixel's own channels: a block's pixels are read
         // only by the wave that computes the block, before its results exist.
-        for (int mb = wave; mb < NREG / 16; mb += kWaves) {
-            const float* px = s_in + (mb * 16 + i) * PS + 8 * q;
-            const v4f a0 = *reinterpret_cast<const v4f*>(px), a1 = *reinterpret_cast<const v4f*>(px + 4);
-            v4f z0 = v4f{ 0.f, 0.f, 0.f, 0.f }, z1 = z0;
+        static_assert(NREG / 16 == 8 * kWaves, "eight blocks per wave, in pairs");
+#pragma unroll 1
+        for (int mb = wave; mb < NREG / 16; mb += 2 * kWaves) {
+            v4f z[2][2];
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const float a = s < 4 ? a0[s] : a1[s - 4];
-                z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw4[s][0], z0, 0, 0, 0);
-                z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw4[s][1], z1, 0, 0, 0);
+            for (int u = 0; u < 2; ++u) {
+                const float* px = s_in + ((mb + u * kWaves) * 16 + i) * PS + 8 * q;
+                const v4f a0 = *reinterpret_cast<const v4f*>(px), a1 = *reinterpret_cast<const v4f*>(px + 4);
+                z[u][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
+                z[u][1] = z[u][0];
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const float a = s < 4 ? a0[s] : a1[s - 4];
+                    z[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw4[s][0], z[u][0], 0, 0, 0);
+                    z[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw4[s][1], z[u][1], 0, 0, 0);
+                }
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float* zp = s_in + (mb * 16 + 4 * q + r) * PS;
-                zp[i] = z0[r];
-                if (i < 2) zp[16 + i] = z1[r];
-            }
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float* zp = s_in + ((mb + u * kWaves) * 16 + 4 * q + r) * PS;
+                    zp[i] = z[u][0][r];
+                    if (i < 2) zp[16 + i] = z[u][1][r];
+                }
         }
         __syncthreads();
         // then each output pixel sums its 9 taps: disp[o] = b4[o] + sum_t Z[pixel + tap t][9 o + t]

@@ -13,8 +13,9 @@
 // conv2 on 18 x 34, conv3 on 16 x 32, conv4 on 14 x 30): a pass reads only
 // the 2-channel velocity and writes only the 2-channel displacement, and
 // needs no device workspace beyond the packed weights.  conv1 (K = 18) is
-// padded to one K = 32 step; conv4 (N = 2) uses one N-block of 16 with 14
-// zero columns.
+// padded to one K = 32 step; conv4 (N = 2) computes, per conv3 pixel, its 18
+// (output channel, tap) contributions (two N-blocks of one K = 32
+// instruction each) and then sums 9 taps per output pixel.
 #include "common.h"
 
 namespace cnnsns {
@@ -46,8 +47,9 @@ __device__ __forceinline__ int chan_at(int pos)
 // packed weights, one bf16x8 B operand per lane:
 //   w1p[nb][lane]: k = 8 (l/16) + j = 9 ci + tap (< 18, else 0) of output channel 16 nb + l%16
 //   w2p/w3p[tap][nb][lane]: input channel chan_at(8 (l/16) + j), output channel 16 nb + l%16
-//   w4p[tap][lane]: input channel chan_at(8 (l/16) + j), output channel l%16 (< 2, else 0)
-constexpr int P1 = 2 * 64, P2 = 9 * 2 * 64, P4 = 9 * 64;
+//   w4p[nb][lane]: input channel chan_at(8 (l/16) + j), column n = 16 nb + l%16 = 9 o + tap
+//                  (output channel o = n / 9, tap n % 9) for n < 18, else 0
+constexpr int P1 = 2 * 64, P2 = 9 * 2 * 64, P4 = 2 * 64;
 constexpr int PACKED = P1 + 2 * P2 + P4;  // bf16x8 entries
 
 __global__ void k_pack_bf16(const float* __restrict__ w1, const float* __restrict__ w2, const float* __restrict__ w3,
@@ -69,8 +71,8 @@ __global__ void k_pack_bf16(const float* __restrict__ w1, const float* __restric
         const int g = f % P2, t = g / 128, nb = (g >> 6) & 1;
         for (int j = 0; j < 8; ++j) v[j] = (bf16)w[((nb * 16 + i) * C + chan_at(8 * q + j)) * 9 + t];
     } else {
-        const int t = (e - P1 - 2 * P2) >> 6;
-        for (int j = 0; j < 8; ++j) v[j] = (bf16)(i < 2 ? w4[(i * C + chan_at(8 * q + j)) * 9 + t] : 0.f);
+        const int n = 16 * ((e - P1 - 2 * P2) >> 6) + i;
+        for (int j = 0; j < 8; ++j) v[j] = (bf16)(n < 18 ? w4[((n / 9) * C + chan_at(8 * q + j)) * 9 + n % 9] : 0.f);
     }
     out[e] = v;
 }
@@ -306,47 +308,41 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             conv32_bf16<H3, W3, false>(bufB, bufA, w3, s_b + 2 * C, ty0 - 1, tx0 - 1, G, wave, lane);
         __syncthreads();
 
-        // conv4 on the 14 x 30 output tile: one N-block whose columns 0 and 1 are the two
-        // output channels; two M-blocks at a time for independent accumulators
+        // conv4 as a contraction: for every pixel p of the 16 x 32 conv3 region,
+        // Z[p][9 o + t] = sum_c act3[p][c] w4[o][c][t] (one K = 32 instruction per 16 pixels and
+        // N-block), written in FP32 over the pixel's own 80 bytes: a block's pixels are read
+        // only by the wave that computes the block, before its results exist.  Then each output
+        // pixel sums its 9 taps.
         {
-            constexpr int N = OH * OW, NMB = (N + 15) / 16, WI = W3;
-            const int lo = wave * NMB / kWaves, hi = (wave + 1) * NMB / kWaves;
-            for (int mb = lo; mb < hi; mb += 4) {
-                int base[4];
-                v4f d[4];
+            constexpr int NMB3 = H3 * W3 / 16, ZS = PXS / 2;  // 32 blocks; floats per pixel
+            static_assert(H3 * W3 % 16 == 0, "conv3 region is whole M-blocks");
+            float* zf = reinterpret_cast<float*>(bufA);
+            for (int mb = wave; mb < NMB3; mb += kWaves) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(bufA + (mb * 16 + i) * PXS + 8 * q);
+                const v4f z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, s_w4[lane], v4f{ 0.f, 0.f, 0.f, 0.f }, 0, 0, 0);
+                const v4f z1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, s_w4[64 + lane], v4f{ 0.f, 0.f, 0.f, 0.f }, 0,
+                                                                       0, 0);
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int p = min((mb + m) * 16 + i, N - 1);
-                    base[m] = ((p / OW) * WI + p % OW) * PXS + 8 * q;
-                    d[m] = v4f{ 0.f, 0.f, 0.f, 0.f };
+                for (int r = 0; r < 4; ++r) {
+                    float* zp = zf + (mb * 16 + 4 * q + r) * ZS;
+                    zp[i] = z0[r];
+                    if (i < 2) zp[16 + i] = z1[r];
                 }
-                bf16x8 a[2][4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) a[0][m] = *reinterpret_cast<const bf16x8*>(bufA + base[m]);
+            }
+            __syncthreads();
+            for (int e = tid; e < OH * OW; e += kThreads) {
+                const int oy = e / OW, ox = e - oy * OW;
+                float d0 = s_b[3 * C], d1 = s_b[3 * C + 1];
 #pragma unroll
                 for (int t = 0; t < 9; ++t) {
-                    const int cur = t & 1;
-                    if (t + 1 < 9) {
-                        const int off = (((t + 1) / 3) * WI + (t + 1) % 3) * PXS;
-#pragma unroll
-                        for (int m = 0; m < 4; ++m)
-                            a[cur ^ 1][m] = *reinterpret_cast<const bf16x8*>(bufA + base[m] + off);
-                    }
-                    const bf16x8 b = s_w4[t * 64 + lane];
-#pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        d[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cur][m], b, d[m], 0, 0, 0);
+                    const float* zp = zf + ((oy + t / 3) * W3 + ox + t % 3) * ZS;
+                    d0 += zp[t];
+                    d1 += zp[9 + t];
                 }
-                if (i < 2) {
-#pragma unroll
-                    for (int m = 0; m < 4; ++m)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int pp = (mb + m) * 16 + 4 * q + r;
-                            const int gy = ty0 + pp / OW, gx = tx0 + pp % OW;
-                            if (mb + m < hi && pp < N && gy < G && gx < G)
-                                disp[i * GG + (int64_t)gy * G + gx] = d[m][r] + s_b[3 * C + i];
-                        }
+                const int gy = ty0 + oy, gx = tx0 + ox;
+                if (gy < G && gx < G) {
+                    disp[(int64_t)gy * G + gx] = d0;
+                    disp[GG + (int64_t)gy * G + gx] = d1;
                 }
             }
         }
