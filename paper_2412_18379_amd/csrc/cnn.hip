@@ -8,8 +8,8 @@
 // wavefronts per compute unit, one wavefront per SIMD so each may hold 512
 // registers) looping over tiles:
 //   conv12: conv1 (K = 18 padded to 20) on the matrix cores into LDS on the
-//           16 x 32 tile plus a one-pixel border, then conv2; writes the
-//           32-channel activation, pixel-major ([G][G][32]).
+//           16 x 32 tile plus a one-pixel border, then conv2, stored from
+//           registers as the 32-channel activation, pixel-major ([G][G][32]).
 //   conv34: conv3 on a 16 x 32 region (the 14 x 30 output tile plus a
 //           one-pixel border), kept in LDS, then conv4 (N = 2): per region
 //           pixel, its 18 (output channel, tap) contributions on the matrix
@@ -328,22 +328,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         const int y0 = (it.t / tiles_x) * RH, x0 = (it.t % tiles_x) * RW;
 
         // conv1 on the 18 x 34 input tile of conv2; zero outside the grid (conv2's padding).
-        // Two 16-pixel blocks at a time (four independent accumulation chains).
-        auto conv1_block = [&](int mb, v4f& d0, v4f& d1) {
+        // Wave w takes blocks w, w + 4, ..., two at a time (four independent accumulation
+        // chains), with the next pair's gathers issued before this pair's matrix instructions.
+        auto conv1_gather = [&](int mb, float (&a)[5]) {
             const int p = min(mb * 16 + i, NIN - 1);
             const int py = p / IW, base = py * VW + (p - py * IW);
-            float a[5];
 #pragma unroll
             for (int s = 0; s < 5; ++s) {
                 const float v = s_vel[base + l1_off[s]];
                 a[s] = l1_on[s] ? v : 0.f;
-            }
-            d0 = v4f{ 0.f, 0.f, 0.f, 0.f };
-            d1 = d0;
-#pragma unroll
-            for (int s = 0; s < 5; ++s) {
-                d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bw1[s][0], d0, 0, 0, 0);
-                d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bw1[s][1], d1, 0, 0, 0);
             }
         };
         // result rows 4q .. 4q+3 of a block: tile pixels pp0 .. pp0+3 (the last block's
@@ -363,49 +356,68 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
                 }
             }
         };
-        for (int mb = wave; mb < L1_MBLOCKS; mb += 2 * kWaves) {
-            const bool two = mb + kWaves < L1_MBLOCKS;  // wave-uniform
-            v4f d00, d01, d10, d11;
-            conv1_block(mb, d00, d01);
-            conv1_block(two ? mb + kWaves : mb, d10, d11);
-            conv1_store(mb, d00, d01);
-            if (two) conv1_store(mb + kWaves, d10, d11);
+        {
+            float an[2][5];
+            conv1_gather(wave, an[0]);
+            conv1_gather(min(wave + kWaves, L1_MBLOCKS - 1), an[1]);
+            for (int mb = wave; mb < L1_MBLOCKS; mb += 2 * kWaves) {
+                const bool two = mb + kWaves < L1_MBLOCKS;  // wave-uniform
+                float a[2][5];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int s = 0; s < 5; ++s) a[u][s] = an[u][s];
+                if (mb + 2 * kWaves < L1_MBLOCKS) {
+                    conv1_gather(mb + 2 * kWaves, an[0]);
+                    conv1_gather(min(mb + 3 * kWaves, L1_MBLOCKS - 1), an[1]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                v4f d[2][2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    d[u][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
+                    d[u][1] = d[u][0];
+                }
+#pragma unroll
+                for (int s = 0; s < 5; ++s)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        d[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s], bw1[s][0], d[u][0], 0, 0, 0);
+                        d[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s], bw1[s][1], d[u][1], 0, 0, 0);
+                    }
+                conv1_store(mb, d[0][0], d[0][1]);
+                if (two) conv1_store(mb + kWaves, d[1][0], d[1][1]);
+            }
         }
         __syncthreads();
 
         const int next = it.t + it.step;
         if (next < it.end) fetch_vel(next);  // lands while conv2 runs
 
-        // Two rounds of block rows, ty = wave and wave + 4.  The first round reads
-        // tile rows 0 .. 9 and the second rows 8 .. 17, so after the first round the
-        // outputs of region rows 0 .. 7 (output pixels 0 .. 255, pixel-major at
-        // stride PS) can overwrite tile rows 0 .. 7; the rest waits for the second.
+        // conv2 in two rounds of block rows (ty = wave, wave + 4), nothing written to LDS:
+        // each lane stores its results (bias, ReLU) straight to act2, per pixel two 16-byte
+        // runs of channels that L2 merges into whole lines
 #pragma unroll
         for (int round = 0; round < 2; ++round) {
+            const int ty = wave + 4 * round;
             v4f y[4][2];
-            conv32_wino(s_in, s_u, wave + 4 * round, lane, y);
-            __syncthreads();
+            conv32_wino(s_in, s_u, ty, lane, y);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int p = (2 * (wave + 4 * round) + (e >> 1)) * RW + 2 * i + (e & 1);
+                const int gy = y0 + 2 * ty + (e >> 1), gx = x0 + 2 * i + (e & 1);
+                if (gy < G && gx < G) {
+                    float* dst = act2 + ((int64_t)gy * G + gx) * C + 4 * q;
 #pragma unroll
-                for (int nb = 0; nb < 2; ++nb) {
-                    v4f v = y[e][nb] + bias2[nb];
+                    for (int nb = 0; nb < 2; ++nb) {
+                        v4f v = y[e][nb] + bias2[nb];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
-                    *reinterpret_cast<v4f*>(s_in + p * PS + 16 * nb + 4 * q) = v;
+                        for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
+                        *reinterpret_cast<v4f*>(dst + 16 * nb) = v;
+                    }
                 }
             }
         }
-        if (next < it.end) stash_vel();  // s_vel is free since the first round's barrier
-        __syncthreads();
-        for (int e = tid; e < NREG * (C / 4); e += kThreads) {
-            const int p = e >> 3, part = e & 7;
-            const int gy = y0 + p / RW, gx = x0 + p % RW;
-            if (gy < G && gx < G)
-                *reinterpret_cast<v4f*>(act2 + ((int64_t)gy * G + gx) * C + part * 4) =
-                    *reinterpret_cast<const v4f*>(s_in + p * PS + part * 4);
-        }
+        if (next < it.end) stash_vel();  // conv1 of this tile is done with s_vel
         __syncthreads();
     }
 }
