@@ -303,7 +303,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         const int y0 = (t / tiles_x) * RH, x0 = (t % tiles_x) * RW;
 #pragma unroll
         for (int k = 0; k < VEL_PER_THREAD; ++k) {
-            const int e = tid + k * kThreads;
+            // opaque to the compiler, so the positions are not kept in registers across tiles
+            int e = tid + k * kThreads;
+            asm volatile("" : "+v"(e));
             float v = 0.f;
             if (e < 2 * VH * VW) {
                 const int c = e / (VH * VW), rem = e % (VH * VW);
