@@ -330,8 +330,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         const int y0 = (it.t / tiles_x) * RH, x0 = (it.t % tiles_x) * RW;
 
         // conv1 on the 18 x 34 input tile of conv2; zero outside the grid (conv2's padding).
-        // Wave w takes blocks w, w + 4, ..., two at a time (four independent accumulation
-        // chains), with the next pair's gathers issued before this pair's matrix instructions.
+        // Wave w takes blocks w, w + 4, ....
         auto conv1_gather = [&](int mb, float (&a)[5]) {
             const int p = min(mb * 16 + i, NIN - 1);
             const int py = p / IW, base = py * VW + (p - py * IW);
@@ -359,37 +358,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             }
         };
         {
-            float an[2][5];
-            conv1_gather(wave, an[0]);
-            conv1_gather(min(wave + kWaves, L1_MBLOCKS - 1), an[1]);
-            for (int mb = wave; mb < L1_MBLOCKS; mb += 2 * kWaves) {
-                const bool two = mb + kWaves < L1_MBLOCKS;  // wave-uniform
-                float a[2][5];
+            // all of the wave's blocks at once (w, w + 4, ..., at most 10): every gather issues
+            // first, then 20 independent accumulation chains
+            constexpr int NB1 = (L1_MBLOCKS + kWaves - 1) / kWaves;
+            float a[NB1][5];
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+            for (int u = 0; u < NB1; ++u) conv1_gather(min(wave + u * kWaves, L1_MBLOCKS - 1), a[u]);
+            v4f d[NB1][2];
 #pragma unroll
-                    for (int s = 0; s < 5; ++s) a[u][s] = an[u][s];
-                if (mb + 2 * kWaves < L1_MBLOCKS) {
-                    conv1_gather(mb + 2 * kWaves, an[0]);
-                    conv1_gather(min(mb + 3 * kWaves, L1_MBLOCKS - 1), an[1]);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                v4f d[2][2];
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    d[u][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
-                    d[u][1] = d[u][0];
-                }
-#pragma unroll
-                for (int s = 0; s < 5; ++s)
-#pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        d[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s], bw1[s][0], d[u][0], 0, 0, 0);
-                        d[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s], bw1[s][1], d[u][1], 0, 0, 0);
-                    }
-                conv1_store(mb, d[0][0], d[0][1]);
-                if (two) conv1_store(mb + kWaves, d[1][0], d[1][1]);
+            for (int u = 0; u < NB1; ++u) {
+                d[u][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
+                d[u][1] = d[u][0];
             }
+#pragma unroll
+            for (int s = 0; s < 5; ++s)
+#pragma unroll
+                for (int u = 0; u < NB1; ++u) {
+                    d[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s], bw1[s][0], d[u][0], 0, 0, 0);
+                    d[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s], bw1[s][1], d[u][1], 0, 0, 0);
+                }
+#pragma unroll
+            for (int u = 0; u < NB1; ++u)
+                if (wave + u * kWaves < L1_MBLOCKS) conv1_store(wave + u * kWaves, d[u][0], d[u][1]);
         }
         __syncthreads();
 
@@ -527,28 +517,31 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         // Z[p][9 o + t] = sum_c act3[p][c] w4[o][c][t] (32 blocks of 16 pixels, 8 per
         // wave), written over the pixel's own channels: a block's pixels are read
         // only by the wave that computes the block, before its results exist.
-        static_assert(NREG / 16 == 8 * kWaves, "eight blocks per wave, in pairs");
-#pragma unroll 1
-        for (int mb = wave; mb < NREG / 16; mb += 2 * kWaves) {
-            v4f z[2][2];
+        static_assert(NREG / 16 == 8 * kWaves, "eight blocks per wave");
+        {
+            // the wave's 8 blocks (wave, wave + 4, ...) at once: 16 independent accumulation chains
+            v4f a[8][2], z[8][2];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const float* px = s_in + ((mb + u * kWaves) * 16 + i) * PS + 8 * q;
-                const v4f a0 = *reinterpret_cast<const v4f*>(px), a1 = *reinterpret_cast<const v4f*>(px + 4);
+            for (int u = 0; u < 8; ++u) {
+                const float* px = s_in + ((wave + u * kWaves) * 16 + i) * PS + 8 * q;
+                a[u][0] = *reinterpret_cast<const v4f*>(px);
+                a[u][1] = *reinterpret_cast<const v4f*>(px + 4);
                 z[u][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
                 z[u][1] = z[u][0];
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const float a = s < 4 ? a0[s] : a1[s - 4];
-                    z[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw4[s][0], z[u][0], 0, 0, 0);
-                    z[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw4[s][1], z[u][1], 0, 0, 0);
-                }
             }
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
+            for (int s = 0; s < 8; ++s)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float av = s < 4 ? a[u][0][s] : a[u][1][s - 4];
+                    z[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw4[s][0], z[u][0], 0, 0, 0);
+                    z[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw4[s][1], z[u][1], 0, 0, 0);
+                }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    float* zp = s_in + ((mb + u * kWaves) * 16 + 4 * q + r) * PS;
+                    float* zp = s_in + ((wave + u * kWaves) * 16 + 4 * q + r) * PS;
                     zp[i] = z[u][0][r];
                     if (i < 2) zp[16 + i] = z[u][1][r];
                 }
