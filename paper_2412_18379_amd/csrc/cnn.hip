@@ -145,86 +145,95 @@ __device__ __forceinline__ void wino_weights(const v4f* __restrict__ su, int grp
     }
 }
 
-// conv 32 -> 32 (no bias) for one row of 2 x 2 output blocks of the block's
-// 16 x 32 region: block row ty, region rows 2 ty and 2 ty + 1.  s_in holds the
-// 32-channel input on the 18 x 34 tile around the region, s_u the transformed
-// weights.  Result y[e][nb][r], e = 2a + b: region pixel (2 ty + a, 2 (l%16) + b),
-// output channel 16 nb + 4 (l/16) + r.
+// conv 32 -> 32 (no bias) over the block's 16 x 32 region, in two rounds: in
+// round r wave w computes block row ty = w + 4r (region rows 2 ty, 2 ty + 1).
+// s_in holds the 32-channel input on the 18 x 34 tile around the region, s_u
+// the transformed weights.  After each round, emit(r, y) receives the wave's
+// results: y[e][nb][r'], e = 2a + b, is region pixel (2 ty + a, 2 (l%16) + b),
+// output channel 16 nb + 4 (l/16) + r'.
 //
-// The contraction runs in 8 groups (2 channel halves x 4 groups of 4
+// A round's contraction runs in 8 groups (2 channel halves x 4 groups of 4
 // transformed positions), 32 matrix instructions each, with 8 independent
 // accumulators between two updates of one.  Every LDS read is issued one group
-// ahead of its use (the next group's weights, and during the first group the
-// second half's input patch; scheduling barriers keep the compiler from
-// sinking them), and the second half's input transform is spread between the
-// matrix instructions of the fourth group, so a single wave per SIMD keeps the
-// matrix core fed.
-__device__ __forceinline__ void conv32_wino(const float* __restrict__ s_in, const float* __restrict__ s_u, int ty,
-                                            int lane, v4f (&y)[4][2])
+// ahead of its use: the next group's weights; during a round's first group its
+// second half's input patch, and during its fifth group the next round's first
+// patch (scheduling barriers keep the compiler from sinking these reads).  The
+// input transform of each prefetched patch is spread between the matrix
+// instructions of the group before its use, so the matrix core waits only for
+// the output transform between rounds.
+template <class Emit>
+__device__ __forceinline__ void conv32_wino(const float* __restrict__ s_in, const float* __restrict__ s_u, int wave,
+                                            int lane, Emit&& emit)
 {
     const int tx = lane & 15, g = lane >> 4;
     const v4f* su = reinterpret_cast<const v4f*>(s_u) + lane;
-    v4f acc[16][2];
-#pragma unroll
-    for (int xn = 0; xn < 16; ++xn) {
-        acc[xn][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
-        acc[xn][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
-    }
     v4f d[4][4], dn[4][4], bc[4][2], bn[4][2];
-    wino_patch(s_in, ty, tx, g, 0, d);
+    wino_patch(s_in, wave, tx, g, 0, d);
     wino_weights(su, 0, 0, bc);
     wino_input_transform(d);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int round = 0; round < 2; ++round) {
+        const int ty = wave + 4 * round;
+        v4f acc[16][2];
 #pragma unroll
-        for (int grp = 0; grp < 4; ++grp) {
-            const bool last = h == 1 && grp == 3;
-            if (!last) wino_weights(su, (grp + 1) & 3, grp == 3 ? h + 1 : h, bn);
-            if (h == 0 && grp == 0) wino_patch(s_in, ty, tx, g, 1, dn);
-            // keep these reads a whole group ahead of their use
-            __builtin_amdgcn_sched_barrier(0);
+        for (int xn = 0; xn < 16; ++xn) {
+            acc[xn][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
+            acc[xn][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
+        }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+        for (int h = 0; h < 2; ++h) {
+            const bool final_half = round == 1 && h == 1;  // nothing to prefetch after it
+#pragma unroll
+            for (int grp = 0; grp < 4; ++grp) {
+                if (!(final_half && grp == 3)) wino_weights(su, (grp + 1) & 3, grp == 3 ? (h + 1) & 1 : h, bn);
+                if (grp == 0 && !final_half) wino_patch(s_in, h == 0 ? ty : ty + 4, tx, g, h == 0 ? 1 : 0, dn);
+                // keep these reads a whole group ahead of their use
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) {
+                        const int xn = 4 * grp + x;
+                        const float a = d[xn >> 2][xn & 3][j];
+                        acc[xn][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][0][j], a, acc[xn][0], 0, 0, 0);
+                        acc[xn][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][1][j], a, acc[xn][1], 0, 0, 0);
+                    }
+                    if (grp == 3 && !final_half) {
+                        // the prefetched patch's input transform, between the matrix instructions
+                        __builtin_amdgcn_sched_barrier(0);
+                        wino_input_transform_part(dn, j);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
-                    const int xn = 4 * grp + x;
-                    const float a = d[xn >> 2][xn & 3][j];
-                    acc[xn][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][0][j], a, acc[xn][0], 0, 0, 0);
-                    acc[xn][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][1][j], a, acc[xn][1], 0, 0, 0);
-                }
-                if (h == 0 && grp == 3) {
-                    // the second half's input transform, between the matrix instructions
-                    __builtin_amdgcn_sched_barrier(0);
-                    wino_input_transform_part(dn, j);
-                    __builtin_amdgcn_sched_barrier(0);
+                    bc[x][0] = bn[x][0];
+                    bc[x][1] = bn[x][1];
                 }
             }
+            if (!final_half) {
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                bc[x][0] = bn[x][0];
-                bc[x][1] = bn[x][1];
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) d[a][b] = dn[a][b];
             }
         }
-        if (h == 0) {
+        // Y = A^T M A for the lane's block and 8 output channels (4 at a time)
+        v4f y[4][2];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+        for (int nb = 0; nb < 2; ++nb) {
+            v4f m0[4], m1[4];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) d[a][b] = dn[a][b];
+            for (int nu = 0; nu < 4; ++nu) {
+                m0[nu] = acc[nu][nb] + acc[4 + nu][nb] + acc[8 + nu][nb];
+                m1[nu] = acc[4 + nu][nb] - acc[8 + nu][nb] - acc[12 + nu][nb];
+            }
+            y[0][nb] = m0[0] + m0[1] + m0[2];
+            y[1][nb] = m0[1] - m0[2] - m0[3];
+            y[2][nb] = m1[0] + m1[1] + m1[2];
+            y[3][nb] = m1[1] - m1[2] - m1[3];
         }
-    }
-    // Y = A^T M A for the lane's block and 8 output channels (4 at a time)
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-        v4f m0[4], m1[4];
-#pragma unroll
-        for (int nu = 0; nu < 4; ++nu) {
-            m0[nu] = acc[nu][nb] + acc[4 + nu][nb] + acc[8 + nu][nb];
-            m1[nu] = acc[4 + nu][nb] - acc[8 + nu][nb] - acc[12 + nu][nb];
-        }
-        y[0][nb] = m0[0] + m0[1] + m0[2];
-        y[1][nb] = m0[1] - m0[2] - m0[3];
-        y[2][nb] = m1[0] + m1[1] + m1[2];
-        y[3][nb] = m1[1] - m1[2] - m1[3];
+        emit(round, y);
     }
 }
 
@@ -389,11 +398,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         // conv2 in two rounds of block rows (ty = wave, wave + 4), nothing written to LDS:
         // each lane stores its results (bias, ReLU) straight to act2, per pixel two 16-byte
         // runs of channels that L2 merges into whole lines
-#pragma unroll
-        for (int round = 0; round < 2; ++round) {
+        conv32_wino(s_in, s_u, wave, lane, [&](int round, const v4f (&y)[4][2]) {
             const int ty = wave + 4 * round;
-            v4f y[4][2];
-            conv32_wino(s_in, s_u, ty, lane, y);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int gy = y0 + 2 * ty + (e >> 1), gx = x0 + 2 * i + (e & 1);
@@ -408,7 +414,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
                     }
                 }
             }
-        }
+        });
         if (next < it.end) stash_vel();  // conv1 of this tile is done with s_vel
         __syncthreads();
     }
@@ -489,12 +495,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 
         const int next = it.t + it.step;
 
-        // two rounds of block rows (see conv12): the first round's outputs overwrite
-        // tile rows 0 .. 7, which the second round no longer reads
-#pragma unroll
-        for (int round = 0; round < 2; ++round) {
-            v4f y[4][2];
-            conv32_wino(s_in, s_u, wave + 4 * round, lane, y);
+        // two rounds of block rows: the first round's outputs overwrite tile rows 0 .. 7 (output
+        // pixels 0 .. 255 at stride PS), which the second round no longer reads; both wait for
+        // every wave to finish reading
+        conv32_wino(s_in, s_u, wave, lane, [&](int round, const v4f (&y)[4][2]) {
             __syncthreads();
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -509,7 +513,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
                     *reinterpret_cast<v4f*>(s_in + (row * RW + col) * PS + 16 * nb + 4 * q) = v;
                 }
             }
-        }
+        });
         if (next < it.end) fetch_act(next);  // lands while conv4 runs
         __syncthreads();
 
