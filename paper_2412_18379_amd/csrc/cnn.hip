@@ -11,10 +11,10 @@
 //           16 x 32 tile plus a one-pixel border, then conv2, stored from
 //           registers as the 32-channel activation, pixel-major ([G][G][32]).
 //   conv34: conv3 on a 16 x 32 region (the 14 x 30 output tile plus a
-//           one-pixel border), kept in LDS, then conv4 (N = 2): per region
-//           pixel, its 18 (output channel, tap) contributions on the matrix
-//           cores, then a 9-term sum per output pixel; writes the 2-channel
-//           displacement.
+//           one-pixel border); its results feed conv4 (N = 2) in registers:
+//           per region pixel, its 18 (output channel, tap) contributions on
+//           the matrix cores, kept in LDS, then a 9-term sum per output pixel;
+//           writes the 2-channel displacement.
 // The two 32 -> 32 layers use the Winograd minimal filtering algorithm
 // F(2x2, 3x3) (Lavin and Gray, 2016): per 2 x 2 output block and channel
 // pair, 16 products in a transformed domain replace 36 direct ones, so the
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     }
 }
 
-// conv3 + ReLU on the tile plus a one-pixel border (in LDS), then conv4 -> disp [2][G][G].
+// conv3 + ReLU on the tile plus a one-pixel border, then conv4 -> disp [2][G][G].
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_conv34_f32(
     int32_t G, int tiles_x, int ntiles, const float* __restrict__ act2, const float* __restrict__ u3,
     const float* __restrict__ b3, const float* __restrict__ w4, const float* __restrict__ b4,
@@ -442,15 +442,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) bias3[nb][r] = b3[16 * nb + 4 * q + r];
-    // conv4 B operands: k-step s of lane (i, q) is channel 8q + s; column n = 16 nb + i is
-    // (output channel n / 9, tap n % 9) for n < 18, zero beyond
-    float bw4[8][2];
+    // conv4 A operands (rows n = 16 nz + i = 9 o + tap, zero for n >= 18): in k-step s, lane
+    // (i, q) supplies input channel 4q + s (s < 4) or 16 + 4q + s - 4, the channels that the
+    // Winograd result places in this lane
+    float aw4[8][2];
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-            const int n = 16 * nb + i, c = 8 * q + s;
-            bw4[s][nb] = n < 18 ? w4[((n / 9) * C + c) * 9 + n % 9] : 0.f;
+        for (int nz = 0; nz < 2; ++nz) {
+            const int n = 16 * nz + i, c = s < 4 ? 4 * q + s : 16 + 4 * q + s - 4;
+            aw4[s][nz] = n < 18 ? w4[((n / 9) * C + c) * 9 + n % 9] : 0.f;
         }
     const float bias4[2] = { b4[0], b4[1] };
 
@@ -495,9 +496,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 
         const int next = it.t + it.step;
 
-        // two rounds of block rows: the first round's outputs overwrite tile rows 0 .. 7 (output
-        // pixels 0 .. 255 at stride PS), which the second round no longer reads; both wait for
-        // every wave to finish reading
+        // conv3 in two rounds of block rows.  Each round's results go straight into conv4: for
+        // every pixel p of the round, Z[p][n] = sum_c act3[p][c] w4[n / 9][c][n % 9] (n < 18) as a
+        // contraction on the matrix cores (A = conv4 weights, B = the lane's act3 channels), stored
+        // at stride ZS over tile rows the remaining reads no longer need: the first round's
+        // (pixels 0 .. 255) below tile row 8, which the second round does not read, and the
+        // second's after it, each after every wave has finished reading.
+        constexpr int ZS = 20;
+        static_assert(NREG / 2 * ZS <= 8 * IW * PS && NREG * ZS <= NIN * PS, "Z placement");
         conv32_wino(s_in, s_u, wave, lane, [&](int round, const v4f (&y)[4][2]) {
             __syncthreads();
 #pragma unroll
@@ -505,59 +511,38 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
                 const int row = 2 * (wave + 4 * round) + (e >> 1), col = 2 * i + (e & 1);
                 const int gy = y0 + row, gx = x0 + col;
                 const bool in = (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G;  // conv4's zero padding
+                v4f act[2];
 #pragma unroll
                 for (int nb = 0; nb < 2; ++nb) {
-                    v4f v = y[e][nb] + bias3[nb];
+                    act[nb] = y[e][nb] + bias3[nb];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = in ? fmaxf(v[r], 0.f) : 0.f;
-                    *reinterpret_cast<v4f*>(s_in + (row * RW + col) * PS + 16 * nb + 4 * q) = v;
+                    for (int r = 0; r < 4; ++r) act[nb][r] = in ? fmaxf(act[nb][r], 0.f) : 0.f;
+                }
+                v4f z0 = v4f{ 0.f, 0.f, 0.f, 0.f }, z1 = z0;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const float b = s < 4 ? act[0][s] : act[1][s - 4];
+                    z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(aw4[s][0], b, z0, 0, 0, 0);
+                    z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(aw4[s][1], b, z1, 0, 0, 0);
+                }
+                // lane (i, q) holds Z of pixel (row, 2 i + (e & 1)) for n = 4q + r and 16 + 4q + r
+                float* zp = s_in + (row * RW + col) * ZS;
+                *reinterpret_cast<v4f*>(zp + 4 * q) = z0;
+                if (q == 0) {
+                    zp[16] = z1[0];
+                    zp[17] = z1[1];
                 }
             }
         });
-        if (next < it.end) fetch_act(next);  // lands while conv4 runs
+        if (next < it.end) fetch_act(next);  // lands while the taps are summed
         __syncthreads();
-
-        // conv4 as a contraction on the matrix cores: for every region pixel p,
-        // Z[p][9 o + t] = sum_c act3[p][c] w4[o][c][t] (32 blocks of 16 pixels, 8 per
-        // wave), written over the pixel's own channels: a block's pixels are read
-        // only by the wave that computes the block, before its results exist.
-        static_assert(NREG / 16 == 8 * kWaves, "eight blocks per wave");
-        {
-            // the wave's 8 blocks (wave, wave + 4, ...) at once: 16 independent accumulation chains
-            v4f a[8][2], z[8][2];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const float* px = s_in + ((wave + u * kWaves) * 16 + i) * PS + 8 * q;
-                a[u][0] = *reinterpret_cast<const v4f*>(px);
-                a[u][1] = *reinterpret_cast<const v4f*>(px + 4);
-                z[u][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
-                z[u][1] = z[u][0];
-            }
-#pragma unroll
-            for (int s = 0; s < 8; ++s)
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const float av = s < 4 ? a[u][0][s] : a[u][1][s - 4];
-                    z[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw4[s][0], z[u][0], 0, 0, 0);
-                    z[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw4[s][1], z[u][1], 0, 0, 0);
-                }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float* zp = s_in + ((wave + u * kWaves) * 16 + 4 * q + r) * PS;
-                    zp[i] = z[u][0][r];
-                    if (i < 2) zp[16 + i] = z[u][1][r];
-                }
-        }
-        __syncthreads();
-        // then each output pixel sums its 9 taps: disp[o] = b4[o] + sum_t Z[pixel + tap t][9 o + t]
+        // each output pixel sums its 9 taps: disp[o] = b4[o] + sum_t Z[pixel + tap t][9 o + t]
         for (int e = tid; e < OH34 * OW34; e += kThreads) {
             const int oy = e / OW34, ox = e - oy * OW34;
             float d0 = bias4[0], d1 = bias4[1];
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
-                const float* zp = s_in + ((oy + t / 3) * RW + ox + t % 3) * PS;
+                const float* zp = s_in + ((oy + t / 3) * RW + ox + t % 3) * ZS;
                 d0 += zp[t];
                 d1 += zp[9 + t];
             }
