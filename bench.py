@@ -127,6 +127,15 @@ def cpu_baseline(w, ws, bs, band_rows: int):
     }
 
 
+SERVED = {
+    # name: meshes, triangle range (log-uniform), jobs in flight, device budget
+    "c5": dict(n_meshes=64, lo=1e4, hi=4e6, max_inflight=8, budget=4 << 30,
+               label="64 resident meshes, triangles log-uniform in [1e4, 4e6]"),
+    "c5s": dict(n_meshes=6, lo=1.6e3, hi=1.6e5, max_inflight=4, budget=256 << 20,
+                label="6 resident meshes, triangles log-uniform in [1.6e3, 1.6e5] (the serving tests' range)"),
+}
+
+
 def bench_served(args):
     """Served mix: resident meshes of uneven size, CNN-SNS jobs arriving as a Poisson process,
     continuous batching by the library's server (BF16 CNN, FP64 walk)."""
@@ -136,8 +145,9 @@ def bench_served(args):
     from paper_2412_18379_amd import train as T
     from paper_2412_18379_amd import workload as W
 
+    cfg = SERVED[args.workload]
     t0 = time.perf_counter()
-    specs = W.served_mix_specs(n_meshes=args.mix_meshes, seed=5)
+    specs = W.served_mix_specs(n_meshes=cfg["n_meshes"], seed=5, lo=cfg["lo"], hi=cfg["hi"])
     meshes = []
     for spec in specs:
         w = W.build_served(spec)
@@ -172,8 +182,11 @@ def bench_served(args):
     cnn_it = np.concatenate([r[1].cpu().numpy() for r in ref])
     plain_it = np.concatenate([x.cpu().numpy() for x in plain_it])
 
-    budget = 4 << 30
-    srv = C.Server(Wt, hbm_budget_bytes=budget, max_inflight=8, queue_depth=1 << 16, precision=prec)
+    log(f"reference pass (each job alone) and plain SNS done ({time.perf_counter() - t0:.1f}s)")
+    budget = cfg["budget"]
+    srv = C.Server(Wt, hbm_budget_bytes=budget, max_inflight=cfg["max_inflight"], queue_depth=1 << 16,
+                   precision=prec)
+    log("server created")
 
     def run(order, arrivals=None):
         outs, ids = [], []
@@ -192,6 +205,7 @@ def bench_served(args):
         return outs, lat, wall
 
     run(list(range(min(16, len(meshes)))))  # warm-up
+    log("warm-up done")
     order = list(range(len(meshes)))
     outs, lat_sat, wall_sat = run(order)
     same = all(torch.equal(h, ref[mi][0]) and torch.equal(it, ref[mi][1]) for mi, h, it in outs)
@@ -218,10 +232,10 @@ def bench_served(args):
         "value": hi["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": args.mix_jobs, "warmup": 16,
         "ms_per_step": round(1e3 * hi["wall_s"] / args.mix_jobs, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": f"{prec} CNN / f64 SNS", "data": "synthetic",
-        "config": {"workload": f"served mix: {len(meshes)} resident meshes, triangles log-uniform in [1e4, 4e6], "
-                               f"Poisson arrivals, continuous batching", "n_meshes": len(meshes),
+        "config": {"workload": f"served mix: {cfg['label']}, Poisson arrivals, continuous batching",
+                   "n_meshes": len(meshes),
                    "n_triangles": n_tri, "points_per_pass": int(n_pts.sum()), "hbm_budget_bytes": budget,
-                   "max_inflight": 8, "weights": "trained (mix)" if tr is not None else "he-init"},
+                   "max_inflight": cfg["max_inflight"], "weights": "trained (mix)" if tr is not None else "he-init"},
         "saturation": {"jobs_per_s": round(mu, 2), "points_per_s": round(float(n_pts.sum()) / wall_sat, 1),
                        "p50_ms": round(float(np.percentile(lat_sat, 50)), 3),
                        "p99_ms": round(float(np.percentile(lat_sat, 99)), 3)},
@@ -238,8 +252,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
-    ap.add_argument("--mix-meshes", type=int, default=64, help="served mix: number of meshes")
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5", "c5s"])
     ap.add_argument("--mix-jobs", type=int, default=512, help="served mix: jobs per arrival rate")
     ap.add_argument("--precision", default=None, choices=["f32", "bf16", "fp8"])
     ap.add_argument("--weights", default="trained", choices=["trained", "he"])
@@ -272,6 +285,8 @@ def main():
         # until it is.
         sys.exit("bench.py: the served-mix workload (c5) is switched off until the cause of a host crash "
                  "in it is found")
+    if args.workload == "c5s":
+        return bench_served(args)
     precision = args.precision or ("bf16" if args.workload == "c4" else "f32")
     wl_name = "c2" if args.workload == "c4" else args.workload
     t0 = time.perf_counter()
