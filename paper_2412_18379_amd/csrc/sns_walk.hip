@@ -20,10 +20,8 @@ constexpr int64_t kChunk = 512;  // points per wavefront
 
 __device__ __forceinline__ int32_t cell_of(double x, int32_t G)
 {
-    double f = floor(x * (double)G);
-    if (!(f >= 0.0)) return 0;  // negative or NaN
-    if (f > (double)(G - 1)) return G - 1;
-    return (int32_t)f;
+    // floor(x G) clamped to [0, G-1]; fmax takes 0 for a NaN
+    return (int32_t)fmin(fmax(floor(x * (double)G), 0.0), (double)(G - 1));
 }
 
 __device__ __forceinline__ double clamp01(double v)
@@ -32,27 +30,7 @@ __device__ __forceinline__ double clamp01(double v)
 }
 
 template <int MODE>
-__device__ __forceinline__ int32_t start_of(int64_t i, double px, double py, const int32_t* __restrict__ start,
-                                            const double2* __restrict__ origin, const float* __restrict__ disp,
-                                            const int32_t* __restrict__ lookup, int32_t G)
-{
-    if (MODE == START_GIVEN) return start[i];
-    if (MODE == START_ASG) {
-        int32_t k = lookup[(int64_t)cell_of(py, G) * G + cell_of(px, G)];
-        return k < 0 ? 0 : k;
-    }
-    // CNN-SNS: predicted departure point from the displacement of the origin's cell
-    const double2 o = origin[i];
-    const int64_t c = (int64_t)cell_of(o.y, G) * G + cell_of(o.x, G);
-    const double hx = clamp01(o.x + (double)disp[c]);
-    const double hy = clamp01(o.y + (double)disp[(int64_t)G * G + c]);
-    int32_t k = lookup[(int64_t)cell_of(hy, G) * G + cell_of(hx, G)];
-    if (k < 0) k = start ? start[i] : 0;
-    return k;
-}
-
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_locate(const ElemRec* __restrict__ rec, int64_t n_tri, int64_t n,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_locate(const ElemRec* __restrict__ rec, int64_t n_tri, int64_t n,
                                                    const double2* __restrict__ xp, const int32_t* __restrict__ start,
                                                    const double2* __restrict__ origin,
                                                    const float* __restrict__ disp,
@@ -63,8 +41,55 @@ __global__ __launch_bounds__(kBlock) void k_locate(const ElemRec* __restrict__ r
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
     int64_t next = wave * kChunk;           // wave-uniform: next unstarted point of the chunk
+    const int64_t begin = next;
     const int64_t end = next + kChunk < n ? next + kChunk : n;
     if (next >= end) return;
+
+    // Start elements that depend on a lookup (CNN-SNS, ASG) are computed for the whole chunk
+    // first, eight independent load chains per lane, and kept in LDS: a lane that takes a new
+    // point then waits for one load (x_p) instead of a chain of three.
+    __shared__ int32_t s_start[MODE == START_GIVEN ? 1 : kBlock / kWave][MODE == START_GIVEN ? 1 : kChunk];
+    int32_t* const my_start = s_start[MODE == START_GIVEN ? 0 : (threadIdx.x / kWave)];
+    if (MODE != START_GIVEN) {
+        // in two halves of four points per lane, staged so that the four chains' loads of each
+        // level issue together (eight at once would cost occupancy)
+        constexpr int PER_LANE = (int)(kChunk / kWave), H = PER_LANE / 2;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            int64_t pt[H];
+            double2 o[H];
+            int32_t k0[H];
+#pragma unroll
+            for (int u = 0; u < H; ++u) {
+                const int64_t i = begin + (half * H + u) * kWave + lane;
+                pt[u] = i < end ? i : end - 1;  // lanes past the chunk's end repeat its last point
+                o[u] = MODE == START_CNN ? origin[pt[u]] : xp[pt[u]];
+            }
+            if (MODE == START_CNN) {
+                float dx[H], dy[H];
+#pragma unroll
+                for (int u = 0; u < H; ++u) {
+                    const int64_t c = (int64_t)cell_of(o[u].y, G) * G + cell_of(o[u].x, G);
+                    dx[u] = disp[c];
+                    dy[u] = disp[(int64_t)G * G + c];
+                }
+#pragma unroll
+                for (int u = 0; u < H; ++u) {
+                    // predicted departure point of the origin's cell (Alg. 2)
+                    o[u].x = clamp01(o[u].x + (double)dx[u]);
+                    o[u].y = clamp01(o[u].y + (double)dy[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < H; ++u) k0[u] = lookup[(int64_t)cell_of(o[u].y, G) * G + cell_of(o[u].x, G)];
+#pragma unroll
+            for (int u = 0; u < H; ++u) {
+                if (k0[u] < 0) k0[u] = (MODE == START_CNN && start) ? start[pt[u]] : 0;  // uncovered cell
+                if (begin + (half * H + u) * kWave + lane < end) my_start[(half * H + u) * kWave + lane] = k0[u];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // LDS operations of one wavefront complete in order
+    }
 
     bool active = false;
     int64_t idx = 0;
@@ -82,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_locate(const ElemRec* __restrict__ r
                 const double2 p = xp[idx];
                 px = p.x;
                 py = p.y;
-                K = start_of<MODE>(idx, px, py, start, origin, disp, lookup, G);
+                K = MODE == START_GIVEN ? start[idx] : my_start[idx - begin];
                 I = 0;
                 if (K < 0 || K >= n_tri) {
                     host[idx] = -1;
