@@ -40,10 +40,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-    int64_t next = wave * kChunk;           // wave-uniform: next unstarted point of the chunk
-    const int64_t begin = next;
-    const int64_t end = next + kChunk < n ? next + kChunk : n;
-    if (next >= end) return;
+    const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
+    // A wave owns kChunk slots.  From the element before movement (long paths, where
+    // neighbouring points share elements) slot v is point wave kChunk + v, a contiguous chunk.
+    // From a looked-up start (short paths, whose rare long ones cluster near the boundary) the
+    // slots are 8 runs of 64 consecutive points strided across all points: run u is
+    // 64-point block wave + u n_waves, so the long walks of one region spread over many waves.
+    auto point_of = [&](int64_t v) -> int64_t {
+        if (MODE == START_GIVEN) return wave * kChunk + v;
+        return ((wave + (v >> 6) * n_waves) << 6) + (v & (kWave - 1));
+    };
+    int64_t next = 0;  // wave-uniform: next unstarted slot
+    const int64_t n_slots = MODE == START_GIVEN ? (n - wave * kChunk < kChunk ? n - wave * kChunk : kChunk) : kChunk;
+    if (point_of(0) >= n) return;
 
     // Start elements that depend on a lookup (CNN-SNS, ASG) are computed for the whole chunk
     // first, eight independent load chains per lane, and kept in LDS: a lane that takes a new
@@ -61,8 +70,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
             int32_t k0[H];
 #pragma unroll
             for (int u = 0; u < H; ++u) {
-                const int64_t i = begin + (half * H + u) * kWave + lane;
-                pt[u] = i < end ? i : end - 1;  // lanes past the chunk's end repeat its last point
+                const int64_t i = point_of((half * H + u) * kWave + lane);
+                pt[u] = i < n ? i : n - 1;  // slots past the last point repeat it
                 o[u] = MODE == START_CNN ? origin[pt[u]] : xp[pt[u]];
             }
             if (MODE == START_CNN) {
@@ -85,7 +94,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 #pragma unroll
             for (int u = 0; u < H; ++u) {
                 if (k0[u] < 0) k0[u] = (MODE == START_CNN && start) ? start[pt[u]] : 0;  // uncovered cell
-                if (begin + (half * H + u) * kWave + lane < end) my_start[(half * H + u) * kWave + lane] = k0[u];
+                my_start[(half * H + u) * kWave + lane] = k0[u];
             }
         }
         __builtin_amdgcn_wave_barrier();  // LDS operations of one wavefront complete in order
@@ -99,28 +108,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     for (;;) {
         // hand unstarted points of the chunk to idle lanes
         const uint64_t idle = __ballot(!active);
-        if (idle != 0 && next < end) {
+        if (idle != 0 && next < n_slots) {
             const uint32_t lo = (uint32_t)idle, hi = (uint32_t)(idle >> 32);
             const int rank = (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-            if (!active && next + rank < end) {
-                idx = next + rank;
-                const double2 p = xp[idx];
-                px = p.x;
-                py = p.y;
-                K = MODE == START_GIVEN ? start[idx] : my_start[idx - begin];
-                I = 0;
-                if (K < 0 || K >= n_tri) {
-                    host[idx] = -1;
-                    if (iters) iters[idx] = 0;
-                    if (status) status[idx] = CNNSNS_BADSTART;
-                } else {
-                    active = true;
+            if (!active && next + rank < n_slots) {
+                const int64_t v = next + rank;
+                idx = point_of(v);
+                if (idx < n) {
+                    const double2 p = xp[idx];
+                    px = p.x;
+                    py = p.y;
+                    K = MODE == START_GIVEN ? start[idx] : my_start[v];
+                    I = 0;
+                    if (K < 0 || K >= n_tri) {
+                        host[idx] = -1;
+                        if (iters) iters[idx] = 0;
+                        if (status) status[idx] = CNNSNS_BADSTART;
+                    } else {
+                        active = true;
+                    }
                 }
             }
             next += __popcll(idle);
         }
         if (__ballot(active) == 0) {
-            if (next >= end) break;
+            if (next >= n_slots) break;
             continue;
         }
         if (active) {
