@@ -43,16 +43,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
     // A wave owns kChunk slots.  From the element before movement (long paths, where
     // neighbouring points share elements) slot v is point wave kChunk + v, a contiguous chunk.
-    // From a looked-up start (short paths, whose rare long ones cluster near the boundary) the
-    // slots are 8 runs of 64 consecutive points strided across all points: run u is
-    // 64-point block wave + u n_waves, so the long walks of one region spread over many waves.
+    // From a looked-up start (short paths, whose rare long ones cluster at the two ends of the
+    // point order, the domain boundary) the slots are 8 runs of 64 consecutive points strided
+    // across all points, so the long walks of one region spread over many waves: run u is
+    // 64-point block b + u n_waves with b = wave for even u and n_waves - 1 - wave for odd u,
+    // so both ends of the point order fall to the first waves, which walk them first (runs in
+    // the order 0, 7, 1, 6, 2, 5, 3, 4).
     auto point_of = [&](int64_t v) -> int64_t {
         if (MODE == START_GIVEN) return wave * kChunk + v;
-        return ((wave + (v >> 6) * n_waves) << 6) + (v & (kWave - 1));
+        const int k = (int)(v >> 6);
+        const int u = (k & 1) ? 7 - (k >> 1) : (k >> 1);
+        const int64_t b = (u & 1) ? n_waves - 1 - wave : wave;
+        return ((b + u * n_waves) << 6) + (v & (kWave - 1));
     };
     int64_t next = 0;  // wave-uniform: next unstarted slot
     const int64_t n_slots = MODE == START_GIVEN ? (n - wave * kChunk < kChunk ? n - wave * kChunk : kChunk) : kChunk;
-    if (point_of(0) >= n) return;
+    if (MODE == START_GIVEN && n_slots <= 0) return;
 
     // Start elements that depend on a lookup (CNN-SNS, ASG) are computed for the whole chunk
     // first, eight independent load chains per lane, and kept in LDS: a lane that takes a new
