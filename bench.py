@@ -286,7 +286,9 @@ def main():
         sys.exit("bench.py: the served-mix workload (c5) is switched off until the cause of a host crash "
                  "in it is found")
     if args.workload == "c5s":
-        return bench_served(args)
+        # switched off as well: a run of the serving tests later ended in the same kind of host
+        # crash, so the serving loop is off until its cause is found
+        sys.exit("bench.py: the serving loop is switched off (an intermittent host crash in it is unexplained)")
     precision = args.precision or ("bf16" if args.workload == "c4" else "f32")
     wl_name = "c2" if args.workload == "c4" else args.workload
     t0 = time.perf_counter()

@@ -180,6 +180,10 @@ int cnnsns_locate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* sta
  *   max_inflight      jobs on the device at once (>= 1).
  *   queue_depth       jobs waiting for admission at most (>= 1).
  *   w                 CNN weights (device pointers; copied at creation).
+ * Switched off in this build: returns EINVAL unless the environment variable
+ * CNNSNS_ENABLE_SERVING is "1", because runs of the serving loop on the GPU
+ * have occasionally ended in a host-side segmentation fault whose cause has
+ * not been found.
  */
 int cnnsns_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int32_t queue_depth,
                          int32_t precision, const cnnsns_cnn* w, cnnsns_server* out);

@@ -2,6 +2,8 @@
 // Every exported function catches everything; nothing propagates to C.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <cstring>
 #include <exception>
 #include <new>
 #include <string>
@@ -129,6 +131,12 @@ int cnnsns_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int32_t
     return guarded([&] {
         if (!out) fail(CNNSNS_EINVAL, "server_create: out must not be NULL");
         *out = nullptr;
+        // Switched off unless asked for: runs of the serving loop on the GPU have ended, now and
+        // then, in a host-side segmentation fault whose cause has not been found.
+        const char* on = std::getenv("CNNSNS_ENABLE_SERVING");
+        if (!on || std::strcmp(on, "1") != 0)
+            fail(CNNSNS_EINVAL, "server_create: the serving loop is switched off in this build (an intermittent host "
+                                "crash in it is unexplained); set CNNSNS_ENABLE_SERVING=1 to enable it");
         *out = server_create(hbm_budget_bytes, max_inflight, queue_depth, precision, w);
     });
 }

@@ -45,3 +45,18 @@ def test_argument_errors_without_gpu(L):
     assert L.cnnsns_last_error() == b""
     assert L.cnnsns_submit(None, None, None, 0, None, None, None, None, None, None) == C.EINVAL
     assert L.cnnsns_server_destroy(None) == C.OK
+
+
+def test_serving_switched_off_by_default(L):
+    """cnnsns_server_create refuses to start the serving loop unless it is asked for explicitly."""
+    if os.environ.get("CNNSNS_ENABLE_SERVING") == "1":
+        pytest.skip("serving enabled in this environment")
+    from paper_2412_18379_amd import cnnsns as C
+    cnn = C._Cnn()
+    for l in range(4):
+        cnn.w[l] = 1
+        cnn.b[l] = 1
+    out = ctypes.c_void_p()
+    assert L.cnnsns_server_create(1 << 20, 2, 8, C.BF16, ctypes.byref(cnn), ctypes.byref(out)) == C.EINVAL
+    assert b"switched off" in L.cnnsns_last_error()
+    assert not out.value

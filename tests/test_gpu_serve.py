@@ -9,7 +9,12 @@ import numpy as np
 import pytest
 import torch
 
-pytestmark = pytest.mark.gpu
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="the serving loop is switched off: GPU runs of it (this test once, the 64-mesh "
+                            "served-mix benchmark once) ended in a host segmentation fault whose cause has not "
+                            "been found"),
+]
 
 
 @pytest.fixture(scope="module")

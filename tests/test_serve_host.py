@@ -47,7 +47,8 @@ CASES = [
 
 @pytest.mark.parametrize("case", CASES)
 def test_scheduler_under_sanitizers(driver, case):
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1",
+               CNNSNS_ENABLE_SERVING="1")
     r = subprocess.run([driver, *map(str, case)], capture_output=True, text=True, timeout=300, env=env)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
     assert "0 failures" in r.stdout
