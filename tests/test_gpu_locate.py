@@ -184,3 +184,27 @@ def test_mesh_errors_on_device(C):
     with pytest.raises(C.CnnsnsError) as e:
         C.Mesh(xy3, np.array([[0, 1, 2], [0, 1, 3]], np.int32))
     assert e.value.code == C.EMESH
+
+
+def test_ragged_counts_lookup_modes(C, oracle_mod, wl):
+    """CNN-SNS and ASG starts assign each wave strided 64-point runs: every count around the run
+    and chunk sizes (and counts whose waves do not fill the last block) matches the oracle exactly."""
+    w = wl.build("c2")
+    G = w.G
+    rng = np.random.default_rng(3)
+    disp = (-w.dt * w.vel.astype(np.float64) + rng.normal(0, 2 * w.dbar, size=w.vel.shape)).astype(np.float32)
+    mesh = C.Mesh(w.xy, w.tri, overlay_side=G)
+    tc, nbr = oracle_mod.prepare_mesh(w.xy, w.tri)
+    lk = oracle_mod.lookup(w.xy, tc, G)
+    zero = np.zeros((2, G, G))
+    d_disp = _dev(disp)
+    for n in [1, 63, 64, 65, 511, 512, 513, 1000, 2049, 4097, 70001]:
+        print(f"[ragged lookup modes] n={n}", flush=True)
+        xp, org = w.xp[:n], w.origins[:n]
+        _, oh, oi, _ = oracle_mod.cnnsns(w.xy, tc, nbr, lk, org, xp, disp.astype(np.float64))
+        h, it, _ = C.locate(mesh, _dev(xp), origin=_dev(org), disp=d_disp)
+        assert np.array_equal(h.cpu().numpy(), oh) and np.array_equal(it.cpu().numpy(), oi)
+        st = oracle_mod.cnnsns_start(xp, zero, lk)
+        ah, ai, _ = oracle_mod.sns(w.xy, tc, nbr, xp, st)
+        h, it, _ = C.locate(mesh, _dev(xp))
+        assert np.array_equal(h.cpu().numpy(), ah) and np.array_equal(it.cpu().numpy(), ai)
