@@ -13,9 +13,13 @@
 // conv2 on 18 x 34, conv3 on 16 x 32, conv4 on 14 x 30): a pass reads only
 // the 2-channel velocity and writes only the 2-channel displacement, and
 // needs no device workspace beyond the packed weights.  conv1 (K = 18) is
-// padded to one K = 32 step; conv4 (N = 2) computes, per conv3 pixel, its 18
-// (output channel, tap) contributions (two N-blocks of one K = 32
-// instruction each) and then sums 9 taps per output pixel.
+// padded to one K = 32 step, its K ordered tap-major so that a lane's operand
+// is four (u, v) pairs read straight from LDS; conv4 (N = 2) computes, per
+// conv3 pixel, its 18 (output channel, tap) contributions (two N-blocks of one
+// K = 32 instruction each) and then sums 9 taps per output pixel.  Biases
+// enter as the accumulators' initial values, and ReLU acts on the rounded
+// BF16 pair (rounding to nearest keeps the sign, so the order of the two does
+// not change the result).
 #include "common.h"
 
 namespace cnnsns {
@@ -23,6 +27,10 @@ namespace {
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;  // 4 wavefronts, one per SIMD
@@ -34,7 +42,13 @@ constexpr int H2 = OH + 4, W2 = OW + 4;    // conv2 region (18 x 34)
 constexpr int H3 = OH + 2, W3 = OW + 2;    // conv3 region (16 x 32)
 constexpr int HV = OH + 8, WV = OW + 8;    // velocity tile (22 x 38)
 constexpr int PXS = 40;                    // bf16 per pixel in LDS (32 channels + 8 pad: 80 bytes)
-constexpr int VEL_PER_THREAD = (2 * HV * WV + kThreads - 1) / kThreads;
+constexpr int VEL_PER_THREAD = (HV * WV + kThreads - 1) / kThreads;  // velocity pixels per thread
+// M-blocks of 16 pixels per wavefront, and how many of them are in flight at once
+constexpr int NMB1 = H1 * W1 / 16, BPW1 = (NMB1 + kWaves - 1) / kWaves, MB1 = 6;
+constexpr int NMB2 = (H2 * W2 + 15) / 16, BPW2 = (NMB2 + kWaves - 1) / kWaves, MB2 = 5;
+constexpr int NMB3 = H3 * W3 / 16, BPW3 = NMB3 / kWaves, MB3 = 4;
+static_assert(H1 * W1 % 16 == 0 && H3 * W3 % 16 == 0 && NMB3 % kWaves == 0, "whole M-blocks");
+static_assert(BPW1 % MB1 == 0 && BPW2 % MB2 == 0 && BPW3 % MB3 == 0, "whole groups per wavefront");
 
 // Hidden activations are stored pair-interleaved: LDS position 2c + h of a
 // pixel holds channel c + 16 h, so a lane that owns channels c and c + 16 of
@@ -45,7 +59,7 @@ __device__ __forceinline__ int chan_at(int pos)
 }
 
 // packed weights, one bf16x8 B operand per lane:
-//   w1p[nb][lane]: k = 8 (l/16) + j = 9 ci + tap (< 18, else 0) of output channel 16 nb + l%16
+//   w1p[nb][lane]: k = 8 (l/16) + j = 2 tap + ci (< 18, else 0) of output channel 16 nb + l%16
 //   w2p/w3p[tap][nb][lane]: input channel chan_at(8 (l/16) + j), output channel 16 nb + l%16
 //   w4p[nb][lane]: input channel chan_at(8 (l/16) + j), column n = 16 nb + l%16 = 9 o + tap
 //                  (output channel o = n / 9, tap n % 9) for n < 18, else 0
@@ -63,7 +77,7 @@ __global__ void k_pack_bf16(const float* __restrict__ w1, const float* __restric
         const int nb = e >> 6;
         for (int j = 0; j < 8; ++j) {
             const int k = 8 * q + j;
-            v[j] = (bf16)(k < 18 ? w1[((nb * 16 + i) * 2 + k / 9) * 9 + k % 9] : 0.f);
+            v[j] = (bf16)(k < 18 ? w1[((nb * 16 + i) * 2 + (k & 1)) * 9 + (k >> 1)] : 0.f);
         }
     } else if (e < P1 + 2 * P2) {
         const int f = e - P1;
@@ -94,81 +108,82 @@ __device__ __forceinline__ bool inside(int gy, int gx, int G)
     return gy >= 0 && gy < G && gx >= 0 && gx < G;
 }
 
-// Packed store of channels (i, 16 + i) of one pixel: bias, ReLU, and zero when
-// the pixel lies outside the grid (the next layer's zero padding).
-template <bool EDGE>
-__device__ __forceinline__ void store_pair(bf16* __restrict__ out, int pp, int i, float v0, float v1,
-                                           const float* __restrict__ bias, int gy, int gx, int G)
+// Channels (i, 16 + i) of one pixel as a packed BF16 pair after ReLU: the
+// pair is rounded to nearest even, then every half whose sign bit is set
+// (negative, or -0) becomes +0, which is the integer maximum of the bit
+// pattern with 0.  The result is ReLU of the rounded value, which equals the
+// rounded ReLU.
+__device__ __forceinline__ uint32_t relu_pair(float v0, float v1)
 {
-    float a = fmaxf(v0 + bias[i], 0.f), b = fmaxf(v1 + bias[16 + i], 0.f);
-    if (EDGE && !inside(gy, gx, G)) a = b = 0.f;
-    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-    bf16x2 pk;
-    pk[0] = (bf16)a;
-    pk[1] = (bf16)b;
-    *reinterpret_cast<bf16x2*>(out + pp * PXS + 2 * i) = pk;
+    const bf16x2 pk = __builtin_convertvector(f32x2{ v0, v1 }, bf16x2);
+    const s16x2 r = __builtin_elementwise_max(__builtin_bit_cast(s16x2, pk), s16x2{ 0, 0 });
+    return __builtin_bit_cast(uint32_t, r);
+}
+
+// Writes the 4 pixels (p0 .. p0 + 3 of an HO x WO region with grid origin
+// (oy0, ox0)) that lane (i, q) holds after a layer's M-block: ReLU pairs, and
+// zero for pixels outside the grid (the next layer's zero padding).
+template <int WO, bool EDGE>
+__device__ __forceinline__ void store_block(bf16* __restrict__ out, int p0, int i, const v4f& d0, const v4f& d1,
+                                            int oy0, int ox0, int G)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        uint32_t v = relu_pair(d0[r], d1[r]);
+        if (EDGE) {
+            const int p = p0 + r, gy = oy0 + p / WO, gx = ox0 + p % WO;
+            if (!inside(gy, gx, G)) v = 0;
+        }
+        *reinterpret_cast<uint32_t*>(out + (p0 + r) * PXS + 2 * i) = v;
+    }
 }
 
 // One 32 -> 32 layer over an HO x WO region (output origin (oy0, ox0) in the
 // grid) reading an (HO+2) x (WO+2) input region, all in LDS, pixel-major.
-// Wavefront w takes the contiguous M-blocks [w NMB / 4, (w+1) NMB / 4) and
-// works through them four at a time; the A operands of tap t+1 are read
-// while the matrix instructions of tap t issue.
-template <int HO, int WO, bool EDGE>
+// Wavefront w takes the BPW M-blocks [w BPW, (w+1) BPW) and works through
+// them MB at a time; the A operands of tap t+1 are read while the matrix
+// instructions of tap t issue.  Blocks past the region's last one are
+// computed on clamped pixels and not stored.
+template <int HO, int WO, int BPW, int MB, bool EDGE>
 __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* __restrict__ out,
-                                            const bf16x8 (&w)[9][2], const float* __restrict__ bias, int oy0,
-                                            int ox0, int G, int wave, int lane)
+                                            const bf16x8 (&w)[9][2], float blo, float bhi, int oy0, int ox0, int G,
+                                            int wave, int lane)
 {
     constexpr int WI = WO + 2, N = HO * WO, NMB = (N + 15) / 16;
     const int i = lane & 15, q = lane >> 4;
-    const int lo = wave * NMB / kWaves, hi = (wave + 1) * NMB / kWaves;
-    for (int g = lo; g < hi; g += 4) {
-        v4f acc[4][2];
-        int base[4];
+#pragma unroll 1
+    for (int g = wave * BPW; g < (wave + 1) * BPW; g += MB) {
+        v4f acc[MB][2];
+        int base[MB];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < MB; ++m) {
             const int p = min((g + m) * 16 + i, N - 1);
             base[m] = ((p / WO) * WI + p % WO) * PXS + 8 * q;
-            acc[m][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
-            acc[m][1] = acc[m][0];
+            acc[m][0] = v4f{ blo, blo, blo, blo };
+            acc[m][1] = v4f{ bhi, bhi, bhi, bhi };
         }
-        bf16x8 a[2][4];
+        bf16x8 a[2][MB];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) a[0][m] = *reinterpret_cast<const bf16x8*>(in + base[m]);
+        for (int m = 0; m < MB; ++m) a[0][m] = *reinterpret_cast<const bf16x8*>(in + base[m]);
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int cur = t & 1;
             if (t + 1 < 9) {
                 const int off = (((t + 1) / 3) * WI + (t + 1) % 3) * PXS;
 #pragma unroll
-                for (int m = 0; m < 4; ++m) a[cur ^ 1][m] = *reinterpret_cast<const bf16x8*>(in + base[m] + off);
+                for (int m = 0; m < MB; ++m) a[cur ^ 1][m] = *reinterpret_cast<const bf16x8*>(in + base[m] + off);
             }
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
+            for (int m = 0; m < MB; ++m) {
                 acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cur][m], w[t][0], acc[m][0], 0, 0, 0);
                 acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cur][m], w[t][1], acc[m][1], 0, 0, 0);
             }
         }
         // result: lane (i, q) holds region pixels (g + m) 16 + 4q + r, channels i and 16 + i
-        const int p0 = g * 16 + 4 * q;
-        int oy = p0 / WO, ox = p0 % WO;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (g + m < hi) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    store_pair<EDGE>(out, p0 + m * 16 + r, i, acc[m][0][r], acc[m][1][r], bias, oy0 + oy, ox0 + ox,
-                                     G);
-                    if (EDGE) {
-                        if (++ox == WO) { ox = 0; ++oy; }
-                    }
-                }
-                if (EDGE) {
-                    ox += 12;
-                    if (ox >= WO) { ox -= WO; ++oy; }
-                }
-            }
-        }
+        for (int m = 0; m < MB; ++m)
+            if (NMB % BPW == 0 || g + m < NMB)
+                store_block<WO, EDGE>(out, (g + m) * 16 + 4 * q, i, acc[m][0], acc[m][1], oy0, ox0, G);
     }
 }
 
@@ -178,15 +193,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     const float* __restrict__ b4, float* __restrict__ disp)
 {
     __shared__ __attribute__((aligned(16))) bf16 bufA[H1 * W1 * PXS];  // conv1 out, then conv3 out
-    static_assert(H1 * W1 >= (H3 * W3 + 63) / 64 * 64, "conv3 output fits in bufA");
-    // conv2 out, padded to whole groups of four M-blocks (conv32_bf16 stores them unguarded)
-    __shared__ __attribute__((aligned(16))) bf16 bufB[(H2 * W2 + 63) / 64 * 64 * PXS];
-    __shared__ float s_vel[2 * HV * WV];
+    static_assert(H1 * W1 >= NMB3 * 16, "conv3 output fits in bufA");
+    // conv2 out, padded to the last stored M-block
+    __shared__ __attribute__((aligned(16))) bf16 bufB[NMB2 * 16 * PXS];
+    __shared__ uint32_t s_vel[HV * WV];  // (u, v) of each velocity pixel as a packed BF16 pair
     __shared__ bf16x8 s_w1[P1];
     __shared__ bf16x8 s_w4[P4];
-    __shared__ float s_b[3 * C + 2];
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, q = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: block ranges stay scalar
     const int64_t GG = (int64_t)G * G;
 
     TileIter it(ntiles);
@@ -194,12 +209,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 
     for (int k = tid; k < P1; k += kThreads) s_w1[k] = packed[k];
     for (int k = tid; k < P4; k += kThreads) s_w4[k] = packed[P1 + 2 * P2 + k];
-    for (int k = tid; k < C; k += kThreads) {
-        s_b[k] = b1[k];
-        s_b[C + k] = b2[k];
-        s_b[2 * C + k] = b3[k];
-    }
-    if (tid < 2) s_b[3 * C + tid] = b4[tid];
     bf16x8 w2[9][2], w3[9][2];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
@@ -208,39 +217,44 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             w2[t][nb] = packed[P1 + (t * 2 + nb) * 64 + lane];
             w3[t][nb] = packed[P1 + P2 + (t * 2 + nb) * 64 + lane];
         }
+    // the bias of the lane's two output channels (i, 16 + i) in each hidden layer
+    const float b1lo = b1[i], b1hi = b1[16 + i], b2lo = b2[i], b2hi = b2[16 + i], b3lo = b3[i], b3hi = b3[16 + i];
+    const float b40 = b4[0], b41 = b4[1];
 
-    // conv1 gather: slot j of lane group q is k = 8q + j = 9 ci + tap, read at this offset from the
-    // pixel's top-left velocity sample; k >= 18 is a zero slot
-    // (zero slots read offset 0 and are scaled by 0: no branches around the loads)
-    int l1_off[8];
-    float l1_on[8];
+    // conv1 operand: slots j = 2 jj + ci of lane group q hold channel ci of tap 4q + jj, so the
+    // lane reads the packed (u, v) pair of four taps; taps past 8 meet zero weights and read the
+    // pixel itself (any finite value gives the same result)
+    int l1_off[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int k = 8 * q + j, ci = k / 9, t = k % 9;
-        l1_off[j] = k < 18 ? (ci * HV + t / 3) * WV + t % 3 : 0;
-        l1_on[j] = k < 18 ? 1.f : 0.f;
+    for (int jj = 0; jj < 4; ++jj) {
+        const int t = 4 * q + jj;
+        l1_off[jj] = t < 9 ? (t / 3) * WV + t % 3 : 0;
     }
 
-    float pv[VEL_PER_THREAD];
+    float pu[VEL_PER_THREAD], pw[VEL_PER_THREAD];
     auto fetch_vel = [&](int t) {
         const int y0 = (t / tiles_x) * OH - 4, x0 = (t % tiles_x) * OW - 4;
 #pragma unroll
         for (int k = 0; k < VEL_PER_THREAD; ++k) {
             const int e = tid + k * kThreads;
-            float v = 0.f;
-            if (e < 2 * HV * WV) {
-                const int c = e / (HV * WV), rem = e % (HV * WV);
-                const int gy = y0 + rem / WV, gx = x0 + rem % WV;
-                if (inside(gy, gx, G)) v = vel[c * GG + (int64_t)gy * G + gx];
+            float u = 0.f, v = 0.f;
+            if (e < HV * WV) {
+                const int gy = y0 + e / WV, gx = x0 + e % WV;
+                if (inside(gy, gx, G)) {
+                    const int64_t o = (int64_t)gy * G + gx;
+                    u = vel[o];
+                    v = vel[GG + o];
+                }
             }
-            pv[k] = v;
+            pu[k] = u;
+            pw[k] = v;
         }
     };
     auto stash_vel = [&]() {
 #pragma unroll
         for (int k = 0; k < VEL_PER_THREAD; ++k) {
             const int e = tid + k * kThreads;
-            if (e < 2 * HV * WV) s_vel[e] = pv[k];
+            if (e < HV * WV) s_vel[e] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{ pu[k], pw[k] }, bf16x2));
         }
     };
     fetch_vel(it.t);
@@ -253,41 +267,30 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         // tiles whose velocity halo lies inside the grid need no zero-padding tests
         const bool edge = ty0 < 4 || tx0 < 4 || ty0 + OH + 4 > G || tx0 + OW + 4 > G;
 
-        // conv1 on the 20 x 36 region: K = 18 (2 channels x 9 taps) padded to 32
-        {
-            constexpr int N = H1 * W1, NMB = N / 16;
-            static_assert(N % 16 == 0, "conv1 region is whole M-blocks");
-            const int lo = wave * NMB / kWaves, hi = (wave + 1) * NMB / kWaves;
-            for (int g = lo; g < hi; g += 4) {
-                // four M-blocks at once: all gathers issue before the first matrix instruction
-                bf16x8 a[4];
+        // conv1 on the 20 x 36 region: K = 18 (9 taps x 2 channels) padded to 32
+#pragma unroll 1
+        for (int g = wave * BPW1; g < (wave + 1) * BPW1; g += MB1) {
+            // MB1 M-blocks at once: all reads issue before the first matrix instruction
+            bf16x8 a[MB1];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int p = min((g + m) * 16 + i, N - 1);
-                    const int pbase = (p / W1) * WV + p % W1;
+            for (int m = 0; m < MB1; ++m) {
+                const int p = min((g + m) * 16 + i, H1 * W1 - 1);
+                const int pbase = (p / W1) * WV + p % W1;
+                u32x4 v;
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) a[m][j] = (bf16)(s_vel[pbase + l1_off[j]] * l1_on[j]);
-                }
-                v4f d[4][2];
+                for (int jj = 0; jj < 4; ++jj) v[jj] = s_vel[pbase + l1_off[jj]];
+                a[m] = __builtin_bit_cast(bf16x8, v);
+            }
+            const bf16x8 w1lo = s_w1[lane], w1hi = s_w1[64 + lane];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    d[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], s_w1[lane], v4f{ 0.f, 0.f, 0.f, 0.f }, 0, 0, 0);
-                    d[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], s_w1[64 + lane], v4f{ 0.f, 0.f, 0.f, 0.f }, 0,
-                                                                      0, 0);
-                }
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    if (g + m >= hi) break;
-                    const int p0 = (g + m) * 16 + 4 * q;
-                    int oy = p0 / W1, ox = p0 % W1;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        if (edge)
-                            store_pair<true>(bufA, p0 + r, i, d[m][0][r], d[m][1][r], s_b, ty0 - 3 + oy, tx0 - 3 + ox, G);
-                        else
-                            store_pair<false>(bufA, p0 + r, i, d[m][0][r], d[m][1][r], s_b, 0, 0, G);
-                        if (++ox == W1) { ox = 0; ++oy; }
-                    }
+            for (int m = 0; m < MB1; ++m) {
+                const v4f d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], w1lo, v4f{ b1lo, b1lo, b1lo, b1lo }, 0, 0, 0);
+                const v4f d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], w1hi, v4f{ b1hi, b1hi, b1hi, b1hi }, 0, 0, 0);
+                if (NMB1 % BPW1 == 0 || g + m < NMB1) {
+                    if (edge)
+                        store_block<W1, true>(bufA, (g + m) * 16 + 4 * q, i, d0, d1, ty0 - 3, tx0 - 3, G);
+                    else
+                        store_block<W1, false>(bufA, (g + m) * 16 + 4 * q, i, d0, d1, 0, 0, G);
                 }
             }
         }
@@ -297,15 +300,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         if (next < it.end) fetch_vel(next);  // lands while conv2-conv4 run
 
         if (edge)
-            conv32_bf16<H2, W2, true>(bufA, bufB, w2, s_b + C, ty0 - 2, tx0 - 2, G, wave, lane);
+            conv32_bf16<H2, W2, BPW2, MB2, true>(bufA, bufB, w2, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave, lane);
         else
-            conv32_bf16<H2, W2, false>(bufA, bufB, w2, s_b + C, ty0 - 2, tx0 - 2, G, wave, lane);
+            conv32_bf16<H2, W2, BPW2, MB2, false>(bufA, bufB, w2, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave, lane);
         __syncthreads();
         if (next < it.end) stash_vel();
         if (edge)
-            conv32_bf16<H3, W3, true>(bufB, bufA, w3, s_b + 2 * C, ty0 - 1, tx0 - 1, G, wave, lane);
+            conv32_bf16<H3, W3, BPW3, MB3, true>(bufB, bufA, w3, b3lo, b3hi, ty0 - 1, tx0 - 1, G, wave, lane);
         else
-            conv32_bf16<H3, W3, false>(bufB, bufA, w3, s_b + 2 * C, ty0 - 1, tx0 - 1, G, wave, lane);
+            conv32_bf16<H3, W3, BPW3, MB3, false>(bufB, bufA, w3, b3lo, b3hi, ty0 - 1, tx0 - 1, G, wave, lane);
         __syncthreads();
 
         // conv4 as a contraction: for every pixel p of the 16 x 32 conv3 region,
@@ -314,8 +317,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         // only by the wave that computes the block, before its results exist.  Then each output
         // pixel sums its 9 taps.
         {
-            constexpr int NMB3 = H3 * W3 / 16, ZS = PXS / 2;  // 32 blocks; floats per pixel
-            static_assert(H3 * W3 % 16 == 0, "conv3 region is whole M-blocks");
+            constexpr int ZS = PXS / 2;  // floats per pixel
             float* zf = reinterpret_cast<float*>(bufA);
             for (int mb = wave; mb < NMB3; mb += kWaves) {
                 const bf16x8 a = *reinterpret_cast<const bf16x8*>(bufA + (mb * 16 + i) * PXS + 8 * q);
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             __syncthreads();
             for (int e = tid; e < OH * OW; e += kThreads) {
                 const int oy = e / OW, ox = e - oy * OW;
-                float d0 = s_b[3 * C], d1 = s_b[3 * C + 1];
+                float d0 = b40, d1 = b41;
 #pragma unroll
                 for (int t = 0; t < 9; ++t) {
                     const float* zp = zf + ((oy + t / 3) * W3 + ox + t % 3) * ZS;
