@@ -141,16 +141,25 @@ __device__ __forceinline__ void store_block(bf16* __restrict__ out, int p0, int 
 // One 32 -> 32 layer over an HO x WO region (output origin (oy0, ox0) in the
 // grid) reading an (HO+2) x (WO+2) input region, all in LDS, pixel-major.
 // Wavefront w takes the BPW M-blocks [w BPW, (w+1) BPW) and works through
-// them MB at a time; the A operands of tap t+1 are read while the matrix
-// instructions of tap t issue.  Blocks past the region's last one are
+// them MB at a time; the A operands of the next two taps are read while the
+// matrix instructions of the current one issue.  Blocks past the region's last one are
 // computed on clamped pixels and not stored.
 template <int HO, int WO, int BPW, int MB, bool EDGE>
 __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* __restrict__ out,
-                                            const bf16x8 (&w)[9][2], float blo, float bhi, int oy0, int ox0, int G,
-                                            int wave, int lane)
+                                            const bf16x8* __restrict__ sw, float blo, float bhi, int oy0, int ox0,
+                                            int G, int wave, int lane)
 {
     constexpr int WI = WO + 2, N = HO * WO, NMB = (N + 15) / 16;
     const int i = lane & 15, q = lane >> 4;
+    // the layer's B operands, read from LDS on every call: an offset the compiler cannot see
+    // through keeps it from holding both layers' weights in registers across the tile loop
+    int wl = lane;
+    asm volatile("" : "+v"(wl));
+    bf16x8 w[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) w[t][nb] = sw[(t * 2 + nb) * 64 + wl];
 #pragma unroll 1
     for (int g = wave * BPW; g < (wave + 1) * BPW; g += MB) {
         v4f acc[MB][2];
@@ -162,22 +171,31 @@ __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* _
             acc[m][0] = v4f{ blo, blo, blo, blo };
             acc[m][1] = v4f{ bhi, bhi, bhi, bhi };
         }
-        bf16x8 a[2][MB];
+        // operands of taps t+1 and t+2 are in flight while tap t's instructions issue
+        constexpr int PF = 2;
+        static_assert(PF * MB <= 15, "outstanding LDS reads fit the wait counter");
+        auto tap_off = [](int t) { return ((t / 3) * WI + t % 3) * PXS; };
+        bf16x8 a[PF + 1][MB];
 #pragma unroll
-        for (int m = 0; m < MB; ++m) a[0][m] = *reinterpret_cast<const bf16x8*>(in + base[m]);
+        for (int t = 0; t < PF; ++t)
+#pragma unroll
+            for (int m = 0; m < MB; ++m) a[t][m] = *reinterpret_cast<const bf16x8*>(in + base[m] + tap_off(t));
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const int cur = t & 1;
-            if (t + 1 < 9) {
-                const int off = (((t + 1) / 3) * WI + (t + 1) % 3) * PXS;
+            const int cur = t % (PF + 1);
+            if (t + PF < 9) {
 #pragma unroll
-                for (int m = 0; m < MB; ++m) a[cur ^ 1][m] = *reinterpret_cast<const bf16x8*>(in + base[m] + off);
+                for (int m = 0; m < MB; ++m)
+                    a[(t + PF) % (PF + 1)][m] = *reinterpret_cast<const bf16x8*>(in + base[m] + tap_off(t + PF));
             }
+            // keep the reads ahead of the instructions (the scheduler would sink them to their use)
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int m = 0; m < MB; ++m) {
                 acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cur][m], w[t][0], acc[m][0], 0, 0, 0);
                 acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cur][m], w[t][1], acc[m][1], 0, 0, 0);
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
         // result: lane (i, q) holds region pixels (g + m) 16 + 4q + r, channels i and 16 + i
 #pragma unroll
@@ -199,6 +217,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     __shared__ uint32_t s_vel[HV * WV];  // (u, v) of each velocity pixel as a packed BF16 pair
     __shared__ bf16x8 s_w1[P1];
     __shared__ bf16x8 s_w4[P4];
+    __shared__ bf16x8 s_w23[2 * P2];  // conv2 then conv3: [layer][tap][nb][lane]
 
     const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: block ranges stay scalar
@@ -209,14 +228,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 
     for (int k = tid; k < P1; k += kThreads) s_w1[k] = packed[k];
     for (int k = tid; k < P4; k += kThreads) s_w4[k] = packed[P1 + 2 * P2 + k];
-    bf16x8 w2[9][2], w3[9][2];
-#pragma unroll
-    for (int t = 0; t < 9; ++t)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-            w2[t][nb] = packed[P1 + (t * 2 + nb) * 64 + lane];
-            w3[t][nb] = packed[P1 + P2 + (t * 2 + nb) * 64 + lane];
-        }
+    for (int k = tid; k < 2 * P2; k += kThreads) s_w23[k] = packed[P1 + k];
     // the bias of the lane's two output channels (i, 16 + i) in each hidden layer
     const float b1lo = b1[i], b1hi = b1[16 + i], b2lo = b2[i], b2hi = b2[16 + i], b3lo = b3[i], b3hi = b3[16 + i];
     const float b40 = b4[0], b41 = b4[1];
@@ -282,15 +294,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
                 a[m] = __builtin_bit_cast(bf16x8, v);
             }
             const bf16x8 w1lo = s_w1[lane], w1hi = s_w1[64 + lane];
+            // every block's instructions issue before the first result is read back
+            v4f d[MB1][2];
 #pragma unroll
             for (int m = 0; m < MB1; ++m) {
-                const v4f d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], w1lo, v4f{ b1lo, b1lo, b1lo, b1lo }, 0, 0, 0);
-                const v4f d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], w1hi, v4f{ b1hi, b1hi, b1hi, b1hi }, 0, 0, 0);
+                d[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], w1lo, v4f{ b1lo, b1lo, b1lo, b1lo }, 0, 0, 0);
+                d[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], w1hi, v4f{ b1hi, b1hi, b1hi, b1hi }, 0, 0, 0);
+            }
+#pragma unroll
+            for (int m = 0; m < MB1; ++m) {
                 if (NMB1 % BPW1 == 0 || g + m < NMB1) {
                     if (edge)
-                        store_block<W1, true>(bufA, (g + m) * 16 + 4 * q, i, d0, d1, ty0 - 3, tx0 - 3, G);
+                        store_block<W1, true>(bufA, (g + m) * 16 + 4 * q, i, d[m][0], d[m][1], ty0 - 3, tx0 - 3, G);
                     else
-                        store_block<W1, false>(bufA, (g + m) * 16 + 4 * q, i, d0, d1, 0, 0, G);
+                        store_block<W1, false>(bufA, (g + m) * 16 + 4 * q, i, d[m][0], d[m][1], 0, 0, G);
                 }
             }
         }
@@ -300,15 +317,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         if (next < it.end) fetch_vel(next);  // lands while conv2-conv4 run
 
         if (edge)
-            conv32_bf16<H2, W2, BPW2, MB2, true>(bufA, bufB, w2, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave, lane);
+            conv32_bf16<H2, W2, BPW2, MB2, true>(bufA, bufB, s_w23, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave, lane);
         else
-            conv32_bf16<H2, W2, BPW2, MB2, false>(bufA, bufB, w2, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave, lane);
+            conv32_bf16<H2, W2, BPW2, MB2, false>(bufA, bufB, s_w23, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave, lane);
         __syncthreads();
         if (next < it.end) stash_vel();
         if (edge)
-            conv32_bf16<H3, W3, BPW3, MB3, true>(bufB, bufA, w3, b3lo, b3hi, ty0 - 1, tx0 - 1, G, wave, lane);
+            conv32_bf16<H3, W3, BPW3, MB3, true>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G, wave, lane);
         else
-            conv32_bf16<H3, W3, BPW3, MB3, false>(bufB, bufA, w3, b3lo, b3hi, ty0 - 1, tx0 - 1, G, wave, lane);
+            conv32_bf16<H3, W3, BPW3, MB3, false>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G, wave, lane);
         __syncthreads();
 
         // conv4 as a contraction: for every pixel p of the 16 x 32 conv3 region,
