@@ -16,7 +16,8 @@
 // padded to one K = 32 step, its K ordered tap-major so that a lane's operand
 // is four (u, v) pairs read straight from LDS; conv4 (N = 2) computes, per
 // conv3 pixel, its 18 (output channel, tap) contributions (two N-blocks of one
-// K = 32 instruction each) and then sums 9 taps per output pixel.  Biases
+// K = 32 instruction each) into the conv2 buffer, free by then, and sums 9
+// taps per output pixel.  Biases
 // enter as the accumulators' initial values, and ReLU acts on the rounded
 // BF16 pair (rounding to nearest keeps the sign, so the order of the two does
 // not change the result).
@@ -329,34 +330,32 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         __syncthreads();
 
         // conv4 as a contraction: for every pixel p of the 16 x 32 conv3 region,
-        // Z[p][9 o + t] = sum_c act3[p][c] w4[o][c][t] (one K = 32 instruction per 16 pixels and
-        // N-block), written in FP32 over the pixel's own 80 bytes: a block's pixels are read
-        // only by the wave that computes the block, before its results exist.  Then each output
-        // pixel sums its 9 taps.
+        // Z[9 o + t][p] = sum_c act3[p][c] w4[o][c][t] (one K = 32 instruction per 16 pixels and
+        // N-block), in FP32, column-major in the conv2 buffer (no longer read): a lane's four
+        // results are four consecutive pixels of one column, one 16-byte store.  Then each output
+        // pixel sums its 9 taps; the lanes of a wavefront read consecutive pixels of one column,
+        // and the column stride (532 floats) spreads a store's 16 columns over distinct banks.
         {
-            constexpr int ZS = PXS / 2;  // floats per pixel
-            float* zf = reinterpret_cast<float*>(bufA);
+            constexpr int ZC = 532;
+            static_assert(18 * ZC * sizeof(float) <= sizeof(bufB) && ZC >= H3 * W3 && ZC % 4 == 0, "Z fits");
+            float* zb = reinterpret_cast<float*>(bufB);
             for (int mb = wave; mb < NMB3; mb += kWaves) {
                 const bf16x8 a = *reinterpret_cast<const bf16x8*>(bufA + (mb * 16 + i) * PXS + 8 * q);
                 const v4f z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, s_w4[lane], v4f{ 0.f, 0.f, 0.f, 0.f }, 0, 0, 0);
                 const v4f z1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, s_w4[64 + lane], v4f{ 0.f, 0.f, 0.f, 0.f }, 0,
                                                                        0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float* zp = zf + (mb * 16 + 4 * q + r) * ZS;
-                    zp[i] = z0[r];
-                    if (i < 2) zp[16 + i] = z1[r];
-                }
+                *reinterpret_cast<v4f*>(zb + i * ZC + mb * 16 + 4 * q) = z0;
+                if (i < 2) *reinterpret_cast<v4f*>(zb + (16 + i) * ZC + mb * 16 + 4 * q) = z1;
             }
             __syncthreads();
             for (int e = tid; e < OH * OW; e += kThreads) {
                 const int oy = e / OW, ox = e - oy * OW;
+                const float* zp = zb + oy * W3 + ox;
                 float d0 = b40, d1 = b41;
 #pragma unroll
                 for (int t = 0; t < 9; ++t) {
-                    const float* zp = zf + ((oy + t / 3) * W3 + ox + t % 3) * ZS;
-                    d0 += zp[t];
-                    d1 += zp[9 + t];
+                    d0 += zp[t * ZC + (t / 3) * W3 + t % 3];
+                    d1 += zp[(9 + t) * ZC + (t / 3) * W3 + t % 3];
                 }
                 const int gy = ty0 + oy, gx = tx0 + ox;
                 if (gy < G && gx < G) {
