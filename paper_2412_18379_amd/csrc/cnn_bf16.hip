@@ -34,7 +34,7 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;  // 4 wavefronts, one per SIMD
+constexpr int kThreads = 512;  // 8 wavefronts, two per SIMD
 constexpr int kWaves = kThreads / 64;
 constexpr int C = 32;
 constexpr int OH = 14, OW = 30;            // output tile
@@ -45,9 +45,9 @@ constexpr int HV = OH + 8, WV = OW + 8;    // velocity tile (22 x 38)
 constexpr int PXS = 40;                    // bf16 per pixel in LDS (32 channels + 8 pad: 80 bytes)
 constexpr int VEL_PER_THREAD = (HV * WV + kThreads - 1) / kThreads;  // velocity pixels per thread
 // M-blocks of 16 pixels per wavefront, and how many of them are in flight at once
-constexpr int NMB1 = H1 * W1 / 16, BPW1 = (NMB1 + kWaves - 1) / kWaves, MB1 = 6;
-constexpr int NMB2 = (H2 * W2 + 15) / 16, BPW2 = (NMB2 + kWaves - 1) / kWaves, MB2 = 5;
-constexpr int NMB3 = H3 * W3 / 16, BPW3 = NMB3 / kWaves, MB3 = 4;
+constexpr int NMB1 = H1 * W1 / 16, BPW1 = (NMB1 + kWaves - 1) / kWaves, MB1 = BPW1;
+constexpr int NMB2 = (H2 * W2 + 15) / 16, BPW2 = (NMB2 + kWaves - 1) / kWaves, MB2 = BPW2;
+constexpr int NMB3 = H3 * W3 / 16, BPW3 = NMB3 / kWaves, MB3 = BPW3;
 static_assert(H1 * W1 % 16 == 0 && H3 * W3 % 16 == 0 && NMB3 % kWaves == 0, "whole M-blocks");
 static_assert(BPW1 % MB1 == 0 && BPW2 % MB2 == 0 && BPW3 % MB3 == 0, "whole groups per wavefront");
 
@@ -142,8 +142,8 @@ __device__ __forceinline__ void store_block(bf16* __restrict__ out, int p0, int 
 // One 32 -> 32 layer over an HO x WO region (output origin (oy0, ox0) in the
 // grid) reading an (HO+2) x (WO+2) input region, all in LDS, pixel-major.
 // Wavefront w takes the BPW M-blocks [w BPW, (w+1) BPW) and works through
-// them MB at a time; the A operands of the next two taps are read while the
-// matrix instructions of the current one issue.  Blocks past the region's last one are
+// them MB at a time; the A and B operands of the next two taps are read while
+// the matrix instructions of the current one issue.  Blocks past the region's last one are
 // computed on clamped pixels and not stored.
 template <int HO, int WO, int BPW, int MB, bool EDGE>
 __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* __restrict__ out,
@@ -152,17 +152,13 @@ __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* _
 {
     constexpr int WI = WO + 2, N = HO * WO, NMB = (N + 15) / 16;
     const int i = lane & 15, q = lane >> 4;
-    // the layer's B operands, read from LDS on every call: an offset the compiler cannot see
-    // through keeps it from holding both layers' weights in registers across the tile loop
-    int wl = lane;
+    int wl = lane;  // opaque to the compiler: the weights are read per tap, not held across calls
     asm volatile("" : "+v"(wl));
-    bf16x8 w[9][2];
-#pragma unroll
-    for (int t = 0; t < 9; ++t)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) w[t][nb] = sw[(t * 2 + nb) * 64 + wl];
+    // first block, opaque so that its addresses are recomputed per call, not held across tiles
+    int g0 = wave * BPW;
+    asm volatile("" : "+s"(g0));
 #pragma unroll 1
-    for (int g = wave * BPW; g < (wave + 1) * BPW; g += MB) {
+    for (int g = g0; g < g0 + BPW; g += MB) {
         v4f acc[MB][2];
         int base[MB];
 #pragma unroll
@@ -172,29 +168,29 @@ __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* _
             acc[m][0] = v4f{ blo, blo, blo, blo };
             acc[m][1] = v4f{ bhi, bhi, bhi, bhi };
         }
-        // operands of taps t+1 and t+2 are in flight while tap t's instructions issue
+        // operands (and weights) of taps t+1 and t+2 are in flight while tap t's instructions issue
         constexpr int PF = 2;
-        static_assert(PF * MB <= 15, "outstanding LDS reads fit the wait counter");
+        static_assert(PF * (MB + 2) <= 15, "outstanding LDS reads fit the wait counter");
         auto tap_off = [](int t) { return ((t / 3) * WI + t % 3) * PXS; };
-        bf16x8 a[PF + 1][MB];
+        bf16x8 a[PF + 1][MB], w[PF + 1][2];
+        auto fetch = [&](int t, int slot) {
 #pragma unroll
-        for (int t = 0; t < PF; ++t)
+            for (int m = 0; m < MB; ++m) a[slot][m] = *reinterpret_cast<const bf16x8*>(in + base[m] + tap_off(t));
+            w[slot][0] = sw[(t * 2) * 64 + wl];
+            w[slot][1] = sw[(t * 2 + 1) * 64 + wl];
+        };
 #pragma unroll
-            for (int m = 0; m < MB; ++m) a[t][m] = *reinterpret_cast<const bf16x8*>(in + base[m] + tap_off(t));
+        for (int t = 0; t < PF; ++t) fetch(t, t);
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int cur = t % (PF + 1);
-            if (t + PF < 9) {
-#pragma unroll
-                for (int m = 0; m < MB; ++m)
-                    a[(t + PF) % (PF + 1)][m] = *reinterpret_cast<const bf16x8*>(in + base[m] + tap_off(t + PF));
-            }
+            if (t + PF < 9) fetch(t + PF, (t + PF) % (PF + 1));
             // keep the reads ahead of the instructions (the scheduler would sink them to their use)
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int m = 0; m < MB; ++m) {
-                acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cur][m], w[t][0], acc[m][0], 0, 0, 0);
-                acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cur][m], w[t][1], acc[m][1], 0, 0, 0);
+                acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cur][m], w[cur][0], acc[m][0], 0, 0, 0);
+                acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cur][m], w[cur][1], acc[m][1], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -206,7 +202,7 @@ __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* _
     }
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_cnn_bf16(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_cnn_bf16(
     int32_t G, int tiles_x, int ntiles, const float* __restrict__ vel, const bf16x8* __restrict__ packed,
     const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3,
     const float* __restrict__ b4, float* __restrict__ disp)
@@ -281,8 +277,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         const bool edge = ty0 < 4 || tx0 < 4 || ty0 + OH + 4 > G || tx0 + OW + 4 > G;
 
         // conv1 on the 20 x 36 region: K = 18 (9 taps x 2 channels) padded to 32
+        int g1 = wave * BPW1;  // opaque, as in conv32_bf16
+        asm volatile("" : "+s"(g1));
 #pragma unroll 1
-        for (int g = wave * BPW1; g < (wave + 1) * BPW1; g += MB1) {
+        for (int g = g1; g < g1 + BPW1; g += MB1) {
             // MB1 M-blocks at once: all reads issue before the first matrix instruction
             bf16x8 a[MB1];
 #pragma unroll
