@@ -284,8 +284,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) bias2[nb][r] = b2[16 * nb + 4 * q + r];
-    // conv1 B operands: k-step s, slot q holds k = 4s + q = 9 ci + tap (zero for k >= 18)
-    float bw1[5][2], bias1[2];
+    // conv1 A operands (the weights): in k-step s lane (i, q) supplies output channel 16 nb + i at
+    // k = 4s + q = 9 ci + tap (zero for k >= 18).  The gathered inputs are the B operands, so a
+    // lane receives four consecutive output channels 16 nb + 4q + r of one pixel, and the
+    // accumulators start from those channels' biases.
+    float bw1[5][2];
+    v4f bias1[2];
 #pragma unroll
     for (int s = 0; s < 5; ++s)
 #pragma unroll
@@ -293,9 +297,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             const int k = 4 * s + q, o = nb * 16 + i;
             bw1[s][nb] = k < 18 ? w1[(o * 2 + k / 9) * 9 + k % 9] : 0.f;
         }
-    bias1[0] = b1[i];
-    bias1[1] = b1[16 + i];
-    // conv1 A operands: k-step s of lane (i, q) reads s_vel at the pixel's base plus a
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bias1[nb][r] = b1[16 * nb + 4 * q + r];
+    // conv1 B operands: k-step s of lane (i, q) reads s_vel at the pixel's base plus a
     // per-lane constant offset (channel k / 9, tap k % 9); slots k >= 18 read the pixel
     // itself and are zeroed by a select
     int l1_off[5];
@@ -349,22 +355,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
                 a[s] = l1_on[s] ? v : 0.f;
             }
         };
-        // result rows 4q .. 4q+3 of a block: tile pixels pp0 .. pp0+3 (the last block's
-        // pixels past the tile land in the padding of s_in)
+        // result of a block: lane (i, q) holds channels 16 nb + 4q .. +3 of tile pixel 16 mb + i,
+        // written as two 16-byte runs (the last block's pixels past the tile land in the padding
+        // of s_in)
         auto conv1_store = [&](int mb, const v4f& d0, const v4f& d1) {
-            const int pp0 = mb * 16 + 4 * q;
-            int oy = pp0 / IW, ox = pp0 - oy * IW;
+            const int p = mb * 16 + i, oy = p / IW, ox = p - oy * IW;
+            const int gy = y0 - 1 + oy, gx = x0 - 1 + ox;
+            const bool in = (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G;
+            v4f v0, v1;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int gy = y0 - 1 + oy, gx = x0 - 1 + ox;
-                const bool in = (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G;
-                s_in[(pp0 + r) * PS + i] = in ? fmaxf(d0[r] + bias1[0], 0.f) : 0.f;
-                s_in[(pp0 + r) * PS + 16 + i] = in ? fmaxf(d1[r] + bias1[1], 0.f) : 0.f;
-                if (++ox == IW) {
-                    ox = 0;
-                    ++oy;
-                }
+                v0[r] = in ? fmaxf(d0[r], 0.f) : 0.f;
+                v1[r] = in ? fmaxf(d1[r], 0.f) : 0.f;
             }
+            *reinterpret_cast<v4f*>(s_in + p * PS + 4 * q) = v0;
+            *reinterpret_cast<v4f*>(s_in + p * PS + 16 + 4 * q) = v1;
         };
         {
             // all of the wave's blocks at once (w, w + 4, ..., at most 10): every gather issues
@@ -376,15 +381,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             v4f d[NB1][2];
 #pragma unroll
             for (int u = 0; u < NB1; ++u) {
-                d[u][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
-                d[u][1] = d[u][0];
+                d[u][0] = bias1[0];
+                d[u][1] = bias1[1];
             }
 #pragma unroll
             for (int s = 0; s < 5; ++s)
 #pragma unroll
                 for (int u = 0; u < NB1; ++u) {
-                    d[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s], bw1[s][0], d[u][0], 0, 0, 0);
-                    d[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s], bw1[s][1], d[u][1], 0, 0, 0);
+                    d[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(bw1[s][0], a[u][s], d[u][0], 0, 0, 0);
+                    d[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(bw1[s][1], a[u][s], d[u][1], 0, 0, 0);
                 }
 #pragma unroll
             for (int u = 0; u < NB1; ++u)
