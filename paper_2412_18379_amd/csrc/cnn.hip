@@ -4,13 +4,16 @@
 // with the overlay velocity).  Cross-correlation with OIHW weights:
 //   y[o][r][c] = b[o] + sum_i sum_{dy,dx} w[o][i][dy+1][dx+1] x[i][r+dy][c+dx].
 //
-// Two fused FP32 kernels per forward pass, both persistent (one block of 4
-// wavefronts per compute unit, one wavefront per SIMD so each may hold 512
-// registers) looping over tiles:
-//   conv12: conv1 (K = 18 padded to 20) on the matrix cores into LDS on the
-//           16 x 32 tile plus a one-pixel border, then conv2, stored from
-//           registers as the 32-channel activation, pixel-major ([G][G][32]).
-//   conv34: conv3 on a 16 x 32 region (the 14 x 30 output tile plus a
+// Two fused FP32 kernels per forward pass, both persistent (one block per
+// compute unit) looping over tiles:
+//   conv12: 8 wavefronts, two per SIMD, each owning one row of conv2's 2 x 2
+//           output blocks (under 256 registers each): conv1 (K = 18 padded
+//           to 20) on the matrix cores into LDS on the 16 x 32 tile plus a
+//           one-pixel border, then conv2, stored from registers as the
+//           32-channel activation, pixel-major ([G][G][32]).
+//   conv34: 4 wavefronts, one per SIMD (each may hold 512 registers, which
+//           its two rows of conv3 blocks and the conv4 operands use):
+//           conv3 on a 16 x 32 region (the 14 x 30 output tile plus a
 //           one-pixel border); its results feed conv4 (N = 2) in registers:
 //           per region pixel, its 18 (output channel, tap) contributions on
 //           the matrix cores, kept in LDS, then a 9-term sum per output pixel;
@@ -52,6 +55,10 @@ constexpr int NIN_PAD = L1_MBLOCKS * 16;     // conv1's 39 M-blocks write whole 
 static_assert(NU == 16 * C * C, "transformed weights cover the whole layer");
 static_assert(NREG * PS <= NIN * PS, "output tile aliases the input tile");
 static_assert(kWaves * 4 == RH, "each wavefront takes two rows of 2 x 2 output blocks");
+constexpr int kThreads12 = 512;  // conv12: 8 wavefronts, two per SIMD, one row of 2 x 2 blocks each
+constexpr int kWaves12 = kThreads12 / 64;
+static_assert(kWaves12 * 2 == RH, "one row of 2 x 2 output blocks per wavefront");
+constexpr int VEL_PER_THREAD12 = (2 * VH * VW + kThreads12 - 1) / kThreads12;
 static_assert(RW == 32, "a row of 2 x 2 output blocks is one 16-row matrix block");
 
 // Winograd F(2x2, 3x3) for one 2 x 2 output block:
@@ -237,12 +244,67 @@ __device__ __forceinline__ void conv32_wino(const float* __restrict__ s_in, cons
     }
 }
 
+// conv 32 -> 32 (no bias) for the single block row ty of the region (region
+// rows 2 ty, 2 ty + 1), the form used when each of eight wavefronts owns one
+// row: the same contraction as conv32_wino, without its cross-round
+// prefetch (the second wavefront of the SIMD covers the waits), so that a
+// wavefront needs under 256 registers.  emit(y) receives the results as in
+// conv32_wino.
+template <class Emit>
+__device__ __forceinline__ void conv32_wino_row(const float* __restrict__ s_in, const float* __restrict__ s_u,
+                                                int ty, int lane, Emit&& emit)
+{
+    const int tx = lane & 15, g = lane >> 4;
+    const v4f* su = reinterpret_cast<const v4f*>(s_u) + lane;
+    v4f acc[16][2];
+#pragma unroll
+    for (int xn = 0; xn < 16; ++xn) {
+        acc[xn][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
+        acc[xn][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        v4f d[4][4];
+        wino_patch(s_in, ty, tx, g, h, d);
+        wino_input_transform(d);
+#pragma unroll
+        for (int grp = 0; grp < 4; ++grp) {
+            v4f bc[4][2];
+            wino_weights(su, grp, h, bc);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const int xn = 4 * grp + x;
+                    const float a = d[xn >> 2][xn & 3][j];
+                    acc[xn][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][0][j], a, acc[xn][0], 0, 0, 0);
+                    acc[xn][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][1][j], a, acc[xn][1], 0, 0, 0);
+                }
+        }
+    }
+    v4f y[4][2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        v4f m0[4], m1[4];
+#pragma unroll
+        for (int nu = 0; nu < 4; ++nu) {
+            m0[nu] = acc[nu][nb] + acc[4 + nu][nb] + acc[8 + nu][nb];
+            m1[nu] = acc[4 + nu][nb] - acc[8 + nu][nb] - acc[12 + nu][nb];
+        }
+        y[0][nb] = m0[0] + m0[1] + m0[2];
+        y[1][nb] = m0[1] - m0[2] - m0[3];
+        y[2][nb] = m1[0] + m1[1] + m1[2];
+        y[3][nb] = m1[1] - m1[2] - m1[3];
+    }
+    emit(y);
+}
+
 // Block loads of the transformed 32->32 weights into LDS.
 __device__ __forceinline__ void load_u(const float* __restrict__ u, float* __restrict__ s_u)
 {
     const v4f* src = reinterpret_cast<const v4f*>(u);
     v4f* dst = reinterpret_cast<v4f*>(s_u);
-    for (int k = threadIdx.x; k < NU / 4; k += kThreads) dst[k] = src[k];
+    for (int k = threadIdx.x; k < NU / 4; k += blockDim.x) dst[k] = src[k];
 }
 
 // Persistent tile loop.  Tiles (row-major) are split into 8 contiguous
@@ -262,7 +324,7 @@ struct TileIter {
 };
 
 // conv1 + ReLU (matrix cores, into LDS) then conv2 + ReLU -> act2 [G][G][32].
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_conv12_f32(
+__global__ __launch_bounds__(kThreads12) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_conv12_f32(
     int32_t G, int tiles_x, int ntiles, const float* __restrict__ vel, const float* __restrict__ w1,
     const float* __restrict__ b1, const float* __restrict__ u2, const float* __restrict__ b2,
     float* __restrict__ act2)
@@ -271,55 +333,52 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     __shared__ __attribute__((aligned(16))) float s_u[NU];
     __shared__ float s_vel[2 * VH * VW];
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, q = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t GG = (int64_t)G * G;
 
     TileIter it(ntiles);
     if (it.t >= it.end) return;
 
     load_u(u2, s_u);
-    // conv2 biases of the lane's output channels 16 nb + 4q + r
-    v4f bias2[2];
+    // conv1's operands and conv2's biases are (re)loaded on every tile, from an index the
+    // compiler cannot see through, so that none of them occupies registers during conv2
+    auto conv1_setup = [&](float (&bw1)[5][2], v4f (&bias1)[2], int (&l1_off)[5], bool (&l1_on)[5]) {
+        int qq = q;
+        asm volatile("" : "+v"(qq));
+        // A operands (the weights): in k-step s lane (i, q) supplies output channel 16 nb + i at
+        // k = 4s + q = 9 ci + tap (zero for k >= 18).  The gathered inputs are the B operands,
+        // so a lane receives four consecutive output channels 16 nb + 4q + r of one pixel, and
+        // the accumulators start from those channels' biases.
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+        for (int s = 0; s < 5; ++s)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) bias2[nb][r] = b2[16 * nb + 4 * q + r];
-    // conv1 A operands (the weights): in k-step s lane (i, q) supplies output channel 16 nb + i at
-    // k = 4s + q = 9 ci + tap (zero for k >= 18).  The gathered inputs are the B operands, so a
-    // lane receives four consecutive output channels 16 nb + 4q + r of one pixel, and the
-    // accumulators start from those channels' biases.
-    float bw1[5][2];
-    v4f bias1[2];
+            for (int nb = 0; nb < 2; ++nb) {
+                const int k = 4 * s + qq, o = nb * 16 + i;
+                bw1[s][nb] = k < 18 ? w1[(o * 2 + k / 9) * 9 + k % 9] : 0.f;
+            }
 #pragma unroll
-    for (int s = 0; s < 5; ++s)
+        for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-            const int k = 4 * s + q, o = nb * 16 + i;
-            bw1[s][nb] = k < 18 ? w1[(o * 2 + k / 9) * 9 + k % 9] : 0.f;
+            for (int r = 0; r < 4; ++r) bias1[nb][r] = b1[16 * nb + 4 * qq + r];
+        // B operands: k-step s of lane (i, q) reads s_vel at the pixel's base plus a per-lane
+        // constant offset (channel k / 9, tap k % 9); slots k >= 18 read the pixel itself and
+        // are zeroed by a select
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            const int k = 4 * s + qq, t = k % 9;
+            l1_on[s] = k < 18;
+            l1_off[s] = k < 18 ? (k / 9) * VH * VW + (t / 3) * VW + t % 3 : VW + 1;
         }
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) bias1[nb][r] = b1[16 * nb + 4 * q + r];
-    // conv1 B operands: k-step s of lane (i, q) reads s_vel at the pixel's base plus a
-    // per-lane constant offset (channel k / 9, tap k % 9); slots k >= 18 read the pixel
-    // itself and are zeroed by a select
-    int l1_off[5];
-    bool l1_on[5];
-#pragma unroll
-    for (int s = 0; s < 5; ++s) {
-        const int k = 4 * s + q, t = k % 9;
-        l1_on[s] = k < 18;
-        l1_off[s] = k < 18 ? (k / 9) * VH * VW + (t / 3) * VW + t % 3 : VW + 1;
-    }
+    };
 
-    float pv[VEL_PER_THREAD];
+    float pv[VEL_PER_THREAD12];
     auto fetch_vel = [&](int t) {
         const int y0 = (t / tiles_x) * RH, x0 = (t % tiles_x) * RW;
 #pragma unroll
-        for (int k = 0; k < VEL_PER_THREAD; ++k) {
+        for (int k = 0; k < VEL_PER_THREAD12; ++k) {
             // opaque to the compiler, so the positions are not kept in registers across tiles
-            int e = tid + k * kThreads;
+            int e = tid + k * kThreads12;
             asm volatile("" : "+v"(e));
             float v = 0.f;
             if (e < 2 * VH * VW) {
@@ -332,8 +391,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     };
     auto stash_vel = [&]() {
 #pragma unroll
-        for (int k = 0; k < VEL_PER_THREAD; ++k) {
-            const int e = tid + k * kThreads;
+        for (int k = 0; k < VEL_PER_THREAD12; ++k) {
+            const int e = tid + k * kThreads12;
             if (e < 2 * VH * VW) s_vel[e] = pv[k];
         }
     };
@@ -343,6 +402,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 
     for (; it.t < it.end; it.t += it.step) {
         const int y0 = (it.t / tiles_x) * RH, x0 = (it.t % tiles_x) * RW;
+        float bw1[5][2];
+        v4f bias1[2];
+        int l1_off[5];
+        bool l1_on[5];
+        conv1_setup(bw1, bias1, l1_off, l1_on);
 
         // conv1 on the 18 x 34 input tile of conv2; zero outside the grid (conv2's padding).
         // Wave w takes blocks w, w + 4, ....
@@ -372,12 +436,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             *reinterpret_cast<v4f*>(s_in + p * PS + 16 + 4 * q) = v1;
         };
         {
-            // all of the wave's blocks at once (w, w + 4, ..., at most 10): every gather issues
-            // first, then 20 independent accumulation chains
-            constexpr int NB1 = (L1_MBLOCKS + kWaves - 1) / kWaves;
+            // all of the wave's blocks at once (w, w + 8, ..., at most 5): every gather issues
+            // first, then 10 independent accumulation chains
+            constexpr int NB1 = (L1_MBLOCKS + kWaves12 - 1) / kWaves12;
             float a[NB1][5];
 #pragma unroll
-            for (int u = 0; u < NB1; ++u) conv1_gather(min(wave + u * kWaves, L1_MBLOCKS - 1), a[u]);
+            for (int u = 0; u < NB1; ++u) conv1_gather(min(wave + u * kWaves12, L1_MBLOCKS - 1), a[u]);
             v4f d[NB1][2];
 #pragma unroll
             for (int u = 0; u < NB1; ++u) {
@@ -393,21 +457,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
                 }
 #pragma unroll
             for (int u = 0; u < NB1; ++u)
-                if (wave + u * kWaves < L1_MBLOCKS) conv1_store(wave + u * kWaves, d[u][0], d[u][1]);
+                if (wave + u * kWaves12 < L1_MBLOCKS) conv1_store(wave + u * kWaves12, d[u][0], d[u][1]);
         }
         __syncthreads();
 
         const int next = it.t + it.step;
         if (next < it.end) fetch_vel(next);  // lands while conv2 runs
 
-        // conv2 in two rounds of block rows (ty = wave, wave + 4), nothing written to LDS:
-        // each lane stores its results (bias, ReLU) straight to act2, per pixel two 16-byte
-        // runs of channels that L2 merges into whole lines
-        conv32_wino(s_in, s_u, wave, lane, [&](int round, const v4f (&y)[4][2]) {
-            const int ty = wave + 4 * round;
+        // conv2 on block row ty = wave, nothing written to LDS: each lane stores its results
+        // (bias, ReLU) straight to act2, per pixel two 16-byte runs of channels that L2 merges
+        // into whole lines
+        conv32_wino_row(s_in, s_u, wave, lane, [&](const v4f (&y)[4][2]) {
+            int qq = q;
+            asm volatile("" : "+v"(qq));
+            v4f bias2[2];  // of the lane's output channels 16 nb + 4q + r
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) bias2[nb][r] = b2[16 * nb + 4 * qq + r];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int gy = y0 + 2 * ty + (e >> 1), gx = x0 + 2 * i + (e & 1);
+                const int gy = y0 + 2 * wave + (e >> 1), gx = x0 + 2 * i + (e & 1);
                 if (gy < G && gx < G) {
                     float* dst = act2 + ((int64_t)gy * G + gx) * C + 4 * q;
 #pragma unroll
@@ -611,7 +681,7 @@ void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision
     k_wino_weights<<<cdiv(NU, 256), 256, 0, stream>>>(w.w[2], u3);
     const int tx12 = (int)cdiv(G, RW), n12 = tx12 * (int)cdiv(G, RH);
     const int tx34 = (int)cdiv(G, OW34), n34 = tx34 * (int)cdiv(G, OH34);
-    k_conv12_f32<<<persistent_grid(n12), kThreads, 0, stream>>>(G, tx12, n12, vel, w.w[0], w.b[0], u2, w.b[1], act2);
+    k_conv12_f32<<<persistent_grid(n12), kThreads12, 0, stream>>>(G, tx12, n12, vel, w.w[0], w.b[0], u2, w.b[1], act2);
     k_conv34_f32<<<persistent_grid(n34), kThreads, 0, stream>>>(G, tx34, n34, act2, u3, w.b[2], w.w[3], w.b[3],
                                                                disp);
     hip_check(hipGetLastError(), "predict launch");
