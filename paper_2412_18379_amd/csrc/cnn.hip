@@ -503,6 +503,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 {
     __shared__ __attribute__((aligned(16))) float s_in[NIN * PS];
     __shared__ __attribute__((aligned(16))) float s_u[NU];
+    __shared__ __attribute__((aligned(16))) float s_w17[2][C];  // w4[1][c][7], w4[1][c][8]
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, q = lane >> 4;
     const int64_t GG = (int64_t)G * G;
@@ -517,17 +518,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) bias3[nb][r] = b3[16 * nb + 4 * q + r];
-    // conv4 A operands (rows n = 16 nz + i = 9 o + tap, zero for n >= 18): in k-step s, lane
-    // (i, q) supplies input channel 4q + s (s < 4) or 16 + 4q + s - 4, the channels that the
-    // Winograd result places in this lane
-    float aw4[8][2];
+    // conv4 A operands (rows n = i = 9 o + tap, the first 16 of the 18 columns): in k-step s,
+    // lane (i, q) supplies input channel 4q + s (s < 4) or 16 + 4q + s - 4, the channels that
+    // the Winograd result places in this lane
+    float aw4[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s)
-#pragma unroll
-        for (int nz = 0; nz < 2; ++nz) {
-            const int n = 16 * nz + i, c = s < 4 ? 4 * q + s : 16 + 4 * q + s - 4;
-            aw4[s][nz] = n < 18 ? w4[((n / 9) * C + c) * 9 + n % 9] : 0.f;
-        }
+    for (int s = 0; s < 8; ++s) {
+        const int n = i, c = s < 4 ? 4 * q + s : 16 + 4 * q + s - 4;
+        aw4[s] = w4[((n / 9) * C + c) * 9 + n % 9];
+    }
+    // the last two columns (n = 16, 17: output channel 1, taps 7 and 8) are vector dot
+    // products, not a second matrix instruction of which they would be 2 of 16 columns
+    for (int k = tid; k < 2 * C; k += kThreads) s_w17[k / C][k % C] = w4[(C + k % C) * 9 + 7 + k / C];
     const float bias4[2] = { b4[0], b4[1] };
 
     // next tile's input, as float4 chunks (8 per pixel) of the 18 x 34 tile
@@ -593,19 +595,37 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 #pragma unroll
                     for (int r = 0; r < 4; ++r) act[nb][r] = in ? fmaxf(act[nb][r], 0.f) : 0.f;
                 }
-                v4f z0 = v4f{ 0.f, 0.f, 0.f, 0.f }, z1 = z0;
+                v4f z0 = v4f{ 0.f, 0.f, 0.f, 0.f };
 #pragma unroll
                 for (int s = 0; s < 8; ++s) {
                     const float b = s < 4 ? act[0][s] : act[1][s - 4];
-                    z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(aw4[s][0], b, z0, 0, 0, 0);
-                    z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(aw4[s][1], b, z1, 0, 0, 0);
+                    z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(aw4[s], b, z0, 0, 0, 0);
                 }
-                // lane (i, q) holds Z of pixel (row, 2 i + (e & 1)) for n = 4q + r and 16 + 4q + r
+                // columns 16, 17: the lane's 8 channels, then the sum over the four lanes
+                // (i, 0..3) that hold the pixel's other channels
+                float z16 = 0.f, z17 = 0.f;
+                int wq = 4 * q;  // opaque: the weights are read per pixel, not held in registers
+                asm volatile("" : "+v"(wq));
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) {
+                    const v4f u = *reinterpret_cast<const v4f*>(&s_w17[0][16 * nb + wq]);
+                    const v4f v = *reinterpret_cast<const v4f*>(&s_w17[1][16 * nb + wq]);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        z16 += u[r] * act[nb][r];
+                        z17 += v[r] * act[nb][r];
+                    }
+                }
+                z16 += __shfl_xor(z16, 16);
+                z17 += __shfl_xor(z17, 16);
+                z16 += __shfl_xor(z16, 32);
+                z17 += __shfl_xor(z17, 32);
+                // lane (i, q) holds Z of pixel (row, 2 i + (e & 1)) for n = 4q + r, and 16, 17
                 float* zp = s_in + (row * RW + col) * ZS;
                 *reinterpret_cast<v4f*>(zp + 4 * q) = z0;
                 if (q == 0) {
-                    zp[16] = z1[0];
-                    zp[17] = z1[1];
+                    zp[16] = z16;
+                    zp[17] = z17;
                 }
             }
         });
