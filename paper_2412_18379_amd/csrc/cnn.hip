@@ -661,12 +661,9 @@ inline unsigned cdiv(int64_t a, int64_t b)
 // One block per compute unit (the LDS footprint allows one), a multiple of the 8 XCDs.
 unsigned persistent_grid(int ntiles)
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hip_check(hipGetDevice(&dev), "hipGetDevice");
-        hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
-    }
+    int dev = 0, cus = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
     int g = cus < ntiles ? cus : ntiles;
     g = (g + 7) / 8 * 8;
     return (unsigned)(g < 8 ? 8 : g);
