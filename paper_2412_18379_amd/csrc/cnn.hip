@@ -583,49 +583,60 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         static_assert(NREG / 2 * ZS <= 8 * IW * PS && NREG * ZS <= NIN * PS, "Z placement");
         conv32_wino(s_in, s_u, wave, lane, [&](int round, const v4f (&y)[4][2]) {
             __syncthreads();
+            // the lane's four pixels (row, 2 i + (e & 1)) at once, so that their four
+            // accumulation chains, dot products and lane exchanges overlap
+            v4f act[4][2];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gy = y0 + 2 * (wave + 4 * round) + (e >> 1), gx = x0 + 2 * i + (e & 1);
+                const bool in = (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G;  // conv4's zero padding
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) {
+                    act[e][nb] = y[e][nb] + bias3[nb];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) act[e][nb][r] = in ? fmaxf(act[e][nb][r], 0.f) : 0.f;
+                }
+            }
+            v4f z0[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) z0[e] = v4f{ 0.f, 0.f, 0.f, 0.f };
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    z0[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw4[s], s < 4 ? act[e][0][s] : act[e][1][s - 4],
+                                                                 z0[e], 0, 0, 0);
+            // columns 16, 17: the lane's 8 channels, then the sum over the four lanes (i, 0..3)
+            // that hold the pixel's other channels
+            float z16[4] = { 0.f, 0.f, 0.f, 0.f }, z17[4] = { 0.f, 0.f, 0.f, 0.f };
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const v4f u = *reinterpret_cast<const v4f*>(&s_w17[0][16 * nb + 4 * q]);
+                const v4f v = *reinterpret_cast<const v4f*>(&s_w17[1][16 * nb + 4 * q]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        z16[e] += u[r] * act[e][nb][r];
+                        z17[e] += v[r] * act[e][nb][r];
+                    }
+            }
+#pragma unroll
+            for (int m = 16; m <= 32; m *= 2)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    z16[e] += __shfl_xor(z16[e], m);
+                    z17[e] += __shfl_xor(z17[e], m);
+                }
+            // lane (i, q) holds Z of its pixels for n = 4q + r, and 16, 17
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = 2 * (wave + 4 * round) + (e >> 1), col = 2 * i + (e & 1);
-                const int gy = y0 + row, gx = x0 + col;
-                const bool in = (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G;  // conv4's zero padding
-                v4f act[2];
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb) {
-                    act[nb] = y[e][nb] + bias3[nb];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) act[nb][r] = in ? fmaxf(act[nb][r], 0.f) : 0.f;
-                }
-                v4f z0 = v4f{ 0.f, 0.f, 0.f, 0.f };
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const float b = s < 4 ? act[0][s] : act[1][s - 4];
-                    z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(aw4[s], b, z0, 0, 0, 0);
-                }
-                // columns 16, 17: the lane's 8 channels, then the sum over the four lanes
-                // (i, 0..3) that hold the pixel's other channels
-                float z16 = 0.f, z17 = 0.f;
-                int wq = 4 * q;  // opaque: the weights are read per pixel, not held in registers
-                asm volatile("" : "+v"(wq));
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb) {
-                    const v4f u = *reinterpret_cast<const v4f*>(&s_w17[0][16 * nb + wq]);
-                    const v4f v = *reinterpret_cast<const v4f*>(&s_w17[1][16 * nb + wq]);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        z16 += u[r] * act[nb][r];
-                        z17 += v[r] * act[nb][r];
-                    }
-                }
-                z16 += __shfl_xor(z16, 16);
-                z17 += __shfl_xor(z17, 16);
-                z16 += __shfl_xor(z16, 32);
-                z17 += __shfl_xor(z17, 32);
-                // lane (i, q) holds Z of pixel (row, 2 i + (e & 1)) for n = 4q + r, and 16, 17
                 float* zp = s_in + (row * RW + col) * ZS;
-                *reinterpret_cast<v4f*>(zp + 4 * q) = z0;
+                *reinterpret_cast<v4f*>(zp + 4 * q) = z0[e];
                 if (q == 0) {
-                    zp[16] = z16;
-                    zp[17] = z17;
+                    zp[16] = z16[e];
+                    zp[17] = z17[e];
                 }
             }
         });
