@@ -266,17 +266,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             if (e < HV * WV) s_vel[e] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{ pu[k], pw[k] }, bf16x2));
         }
     };
-    fetch_vel(it.t);
-    stash_vel();
-    __syncthreads();
-
-    for (; it.t < it.end; it.t += it.step) {
-        const int ty0 = (it.t / tiles_x) * OH, tx0 = (it.t % tiles_x) * OW;
-
+    // conv1 of tile t on its 20 x 36 region into bufA: K = 18 (9 taps x 2 channels) padded to 32
+    auto conv1 = [&](int t) {
+        const int ty0 = (t / tiles_x) * OH, tx0 = (t % tiles_x) * OW;
         // tiles whose velocity halo lies inside the grid need no zero-padding tests
         const bool edge = ty0 < 4 || tx0 < 4 || ty0 + OH + 4 > G || tx0 + OW + 4 > G;
-
-        // conv1 on the 20 x 36 region: K = 18 (9 taps x 2 channels) padded to 32
         int g1 = wave * BPW1;  // opaque, as in conv32_bf16
         asm volatile("" : "+s"(g1));
 #pragma unroll 1
@@ -310,7 +304,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
                 }
             }
         }
-        __syncthreads();
+    };
+
+    fetch_vel(it.t);
+    stash_vel();
+    __syncthreads();
+    conv1(it.t);
+    __syncthreads();
+
+    for (; it.t < it.end; it.t += it.step) {
+        const int ty0 = (it.t / tiles_x) * OH, tx0 = (it.t % tiles_x) * OW;
+
+        // tiles whose velocity halo lies inside the grid need no zero-padding tests
+        const bool edge = ty0 < 4 || tx0 < 4 || ty0 + OH + 4 > G || tx0 + OW + 4 > G;
 
         const int next = it.t + it.step;
         if (next < it.end) fetch_vel(next);  // lands while conv2-conv4 run
@@ -362,6 +368,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
                 }
             }
         }
+        // the next tile's conv1 in the same phase: bufA (this tile's conv3 output) was last read
+        // before the barrier above, the tap sums read only the conv2 buffer, and the next
+        // tile's velocity was stashed after conv2
+        if (next < it.end) conv1(next);
         __syncthreads();
     }
 }
