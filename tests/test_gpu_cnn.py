@@ -48,7 +48,9 @@ def _square_mesh(C, G):
     return C.Mesh(xy, tri, overlay_side=G)
 
 
-@pytest.mark.parametrize("G,seed", [(1, 1), (2, 2), (3, 3), (37, 4), (64, 5), (100, 6), (131, 7)])
+# G = 601: several tiles per persistent block (the loop paths with a next tile), ragged in
+# every tile dimension of both precisions
+@pytest.mark.parametrize("G,seed", [(1, 1), (2, 2), (3, 3), (37, 4), (64, 5), (100, 6), (131, 7), (601, 8)])
 def test_cnn_f32_full_grid(C, oracle_mod, wl, G, seed):
     print(f"[cnn f32] G={G} seed={seed}", flush=True)
     rng = np.random.default_rng(seed)
@@ -148,7 +150,7 @@ def _bf16_errors(got, ref):
     return float(e.max()), float(e.mean())
 
 
-@pytest.mark.parametrize("G,seed", [(1, 1), (5, 2), (37, 4), (100, 6), (131, 7)])
+@pytest.mark.parametrize("G,seed", [(1, 1), (5, 2), (37, 4), (100, 6), (131, 7), (601, 8)])
 def test_cnn_bf16_full_grid(C, oracle_mod, wl, G, seed):
     print(f"[cnn bf16] G={G} seed={seed}", flush=True)
     rng = np.random.default_rng(seed)
