@@ -72,6 +72,28 @@ def copy_probe(nbytes: int, reps: int = 3):
     print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def copy_bandwidth(nbytes: int = 2 << 30, reps: int = 5) -> float:
+    """Device-to-device copy rate in GB/s (bytes read + bytes written per second): the
+    streaming bandwidth this GPU reaches in practice, a second denominator for HBM-bound
+    kernels beside the published peak."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def _off_edge(w, host, pts, eps=1e-9):
     """Points farther than eps from every edge of their (oracle) host element."""
     V = w.xy[w.tri[host]]
@@ -394,12 +416,17 @@ def main():
             "frac": round(executed / cnn_peak, 4),
             "note": "matrix-core MACs actually issued (conv1 K padded to 20, conv2/conv3 in the Winograd "
                     "domain, conv4 as 32 columns); 'achieved' above counts the direct-convolution FLOPs"}
+    copy_gbps = copy_bandwidth()
+    log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
     roofline_sns = {
         "kernel": "k_locate (plain SNS leg)", "bound": "hbm", "achieved": round(gbps_plain, 1),
         "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": round(gbps_plain / PEAK["hbm_GBps"], 4),
         "traffic": traffic_for("k_locate_plain", args.workload),
         "algorithmic_per_launch": f"{bytes_plain:.4e} B (60 B x sum I_t + 29 B x n)",
+        "measured_copy_GBps": round(copy_gbps, 1),
+        "frac_of_measured_copy": round(gbps_plain / copy_gbps, 4),
         "cnn_sns_leg": {"achieved": round(gbps_cnn_walk, 1), "frac": round(gbps_cnn_walk / PEAK["hbm_GBps"], 4),
+                        "frac_of_measured_copy": round(gbps_cnn_walk / copy_gbps, 4),
                         "algorithmic_per_launch": f"{bytes_cnn_walk:.4e} B (60 B x sum I_t + 69 B x n)"},
     }
     res = {
