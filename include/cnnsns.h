@@ -167,6 +167,29 @@ int cnnsns_locate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* sta
                   void* stream);
 
 /*
+ * Interpolate a nodal field at located points: the step the host element is
+ * found for (Sec. 2.1, the approximation after eq. 4).  For point i with host
+ * element K = host[i] and its nodes n_0, n_1, n_2 (in the counter-clockwise
+ * order the library stores), the value is sum_j lambda_j nodal[n_j], where
+ * lambda_j = s_j / |S_0| are the barycentric coordinates of Sec. 2.2 (s_j the
+ * numerators of cnnsns_locate, |S_0| the doubled element area), i.e. the P1
+ * (linear) interpolant, exact for fields linear in x and y.  All arrays are
+ * DEVICE memory:
+ *   xp     FP64 [n][2] the points (as given to cnnsns_locate).
+ *   host   int32 [n] their host elements (as returned by cnnsns_locate).
+ *   nodal  FP64 [n_nodes][2] the field at the mesh nodes (node ids of
+ *          cnnsns_build_mesh), e.g. the Eulerian velocity u(n_j).
+ *   out    FP64 [n][2] output.
+ * FP64 with no fused multiply-add; the sum runs over j = 0, 1, 2 in order.  A
+ * host id outside [0, n_tri) (a BADSTART point) gives NaN; for an OUTSIDE
+ * point (x_p beyond the mesh, host = the boundary element reached) the same
+ * formula extrapolates.  Asynchronous on `stream`; n == 0 is a no-op.
+ * Errors: EINVAL (null mesh or array, n < 0), EHIP.
+ */
+int cnnsns_interpolate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
+                       double* out, void* stream);
+
+/*
  * Serving loop: a host scheduler that takes CNN-SNS tracking jobs on
  * resident meshes as they arrive and runs them with continuous batching.
  * Each job is one CNN forward pass over its mesh's overlay (in `precision`)

@@ -69,6 +69,7 @@ def _L():
             "orc_cnn_window": [i32, vp, vp, vp, vp, i64, i64, i64, i64, vp],
             "orc_cnnsns_start": [i64, vp, i32, vp, vp, vp, vp],
             "orc_brute_force": [i64, vp, vp, i64, vp, vp],
+            "orc_interp": [i64, vp, vp, vp, i64, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -125,6 +126,22 @@ def sns(xy, tri_ccw, nbr, xp, start, max_iter: int = 0):
     _check(_L().orc_sns(tri_ccw.shape[0], _p(xy), _p(tri_ccw), _p(nbr), n, _p(xp), _p(start), int(max_iter),
                         _p(host), _p(iters), _p(status)), "sns")
     return host, iters, status
+
+
+def interpolate(xy, tri_ccw, nodal, xp, host):
+    """P1 interpolation of a two-component nodal field at xp in the host elements (Sec. 2.1,
+    after eq. 4): FP64 [n][2], NaN where the host id is not an element."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri_ccw = np.ascontiguousarray(tri_ccw, dtype=np.int32)
+    nodal = np.ascontiguousarray(nodal, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    host = np.ascontiguousarray(host, dtype=np.int32)
+    if nodal.shape != (xy.shape[0], 2) or xp.ndim != 2 or xp.shape[1] != 2 or host.shape != (xp.shape[0],):
+        raise ValueError("interpolate: nodal [n_nodes][2], xp [n][2] and host [n] expected")
+    out = np.empty((xp.shape[0], 2), np.float64)
+    _check(_L().orc_interp(tri_ccw.shape[0], _p(xy), _p(tri_ccw), _p(nodal), xp.shape[0], _p(xp), _p(host),
+                           _p(out)), "interpolate")
+    return out
 
 
 def lookup(xy, tri_ccw, G: int):

@@ -205,6 +205,46 @@ int orc_sns(int64_t n_tri, const double* xy, const int32_t* tri, const int32_t* 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Interpolation at the departure point (Sec. 2.1).                          */
+
+/*
+ * After eq. 4, the velocity at the departure point x_p is approximated by
+ * interpolation in its host element with the element's nodal basis functions
+ * phi_j (phi_i(n_j) = 1 for i = j, 0 otherwise).  For a linear triangle these
+ * are its barycentric coordinates (Sec. 2.2), lambda_j = |S_j| / |S_0|, so a
+ * nodal field f takes at p the value
+ *     f(p) = lambda_0 f(n_0) + lambda_1 f(n_1) + lambda_2 f(n_2)
+ * over the nodes of the counter-clockwise host triangle, added in that order.
+ * nodal holds two components per node and out two per point.  A host id
+ * outside [0, n_tri) (a point whose start was invalid) gives NaN.
+ */
+int orc_interp(int64_t n_tri, const double* xy, const int32_t* tri, const double* nodal, int64_t n,
+               const double* xp, const int32_t* host, double* out)
+{
+    if (n < 0 || n_tri < 0) return ORC_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t t = host[i];
+        if (t < 0 || t >= n_tri) {
+            out[2 * i] = NAN;
+            out[2 * i + 1] = NAN;
+            continue;
+        }
+        const int32_t* nd = tri + 3 * t;
+        const double* v[3] = { xy + 2 * (int64_t)nd[0], xy + 2 * (int64_t)nd[1], xy + 2 * (int64_t)nd[2] };
+        double s[3];
+        bary_numerators(v, xp + 2 * i, s);
+        const double a = area2(v[0], v[1], v[2]);
+        for (int c = 0; c < 2; ++c) {
+            double f = 0.0;
+            for (int j = 0; j < 3; ++j) f += (s[j] / a) * nodal[2 * (int64_t)nd[j] + c];
+            out[2 * i + c] = f;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* ASG overlay: cell -> element lookup.                                      */
 
 /*

@@ -23,6 +23,7 @@ PRECISIONS = {"f32": F32, "bf16": BF16, "fp8": FP8E4M3}
 
 EXPORTS = (
     "cnnsns_build_mesh", "cnnsns_mesh_info", "cnnsns_destroy_mesh", "cnnsns_predict", "cnnsns_locate",
+    "cnnsns_interpolate",
     "cnnsns_server_create", "cnnsns_submit", "cnnsns_poll", "cnnsns_wait", "cnnsns_server_destroy",
     "cnnsns_last_error",
 )
@@ -55,6 +56,7 @@ def lib():
             "cnnsns_destroy_mesh": [vp],
             "cnnsns_predict": [vp, vp, ctypes.POINTER(_Cnn), i32, vp, vp],
             "cnnsns_locate": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp],
+            "cnnsns_interpolate": [vp, i64, vp, vp, vp, vp, vp],
             "cnnsns_server_create": [i64, i32, i32, i32, ctypes.POINTER(_Cnn), ctypes.POINTER(vp)],
             "cnnsns_submit": [vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)],
             "cnnsns_poll": [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
@@ -114,6 +116,7 @@ class Mesh:
         _check(lib().cnnsns_build_mesh(xy.ctypes.data, xy.shape[0], tri.ctypes.data, tri.shape[0],
                                        int(overlay_side), _stream(stream), ctypes.byref(h)))
         self.handle = h
+        self.n_nodes = int(xy.shape[0])
         n_tri, G, nbytes, diam = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double()
         _check(lib().cnnsns_mesh_info(h, ctypes.byref(n_tri), ctypes.byref(G), ctypes.byref(nbytes),
                                       ctypes.byref(diam)))
@@ -182,6 +185,21 @@ def locate(mesh: Mesh, xp: torch.Tensor, start: torch.Tensor = None, origin: tor
     _check(lib().cnnsns_locate(mesh.handle, n, _ptr(xp), _ptr(start), _ptr(origin), _ptr(disp), int(max_iter),
                                _ptr(host), _ptr(iters), _ptr(status), _stream(stream)))
     return host, iters, status
+
+
+def interpolate(mesh: Mesh, xp: torch.Tensor, host: torch.Tensor, nodal: torch.Tensor, out: torch.Tensor = None,
+                stream=None) -> torch.Tensor:
+    """P1 interpolation of a nodal field (FP64 [n_nodes][2]) at the points xp in their host
+    elements (cnnsns_interpolate)."""
+    n = xp.shape[0]
+    _need(xp, torch.float64, (n, 2), "xp")
+    _need(host, torch.int32, (n,), "host")
+    _need(nodal, torch.float64, (mesh.n_nodes, 2), "nodal")
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.float64, device=xp.device)
+    _need(out, torch.float64, (n, 2), "out")
+    _check(lib().cnnsns_interpolate(mesh.handle, n, _ptr(xp), _ptr(host), _ptr(nodal), _ptr(out), _stream(stream)))
+    return out
 
 
 class Server:

@@ -125,6 +125,19 @@ int cnnsns_locate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* sta
     });
 }
 
+int cnnsns_interpolate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
+                       double* out, void* stream)
+{
+    return guarded([&] {
+        if (!m) fail(CNNSNS_EINVAL, "interpolate: NULL mesh");
+        if (n < 0) fail(CNNSNS_EINVAL, "interpolate: n must be >= 0");
+        if (n == 0) return;
+        if (!xp || !host || !nodal || !out) fail(CNNSNS_EINVAL, "interpolate: NULL argument");
+        DeviceScope ds(m->device);
+        launch_interp(*m, n, xp, host, nodal, out, static_cast<hipStream_t>(stream));
+    });
+}
+
 int cnnsns_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int32_t queue_depth, int32_t precision,
                          const cnnsns_cnn* w, cnnsns_server* out)
 {

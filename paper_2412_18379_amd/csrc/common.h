@@ -40,6 +40,7 @@ struct cnnsns_mesh_s {
     int32_t G = 0;
     double mean_diam = 0.0;
     cnnsns::ElemRec* rec = nullptr;  // device [n_tri]
+    int32_t* tri = nullptr;          // device [n_tri][3] node ids, in the records' counter-clockwise order
     int32_t* lookup = nullptr;       // device [G][G]
     int64_t device_bytes = 0;
     // CNN workspace, allocated on the first cnnsns_predict of this mesh
@@ -57,6 +58,8 @@ void destroy_mesh(cnnsns_mesh m);
 
 // sns_walk.hip
 enum StartMode { START_GIVEN = 0, START_CNN = 1, START_ASG = 2 };
+void launch_interp(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
+                   double* out, hipStream_t stream);
 void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t* start,
                    const double* origin, const float* disp, int32_t max_iter, int32_t* host, int32_t* iters,
                    uint8_t* status, hipStream_t stream);

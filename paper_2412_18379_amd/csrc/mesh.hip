@@ -306,8 +306,10 @@ cnnsns_mesh build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, in
     m->G = G;
     m->mean_diam = sum / (double)n_tri;
     m->rec = d_rec.release();
+    m->tri = d_tri.release();
     m->lookup = d_lookup.release();
-    m->device_bytes = (int64_t)(sizeof(ElemRec) * (size_t)n_tri + sizeof(int32_t) * (size_t)G * (size_t)G);
+    m->device_bytes = (int64_t)(sizeof(ElemRec) * (size_t)n_tri + sizeof(int32_t) * 3 * (size_t)n_tri +
+                                sizeof(int32_t) * (size_t)G * (size_t)G);
     return m;
 }
 
@@ -319,6 +321,7 @@ void destroy_mesh(cnnsns_mesh m)
     (void)hipSetDevice(m->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(m->rec);
+    (void)hipFree(m->tri);
     (void)hipFree(m->lookup);
     if (m->cnn_ws) (void)hipFree(m->cnn_ws);
     (void)hipSetDevice(cur);

@@ -179,7 +179,53 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
 }
 
+// P1 interpolation at x_p in its host element (the approximation that follows
+// eq. 4 in Sec. 2.1): the element's nodal basis functions are its barycentric
+// coordinates (Sec. 2.2), lambda_j = s_j / |S_0| with s_j the numerators the
+// walk uses and |S_0| the doubled area, and the value is sum_j lambda_j u(n_j)
+// over the element's nodes, summed in node order.  One thread per point;
+// FP64, no fused multiply-add.
+__global__ __launch_bounds__(kBlock) void k_interp(const ElemRec* __restrict__ rec, const int3* __restrict__ tri,
+                                                   int64_t n_tri, int64_t n, const double2* __restrict__ xp,
+                                                   const int32_t* __restrict__ host, const double2* __restrict__ nodal,
+                                                   double2* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t K = host[i];
+    if (K < 0 || K >= n_tri) {  // no element (a start outside the mesh)
+        out[i] = double2{ __builtin_nan(""), __builtin_nan("") };
+        return;
+    }
+    const double2* r2 = reinterpret_cast<const double2*>(rec + K);
+    const double2 A = r2[0], B = r2[1], C = r2[2], p = xp[i];
+    const double adx = A.x - p.x, ady = A.y - p.y;
+    const double bdx = B.x - p.x, bdy = B.y - p.y;
+    const double cdx = C.x - p.x, cdy = C.y - p.y;
+    const double s0 = bdx * cdy - bdy * cdx;
+    const double s1 = cdx * ady - cdy * adx;
+    const double s2 = adx * bdy - ady * bdx;
+    const double area2 = (B.x - A.x) * (C.y - A.y) - (B.y - A.y) * (C.x - A.x);
+    const double l0 = s0 / area2, l1 = s1 / area2, l2 = s2 / area2;
+    const int3 v = tri[K];
+    const double2 u0 = nodal[v.x], u1 = nodal[v.y], u2 = nodal[v.z];
+    out[i] = double2{ l0 * u0.x + l1 * u1.x + l2 * u2.x, l0 * u0.y + l1 * u1.y + l2 * u2.y };
+}
+
 }  // namespace
+
+void launch_interp(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
+                   double* out, hipStream_t stream)
+{
+    if (n == 0) return;
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > (int64_t)INT32_MAX) fail(CNNSNS_EINVAL, "interpolate: too many points");
+    k_interp<<<(unsigned)blocks, kBlock, 0, stream>>>(m.rec, reinterpret_cast<const int3*>(m.tri), m.n_tri, n,
+                                                       reinterpret_cast<const double2*>(xp), host,
+                                                       reinterpret_cast<const double2*>(nodal),
+                                                       reinterpret_cast<double2*>(out));
+    hip_check(hipGetLastError(), "interpolate launch");
+}
 
 void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t* start, const double* origin,
                    const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status,

@@ -67,6 +67,10 @@ void run_cnn(int32_t G, const float* vel, const cnnsns_cnn&, int32_t, float* dis
     std::memcpy(disp, vel, sizeof(float) * 2 * (size_t)G * (size_t)G);
 }
 
+void launch_interp(const cnnsns_mesh_s&, int64_t, const double*, const int32_t*, const double*, double*, hipStream_t)
+{
+}
+
 void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t*, const double* origin,
                    const float* disp, int32_t, int32_t* host, int32_t* iters, uint8_t*, hipStream_t)
 {
