@@ -389,6 +389,23 @@ def main():
     log(f"ASG start: {asg_ms.mean():.3f} ms, mean I_t {it_a.mean():.2f}")
     same_host = float(np.mean(host_c == host_p))
 
+    # the step after location: the velocity at x_p, P1-interpolated in the host element
+    fu, fv = w.flow(w.xy[:, 0], w.xy[:, 1])
+    nodal = torch.from_numpy(np.ascontiguousarray(np.stack([fu, fv], axis=1))).to(dev)
+    host_i = torch.from_numpy(host_c).to(dev)
+    u_xp = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        C.interpolate(mesh, xp, host_i, nodal, out=u_xp)
+    torch.cuda.synchronize()
+    ei = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for k in range(K):
+        ei[k][0].record(stream)
+        C.interpolate(mesh, xp, host_i, nodal, out=u_xp)
+        ei[k][1].record(stream)
+    torch.cuda.synchronize()
+    interp_ms = np.array([a.elapsed_time(b) for a, b in ei])
+    log(f"interpolation at x_p: {interp_ms.mean():.3f} ms")
+
     value = n / (ms_step / 1e3)
     G = w.G
     cnn_flops = 2.0 * CNN_MACS_PER_PIXEL * G * G
@@ -416,6 +433,10 @@ def main():
             "frac": round(executed / cnn_peak, 4),
             "note": "matrix-core MACs actually issued (conv1 K padded to 20, conv2/conv3 in the Winograd "
                     "domain, conv4 as 32 columns); 'achieved' above counts the direct-convolution FLOPs"}
+    # interpolation: x_p 16 + host 4 + element coordinates 48 and node ids 12 + three nodal values 48
+    # + the result 16 bytes per point
+    bytes_interp = n * (16 + 4 + 48 + 12 + 48 + 16)
+    gbps_interp = bytes_interp / (interp_ms.mean() / 1e3) / 1e9
     copy_gbps = copy_bandwidth()
     log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
     roofline_sns = {
@@ -456,6 +477,13 @@ def main():
         "host_agreement_cnn_vs_plain": same_host,
         "status_found_frac": float(np.mean(st_c == C.FOUND)),
         "roofline": roofline, "roofline_sns": roofline_sns,
+        "interp_leg": {"kernel": "k_interp (P1 velocity at x_p in its host element)", "ms": round(float(interp_ms.mean()), 4),
+                       "points_per_s": round(n / (interp_ms.mean() / 1e3), 1), "bound": "hbm",
+                       "achieved": round(gbps_interp, 1), "unit": "GB/s",
+                       "frac": round(gbps_interp / PEAK["hbm_GBps"], 4),
+                       "frac_of_measured_copy": round(gbps_interp / copy_gbps, 4),
+                       "traffic": traffic_for("k_interp", args.workload),
+                       "algorithmic_per_launch": f"{bytes_interp:.4e} B (144 B x n)"},
     }
     disp_bf = None
     if precision == "f32" and not args.no_bf16_variant:

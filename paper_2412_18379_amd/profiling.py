@@ -33,6 +33,7 @@ SOURCES = {
     "cnn_forward_bf16": ("cnn_bf16.hip",),
     "k_locate_plain": ("sns_walk.hip",),
     "k_locate_cnn": ("sns_walk.hip",),
+    "k_interp": ("sns_walk.hip",),
 }
 
 
