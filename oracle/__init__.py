@@ -70,6 +70,11 @@ def _L():
             "orc_cnnsns_start": [i64, vp, i32, vp, vp, vp, vp],
             "orc_brute_force": [i64, vp, vp, i64, vp, vp],
             "orc_interp": [i64, vp, vp, vp, i64, vp, vp, vp],
+            "orc3_canonicalise": [i64, vp, i64, vp, vp],
+            "orc3_neighbours": [i64, vp, vp],
+            "orc3_sns": [i64, vp, vp, vp, i64, vp, vp, i32, vp, vp, vp],
+            "orc3_lookup": [i64, vp, vp, i32, vp],
+            "orc3_brute_force": [i64, vp, vp, i64, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -222,3 +227,55 @@ def err_metric(xy, tri, start, host):
 def opt(c_sns: float, c_cnnsns: float) -> float:
     """Optimisation rate (C(SNS) - C(CNN-SNS)) / C(SNS) (Sec. 3.1)."""
     return (c_sns - c_cnnsns) / c_sns
+
+
+# ----------------------------------------------------------------------------- 3D (tetrahedra)
+
+def canonicalise3(xyz, tet):
+    """Tetrahedra in positive orientation (3rd and 4th vertex swapped where negative)."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tet = np.ascontiguousarray(tet, dtype=np.int32)
+    out = np.empty_like(tet)
+    _check(_L().orc3_canonicalise(xyz.shape[0], _p(xyz), tet.shape[0], _p(tet), _p(out)), "canonicalise3")
+    return out
+
+
+def neighbours3(tet_pos):
+    tet_pos = np.ascontiguousarray(tet_pos, dtype=np.int32)
+    nbr = np.empty_like(tet_pos)
+    _check(_L().orc3_neighbours(tet_pos.shape[0], _p(tet_pos), _p(nbr)), "neighbours3")
+    return nbr
+
+
+def prepare_mesh3(xyz, tet):
+    """(positively oriented tetrahedra, neighbour table) of a tetrahedral mesh."""
+    tp = canonicalise3(xyz, tet)
+    return tp, neighbours3(tp)
+
+
+def sns3(xyz, tet_pos, nbr, xp, start, max_iter: int = 0):
+    """Alg. 1 on a tetrahedral mesh for every point: (host, iters, status)."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    start = np.ascontiguousarray(start, dtype=np.int32)
+    n = xp.shape[0]
+    host, iters, status = np.empty(n, np.int32), np.empty(n, np.int32), np.empty(n, np.uint8)
+    _check(_L().orc3_sns(tet_pos.shape[0], _p(xyz), _p(tet_pos), _p(nbr), n, _p(xp), _p(start), int(max_iter),
+                         _p(host), _p(iters), _p(status)), "sns3")
+    return host, iters, status
+
+
+def lookup3(xyz, tet_pos, G: int):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    out = np.empty((G, G, G), np.int32)
+    _check(_L().orc3_lookup(tet_pos.shape[0], _p(xyz), _p(tet_pos), int(G), _p(out)), "lookup3")
+    return out
+
+
+def brute_force3(xyz, tet_pos, xp):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    host = np.empty(xp.shape[0], np.int32)
+    _check(_L().orc3_brute_force(tet_pos.shape[0], _p(xyz), _p(tet_pos), xp.shape[0], _p(xp), _p(host)),
+           "brute_force3")
+    return host

@@ -447,3 +447,256 @@ int orc_brute_force(int64_t n_tri, const double* xy, const int32_t* tri, int64_t
     }
     return ORC_OK;
 }
+
+/* ======================================================================== */
+/* 3D: tetrahedral meshes, the paper's own setting (Sec. 2.2 with 4 nodes).  */
+/* ======================================================================== */
+
+/*
+ * det[a - p, b - p, c - p]: six times the signed volume of tetrahedron
+ * (p, a, b, c), positive when (a, b, c) turn counter-clockwise seen from p's
+ * opposite side, i.e. the determinant |S| of Sec. 2.2 with the homogeneous
+ * row removed by subtracting p's column.  Evaluated as written:
+ *   det = ax (by cz - bz cy) - ay (bx cz - bz cx) + az (bx cy - by cx).
+ */
+static double orient3(const double* p, const double* a, const double* b, const double* c)
+{
+    const double ax = a[0] - p[0], ay = a[1] - p[1], az = a[2] - p[2];
+    const double bx = b[0] - p[0], by = b[1] - p[1], bz = b[2] - p[2];
+    const double cx = c[0] - p[0], cy = c[1] - p[1], cz = c[2] - p[2];
+    const double t1 = by * cz - bz * cy, t2 = bx * cz - bz * cx, t3 = bx * cy - by * cx;
+    return ax * t1 - ay * t2 + az * t3;
+}
+
+/*
+ * The four barycentric numerators s_j = |S_j| of p in the positively
+ * oriented tetrahedron v[0..3] (node ids id[0..3]): the volume determinant
+ * with vertex j replaced by p.  Moving p to the front gives
+ *   s_j = sigma_j det[F_j - p], sigma = (+, -, +, -),
+ * with F_j the other three vertices in the tetrahedron's order.  The face is
+ * evaluated with its vertices sorted by node id (and the sign of that
+ * permutation applied), so the two tetrahedra that share a face compute the
+ * very same number for it and their numerators are exact negatives.
+ */
+static void bary3_numerators(const double* const v[4], const int32_t id[4], const double* p, double s[4])
+{
+    for (int j = 0; j < 4; ++j) {
+        int f[3], k = 0;
+        for (int m = 0; m < 4; ++m)
+            if (m != j) f[k++] = m;
+        int sign = (j & 1) ? -1 : 1;
+        /* sort the three face vertices by node id, flipping the sign per swap */
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2 - a; ++b)
+                if (id[f[b]] > id[f[b + 1]]) {
+                    const int t = f[b];
+                    f[b] = f[b + 1];
+                    f[b + 1] = t;
+                    sign = -sign;
+                }
+        const double d = orient3(p, v[f[0]], v[f[1]], v[f[2]]);
+        s[j] = sign > 0 ? d : -d;
+    }
+}
+
+static void tet_vertices(const double* xyz, const int32_t* tet, int64_t t, const double* v[4], int32_t id[4])
+{
+    for (int k = 0; k < 4; ++k) {
+        id[k] = tet[4 * t + k];
+        v[k] = xyz + 3 * (int64_t)id[k];
+    }
+}
+
+/*
+ * Put every tetrahedron in positive orientation (det[b - a, c - a, d - a] > 0;
+ * swap its 3rd and 4th vertex when negative), keeping ids.  Zero volume and
+ * vertex indices outside [0, n_nodes) are mesh errors.
+ */
+int orc3_canonicalise(int64_t n_nodes, const double* xyz, int64_t n_tet, const int32_t* tet_in, int32_t* tet_out)
+{
+    for (int64_t t = 0; t < n_tet; ++t) {
+        const int32_t* q = tet_in + 4 * t;
+        for (int k = 0; k < 4; ++k)
+            if (q[k] < 0 || q[k] >= n_nodes) return ORC_EMESH;
+        const double vol = orient3(xyz + 3 * (int64_t)q[0], xyz + 3 * (int64_t)q[1], xyz + 3 * (int64_t)q[2],
+                                   xyz + 3 * (int64_t)q[3]);
+        if (vol == 0.0) return ORC_EMESH;
+        tet_out[4 * t] = q[0];
+        tet_out[4 * t + 1] = q[1];
+        tet_out[4 * t + 2] = vol < 0.0 ? q[3] : q[2];
+        tet_out[4 * t + 3] = vol < 0.0 ? q[2] : q[3];
+    }
+    return ORC_OK;
+}
+
+typedef struct {
+    int32_t k[3];
+    int64_t slot; /* 4 t + j */
+} Face3;
+
+static int face3_cmp(const void* x, const void* y)
+{
+    const Face3* a = (const Face3*)x;
+    const Face3* b = (const Face3*)y;
+    for (int i = 0; i < 3; ++i)
+        if (a->k[i] != b->k[i]) return a->k[i] < b->k[i] ? -1 : 1;
+    return a->slot < b->slot ? -1 : (a->slot > b->slot ? 1 : 0);
+}
+
+/*
+ * Neighbour table: nbr[4t + j] is the tetrahedron sharing the face opposite
+ * vertex j of t, or -1 on the boundary.  A face in more than two tetrahedra
+ * is a mesh error.  (Sorted list of faces keyed by their node ids.)
+ */
+int orc3_neighbours(int64_t n_tet, const int32_t* tet, int32_t* nbr)
+{
+    Face3* f = (Face3*)malloc(sizeof(Face3) * 4 * (size_t)n_tet);
+    if (!f) return ORC_ENOMEM;
+    for (int64_t t = 0; t < n_tet; ++t)
+        for (int j = 0; j < 4; ++j) {
+            Face3* e = f + 4 * t + j;
+            int k = 0;
+            for (int m = 0; m < 4; ++m)
+                if (m != j) e->k[k++] = tet[4 * t + m];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2 - a; ++b)
+                    if (e->k[b] > e->k[b + 1]) {
+                        const int32_t x = e->k[b];
+                        e->k[b] = e->k[b + 1];
+                        e->k[b + 1] = x;
+                    }
+            e->slot = 4 * t + j;
+            nbr[4 * t + j] = -1;
+        }
+    qsort(f, 4 * (size_t)n_tet, sizeof(Face3), face3_cmp);
+    int rc = ORC_OK;
+    for (int64_t i = 0; i < 4 * n_tet;) {
+        int64_t e = i + 1;
+        while (e < 4 * n_tet && f[e].k[0] == f[i].k[0] && f[e].k[1] == f[i].k[1] && f[e].k[2] == f[i].k[2]) ++e;
+        if (e - i > 2) rc = ORC_EMESH;
+        if (e - i == 2) {
+            nbr[f[i].slot] = (int32_t)(f[i + 1].slot / 4);
+            nbr[f[i + 1].slot] = (int32_t)(f[i].slot / 4);
+        }
+        i = e;
+    }
+    free(f);
+    return rc;
+}
+
+/* Alg. 1 in 3D for one point: as sns_one with four numerators and neighbours. */
+static void sns3_one(int64_t n_tet, const double* xyz, const int32_t* tet, const int32_t* nbr, const double* p,
+                     int32_t start, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status)
+{
+    if (start < 0 || start >= n_tet) {
+        *host = -1;
+        *iters = 0;
+        *status = ORC_BADSTART;
+        return;
+    }
+    int32_t K = start, I = 0;
+    for (;;) {
+        I += 1;
+        const double* v[4];
+        int32_t id[4];
+        double s[4];
+        tet_vertices(xyz, tet, K, v, id);
+        bary3_numerators(v, id, p, s);
+        if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0 && s[3] >= 0.0) {
+            *host = K;
+            *iters = I;
+            *status = ORC_FOUND;
+            return;
+        }
+        int jmin = 0;
+        for (int j = 1; j < 4; ++j)
+            if (s[j] < s[jmin]) jmin = j;
+        const int32_t m = nbr[4 * (int64_t)K + jmin];
+        if (m == -1) {
+            *host = K;
+            *iters = I;
+            *status = ORC_OUTSIDE;
+            return;
+        }
+        K = m;
+        if (I >= max_iter) {
+            *host = K;
+            *iters = I;
+            *status = ORC_MAXITER;
+            return;
+        }
+    }
+}
+
+int orc3_sns(int64_t n_tet, const double* xyz, const int32_t* tet, const int32_t* nbr, int64_t n, const double* xp,
+             const int32_t* start, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status)
+{
+    if (n < 0 || n_tet < 0) return ORC_EINVAL;
+    if (max_iter <= 0) max_iter = 1 << 20;
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i)
+        sns3_one(n_tet, xyz, tet, nbr, xp + 3 * i, start[i], max_iter, host + i, iters + i, status + i);
+    return ORC_OK;
+}
+
+/*
+ * 3D overlay: lookup[(cz G + cy) G + cx] is the smallest id of a tetrahedron
+ * whose closed region contains the cell centre ((c + 1/2) / G per axis), or
+ * -1.  Tetrahedra in increasing id test the centres in their bounding box;
+ * the first to claim a cell is the smallest containing id.
+ */
+int orc3_lookup(int64_t n_tet, const double* xyz, const int32_t* tet, int32_t G, int32_t* lookup)
+{
+    if (G <= 0 || n_tet < 0) return ORC_EINVAL;
+    const int64_t nc = (int64_t)G * G * G;
+    for (int64_t c = 0; c < nc; ++c) lookup[c] = -1;
+    for (int64_t t = 0; t < n_tet; ++t) {
+        const double* v[4];
+        int32_t id[4];
+        tet_vertices(xyz, tet, t, v, id);
+        int lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            double mn = v[0][d], mx = v[0][d];
+            for (int k = 1; k < 4; ++k) {
+                mn = v[k][d] < mn ? v[k][d] : mn;
+                mx = v[k][d] > mx ? v[k][d] : mx;
+            }
+            lo[d] = (int)floor(mn * G - 0.5) - 1;
+            hi[d] = (int)ceil(mx * G - 0.5) + 1;
+            if (lo[d] < 0) lo[d] = 0;
+            if (hi[d] > G - 1) hi[d] = G - 1;
+        }
+        for (int cz = lo[2]; cz <= hi[2]; ++cz)
+            for (int cy = lo[1]; cy <= hi[1]; ++cy)
+                for (int cx = lo[0]; cx <= hi[0]; ++cx) {
+                    int32_t* cell = lookup + ((int64_t)cz * G + cy) * G + cx;
+                    if (*cell != -1) continue;
+                    const double p[3] = { (cx + 0.5) / G, (cy + 0.5) / G, (cz + 0.5) / G };
+                    double s[4];
+                    bary3_numerators(v, id, p, s);
+                    if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0 && s[3] >= 0.0) *cell = (int32_t)t;
+                }
+    }
+    return ORC_OK;
+}
+
+/* Smallest id of a tetrahedron containing each point (closed), or -1: by trying all of them. */
+int orc3_brute_force(int64_t n_tet, const double* xyz, const int32_t* tet, int64_t n, const double* xp, int32_t* host)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        host[i] = -1;
+        for (int64_t t = 0; t < n_tet; ++t) {
+            const double* v[4];
+            int32_t id[4];
+            double s[4];
+            tet_vertices(xyz, tet, t, v, id);
+            bary3_numerators(v, id, xp + 3 * i, s);
+            if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0 && s[3] >= 0.0) {
+                host[i] = (int32_t)t;
+                break;
+            }
+        }
+    }
+    return ORC_OK;
+}

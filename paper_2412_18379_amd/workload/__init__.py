@@ -362,3 +362,121 @@ def random_weights(seed: int, channels=(2, 32, 32, 32, 2), bias_scale: float = 0
     rng = np.random.default_rng(seed + 1)
     bs = [np.ascontiguousarray((rng.standard_normal(w.shape[0]) * bias_scale).astype(np.float32)) for w in ws]
     return ws, bs
+
+
+# ----------------------------------------------------------------------------- 3D (tetrahedra)
+
+def kuhn_mesh(n: int, seed: int, jitter: float = 0.15):
+    """Tetrahedral mesh of [0,1]^3: an n x n x n point grid (node (i, j, k) at index (k n + j) n + i),
+    interior points moved by U(-jitter h, +jitter h) per axis (h = 1/(n-1)), points on a face of
+    the cube only within that face, and every cell split into the six tetrahedra of its Kuhn
+    (Freudenthal) subdivision along the main diagonal, which conforms across cells.  With
+    jitter <= 0.15 no tetrahedron can invert (a Kuhn tetrahedron's heights are >= h / sqrt(2)).
+    Returns (xyz float64 [n^3][3], tet int32 [6 (n-1)^3][4])."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / (n - 1)
+    g = np.linspace(0.0, 1.0, n)
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")  # X[k, j, i] = i h
+    P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    J = rng.uniform(-jitter, jitter, size=P.shape) * h
+    J[(P == 0.0) | (P == 1.0)] = 0.0  # points on a face of the cube stay on it
+    P = P + J
+    i, j, k = np.meshgrid(np.arange(n - 1), np.arange(n - 1), np.arange(n - 1), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+
+    def node(di, dj, dk):
+        return ((k + dk) * n + (j + dj)) * n + (i + di)
+
+    tets = []
+    unit = {0: (1, 0, 0), 1: (0, 1, 0), 2: (0, 0, 1)}
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        c = [0, 0, 0]
+        vs = [node(*c)]
+        for axis in perm:
+            c = [c[a] + unit[axis][a] for a in range(3)]
+            vs.append(node(*c))
+        tets.append(np.stack(vs, axis=1))
+    # cell-major order: the six tetrahedra of a cell are consecutive
+    tet = np.stack(tets, axis=1).reshape(-1, 4).astype(np.int32)
+    order = np.argsort(np.repeat((k * (n - 1) + j) * (n - 1) + i, 6), kind="stable")
+    return np.ascontiguousarray(P), np.ascontiguousarray(tet[order])
+
+
+class ABCFlow:
+    """Arnold-Beltrami-Childress flow on the unit cube (divergence-free):
+    u = A sin 2 pi z + C cos 2 pi y, v = B sin 2 pi x + A cos 2 pi z, w = C sin 2 pi y + B cos 2 pi x."""
+
+    def __init__(self, A: float = 1.0, B: float = 0.8, C: float = 0.6):
+        self.A, self.B, self.C = A, B, C
+
+    def __call__(self, x, y, z):
+        t = 2.0 * np.pi
+        u = self.A * np.sin(t * z) + self.C * np.cos(t * y)
+        v = self.B * np.sin(t * x) + self.A * np.cos(t * z)
+        w = self.C * np.sin(t * y) + self.B * np.cos(t * x)
+        return u, v, w
+
+
+def tet_longest_edges(xyz: np.ndarray, tet: np.ndarray) -> np.ndarray:
+    best = np.zeros(tet.shape[0])
+    for a in range(4):
+        for b in range(a + 1, 4):
+            best = np.maximum(best, np.linalg.norm(xyz[tet[:, b]] - xyz[tet[:, a]], axis=1))
+    return best
+
+
+def node_start_tets(n_nodes: int, tet: np.ndarray) -> np.ndarray:
+    """The smallest id of a tetrahedron incident to each node."""
+    start = np.full(n_nodes, np.iinfo(np.int32).max, dtype=np.int64)
+    ids = np.repeat(np.arange(tet.shape[0], dtype=np.int64), 4)
+    np.minimum.at(start, tet.reshape(-1), ids)
+    return start.astype(np.int32)
+
+
+def overlay_side_for_3d(n_tet: int) -> int:
+    return 1 << int(math.ceil(math.log2(n_tet ** (1.0 / 3.0))))
+
+
+@dataclass
+class Workload3D:
+    name: str
+    n_side: int
+    xyz: np.ndarray     # float64 [N_v][3]
+    tet: np.ndarray     # int32 [N_t][4] (orientation as generated)
+    xp: np.ndarray      # float64 [n][3] departure points
+    start: np.ndarray   # int32 [n] K_m
+    G: int              # overlay side (G^3 cells)
+    dt: float
+    dbar: float
+    flow: object = None
+
+    @property
+    def n_points(self) -> int:
+        return int(self.xp.shape[0])
+
+    @property
+    def n_tet(self) -> int:
+        return int(self.tet.shape[0])
+
+
+CONFIGS_3D = {
+    # name: grid side, mesh seed, displacement in mean element diameters
+    "t1": dict(n_side=16, seed=41, k=4.0),
+    "t2": dict(n_side=48, seed=42, k=10.0),
+    "t3": dict(n_side=100, seed=43, k=10.0),
+}
+
+
+def build_3d(name: str) -> Workload3D:
+    """Nodes of a jittered Kuhn mesh advected backwards one step in the ABC flow
+    (x_p = clamp(x_i - dt u(x_i), 0, 1)), starting from their smallest incident tetrahedron."""
+    cfg = CONFIGS_3D[name]
+    xyz, tet = kuhn_mesh(cfg["n_side"], cfg["seed"])
+    fl = ABCFlow()
+    dbar = float(tet_longest_edges(xyz, tet).mean())
+    u, v, w = fl(xyz[:, 0], xyz[:, 1], xyz[:, 2])
+    dt = cfg["k"] * dbar / float(np.mean(np.sqrt(u * u + v * v + w * w)))
+    xp = np.clip(xyz - dt * np.stack([u, v, w], axis=1), 0.0, 1.0)
+    return Workload3D(name=name, n_side=cfg["n_side"], xyz=xyz, tet=tet, xp=np.ascontiguousarray(xp),
+                      start=node_start_tets(xyz.shape[0], tet), G=overlay_side_for_3d(tet.shape[0]), dt=dt,
+                      dbar=dbar, flow=fl)
