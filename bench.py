@@ -37,6 +37,9 @@ CNN_MACS_PER_PIXEL = 2 * 32 * 9 + 32 * 32 * 9 * 2 + 32 * 2 * 9  # 19,584
 # 14 x 30 output tile: x 512/420), conv4 (K 32 x N 32 per region pixel: x 512/420)
 EXEC_MACS_PER_PIXEL_F32 = round(20 * 32 * 612 / 512 + 4096 + 4096 * 512 / 420 + 32 * 32 * 512 / 420)
 REC_BYTES = 60  # algorithmic bytes of one element record: 6 FP64 coordinates + 3 int32 neighbours
+# one tetrahedron record: 12 FP64 coordinates, 4 int32 neighbours and the 4 int32 node ids that put
+# each face's nodes in a fixed order
+TET_REC_BYTES = 128
 
 
 def log(msg):
@@ -108,6 +111,78 @@ def _off_edge(w, host, pts, eps=1e-9):
 
 def pct(a, q):
     return float(np.percentile(a, q))
+
+
+def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
+    """Alg. 1 on a tetrahedral mesh (the walk of Sec. 2.2 with four faces per element): the
+    departure points of a jittered Kuhn mesh advected in the ABC flow, walked from the element
+    before movement and from the overlay lookup, on the same GPU."""
+    import torch
+
+    from paper_2412_18379_amd import cnnsns as C
+    from paper_2412_18379_amd import workload as W
+
+    t0 = time.perf_counter()
+    w = W.build_3d(name)
+    mesh = C.Mesh3D(w.xyz, w.tet, overlay_side=w.G)
+    torch.cuda.synchronize()
+    log(f"3D workload {name}: {w.n_tet} tetrahedra, {w.n_points} points, G={w.G}, "
+        f"{mesh.device_bytes / 2**20:.0f} MiB resident ({time.perf_counter() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n = w.n_points
+    xp = torch.from_numpy(w.xp).to(dev)
+    start = torch.from_numpy(w.start).to(dev)
+    host = torch.empty(n, dtype=torch.int32, device=dev)
+    iters = torch.empty(n, dtype=torch.int32, device=dev)
+    status = torch.empty(n, dtype=torch.uint8, device=dev)
+
+    def timed(**kw):
+        for _ in range(warmup):
+            C.locate3d(mesh, xp, host=host, iters=iters, status=status, **kw)
+        torch.cuda.synchronize()
+        e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        for k in range(K):
+            e[k][0].record(stream)
+            C.locate3d(mesh, xp, host=host, iters=iters, status=status, **kw)
+            e[k][1].record(stream)
+        torch.cuda.synchronize()
+        return (np.array([a.elapsed_time(b) for a, b in e]), iters.cpu().numpy(), status.cpu().numpy(),
+                host.cpu().numpy())
+
+    plain_ms, it_p, st_p, host_p = timed(start=start)
+    asg_ms, it_a, st_a, host_a = timed()
+    log(f"3D plain SNS: {plain_ms.mean():.3f} ms, mean I_t {it_p.mean():.2f}; "
+        f"3D lookup start: {asg_ms.mean():.3f} ms, mean I_t {it_a.mean():.2f}")
+    # one 128-byte element record per iteration; per point x_p 24 B, the start (or lookup entry)
+    # 4 B and host, iteration count and status 9 B
+    per_point = 24 + 4 + 9
+    b_plain = TET_REC_BYTES * float(it_p.sum()) + n * per_point
+    b_asg = TET_REC_BYTES * float(it_a.sum()) + n * per_point
+    g_plain = b_plain / (plain_ms.mean() / 1e3) / 1e9
+    g_asg = b_asg / (asg_ms.mean() / 1e3) / 1e9
+    out = {
+        "workload": f"{w.n_side}^3-node jittered Kuhn mesh, {w.n_tet} tetrahedra, {n} node points advected "
+                    f"{W.CONFIGS_3D[name]['k']:g} mean element diameters in the ABC flow, G={w.G}",
+        "plain_sns": {"ms": round(float(plain_ms.mean()), 4), "points_per_s": round(n / (plain_ms.mean() / 1e3), 1),
+                      "mean_path_length": round(float(it_p.mean()), 3),
+                      "path_length_p50_p99_max": [pct(it_p, 50), pct(it_p, 99), int(it_p.max())],
+                      "found_frac": float(np.mean(st_p == C.FOUND))},
+        "lookup_start": {"ms": round(float(asg_ms.mean()), 4), "points_per_s": round(n / (asg_ms.mean() / 1e3), 1),
+                         "mean_path_length": round(float(it_a.mean()), 3),
+                         "path_length_p50_p99_max": [pct(it_a, 50), pct(it_a, 99), int(it_a.max())],
+                         "found_frac": float(np.mean(st_a == C.FOUND)),
+                         "host_agreement_with_plain": float(np.mean(host_a == host_p))},
+        "roofline": {"kernel": "k3_locate (plain SNS leg)", "bound": "hbm", "achieved": round(g_plain, 1),
+                     "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": round(g_plain / PEAK["hbm_GBps"], 4),
+                     "frac_of_measured_copy": round(g_plain / copy_gbps, 4),
+                     "traffic": traffic_for("k3_locate_plain", name),
+                     "algorithmic_per_launch": f"{b_plain:.4e} B (128 B x sum I_t + {per_point} B x n)",
+                     "lookup_start_leg": {"achieved": round(g_asg, 1), "frac": round(g_asg / PEAK["hbm_GBps"], 4),
+                                          "traffic": traffic_for("k3_locate_lookup", name)}},
+    }
+    mesh.close()
+    return out
 
 
 def cpu_baseline(w, ws, bs, band_rows: int):
@@ -281,6 +356,8 @@ def main():
     ap.add_argument("--cpu-band-rows", type=int, default=0, help="oracle sample band (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16-variant", action="store_true", help="skip the BF16 CNN leg of an FP32 run")
+    ap.add_argument("--walk3d", default="t3", choices=["t1", "t2", "t3", "none"],
+                    help="tetrahedral walk leg (none: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -533,6 +610,8 @@ def main():
         it32 = it32.cpu().numpy()
         res["precision_report"] = {"mean_path_f32_cnn": round(float(it32.mean()), 4),
                                    "mean_path_change": round(float(it_c.mean() - it32.mean()), 4)}
+    if args.walk3d != "none":
+        res["walk3d_leg"] = walk3d_leg(args.walk3d, K, args.warmup, copy_gbps)
     if not args.no_cpu_baseline:
         band = args.cpu_band_rows or {"c2": 1024, "c3": 1536, "c4": 1024}[args.workload]
         t0 = time.perf_counter()

@@ -70,6 +70,7 @@ enum {
 };
 
 typedef struct cnnsns_mesh_s* cnnsns_mesh;
+typedef struct cnnsns_mesh3_s* cnnsns_mesh3; /* a tetrahedral mesh (the 3D walk) */
 typedef struct cnnsns_server_s* cnnsns_server;
 
 /*
@@ -188,6 +189,54 @@ int cnnsns_locate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* sta
  */
 int cnnsns_interpolate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
                        double* out, void* stream);
+
+/*
+ * Build a device-resident tetrahedral mesh for the 3D walk (the paper's own
+ * setting: Sec. 2.2 with four nodes and four neighbours per element).
+ *   xyz          HOST FP64 [n_nodes][3] node coordinates.
+ *   tet          HOST int32 [n_tet][4] node indices per tetrahedron, 0-based,
+ *                either orientation (the library makes det[b-a, c-a, d-a] > 0
+ *                by swapping the 3rd and 4th node where it is negative;
+ *                neighbour j is across the face opposite the j-th node).
+ *   overlay_side G >= 1 for a G x G x G overlay lookup over the unit cube
+ *                (cell centre ((c + 1/2) / G per axis -> the smallest id of a
+ *                tetrahedron containing it, -1 if none), or 0 to choose
+ *                2^ceil(log2(cbrt(n_tet))) (at most 1024).
+ *   stream       stream for the upload and build kernels; the call waits for it.
+ *   out          receives the handle (owned by the library until
+ *                cnnsns_destroy_mesh3d).
+ * Inputs are copied.  Errors: EINVAL (null pointer, n_nodes < 4, n_tet < 1,
+ * overlay_side < 0 or > 1024), EMESH (a node index out of range, a
+ * tetrahedron of zero or non-finite volume, a face in more than two tetrahedra, or two
+ * tetrahedra overlapping across a face), ENOMEM, EHIP.
+ */
+int cnnsns_build_mesh3d(const double* xyz, int64_t n_nodes, const int32_t* tet, int64_t n_tet, int32_t overlay_side,
+                        void* stream, cnnsns_mesh3* out);
+
+/* Facts about a tetrahedral mesh; any output pointer may be NULL. */
+int cnnsns_mesh3d_info(cnnsns_mesh3 m, int64_t* n_tet, int32_t* overlay_side, int64_t* device_bytes);
+
+/* Free a tetrahedral mesh (synchronises the device first).  NULL is a no-op. */
+int cnnsns_destroy_mesh3d(cnnsns_mesh3 m);
+
+/*
+ * Locate n points in a tetrahedral mesh (Alg. 1 with four barycentric
+ * coordinates).  The numerator of coordinate j is the volume determinant of
+ * the tetrahedron with node j replaced by x_p, det[F - p] over the other three
+ * nodes F taken in node-id order with the sign of that permutation applied,
+ * so both tetrahedra of a face compute it identically; containment is closed
+ * (all >= 0), the smallest coordinate picks the face (ties to the lowest j)
+ * and the walk steps across it.  DEVICE arrays:
+ *   xp      FP64 [n][3] query points.
+ *   start   int32 [n] start elements, or NULL for the overlay lookup of the cell
+ *           holding x_p (cell of a coordinate: min(G-1, max(0, floor(x G)));
+ *           element 0 where the cell has no element).
+ *   max_iter, host, iters, status as in cnnsns_locate.
+ * Asynchronous on `stream`.  n == 0 is a no-op.  Errors: EINVAL (null mesh,
+ * xp or host, n < 0), EHIP.
+ */
+int cnnsns_locate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int32_t* start, int32_t max_iter, int32_t* host,
+                    int32_t* iters, uint8_t* status, void* stream);
 
 /*
  * Serving loop: a host scheduler that takes CNN-SNS tracking jobs on

@@ -24,6 +24,7 @@ SOURCES = {
     # file: extra flags
     "mesh.hip": ["-ffp-contract=off"],
     "sns_walk.hip": ["-ffp-contract=off"],
+    "mesh3d.hip": ["-ffp-contract=off"],
     "cnn.hip": [],
     "cnn_bf16.hip": [],
     "api.cpp": [],

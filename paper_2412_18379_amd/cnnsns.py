@@ -23,7 +23,7 @@ PRECISIONS = {"f32": F32, "bf16": BF16, "fp8": FP8E4M3}
 
 EXPORTS = (
     "cnnsns_build_mesh", "cnnsns_mesh_info", "cnnsns_destroy_mesh", "cnnsns_predict", "cnnsns_locate",
-    "cnnsns_interpolate",
+    "cnnsns_interpolate", "cnnsns_build_mesh3d", "cnnsns_mesh3d_info", "cnnsns_destroy_mesh3d", "cnnsns_locate3d",
     "cnnsns_server_create", "cnnsns_submit", "cnnsns_poll", "cnnsns_wait", "cnnsns_server_destroy",
     "cnnsns_last_error",
 )
@@ -57,6 +57,10 @@ def lib():
             "cnnsns_predict": [vp, vp, ctypes.POINTER(_Cnn), i32, vp, vp],
             "cnnsns_locate": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp],
             "cnnsns_interpolate": [vp, i64, vp, vp, vp, vp, vp],
+            "cnnsns_build_mesh3d": [vp, i64, vp, i64, i32, vp, ctypes.POINTER(vp)],
+            "cnnsns_mesh3d_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64)],
+            "cnnsns_destroy_mesh3d": [vp],
+            "cnnsns_locate3d": [vp, i64, vp, vp, i32, vp, vp, vp, vp],
             "cnnsns_server_create": [i64, i32, i32, i32, ctypes.POINTER(_Cnn), ctypes.POINTER(vp)],
             "cnnsns_submit": [vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)],
             "cnnsns_poll": [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
@@ -184,6 +188,53 @@ def locate(mesh: Mesh, xp: torch.Tensor, start: torch.Tensor = None, origin: tor
     _need(status, torch.uint8, (n,), "status")
     _check(lib().cnnsns_locate(mesh.handle, n, _ptr(xp), _ptr(start), _ptr(origin), _ptr(disp), int(max_iter),
                                _ptr(host), _ptr(iters), _ptr(status), _stream(stream)))
+    return host, iters, status
+
+
+class Mesh3D:
+    """A device-resident tetrahedral mesh (cnnsns_build_mesh3d).  xyz, tet are host numpy arrays."""
+
+    def __init__(self, xyz, tet, overlay_side: int = 0, stream=None):
+        import numpy as np
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tet = np.ascontiguousarray(tet, dtype=np.int32)
+        if xyz.ndim != 2 or xyz.shape[1] != 3 or tet.ndim != 2 or tet.shape[1] != 4:
+            raise ValueError("xyz must be [n,3] and tet [m,4]")
+        h = ctypes.c_void_p()
+        _check(lib().cnnsns_build_mesh3d(xyz.ctypes.data, xyz.shape[0], tet.ctypes.data, tet.shape[0],
+                                         int(overlay_side), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        n_tet, G, nbytes = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().cnnsns_mesh3d_info(h, ctypes.byref(n_tet), ctypes.byref(G), ctypes.byref(nbytes)))
+        self.n_tet, self.G, self.device_bytes = n_tet.value, G.value, nbytes.value
+
+    def close(self):
+        if self.handle:
+            _check(lib().cnnsns_destroy_mesh3d(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def locate3d(mesh: Mesh3D, xp: torch.Tensor, start: torch.Tensor = None, max_iter: int = 0,
+             host: torch.Tensor = None, iters: torch.Tensor = None, status: torch.Tensor = None, stream=None):
+    """Alg. 1 on a tetrahedral mesh (cnnsns_locate3d): (host, iters, status)."""
+    n = xp.shape[0]
+    _need(xp, torch.float64, (n, 3), "xp")
+    _need(start, torch.int32, (n,), "start")
+    dev = xp.device
+    host = torch.empty(n, dtype=torch.int32, device=dev) if host is None else host
+    iters = torch.empty(n, dtype=torch.int32, device=dev) if iters is None else iters
+    status = torch.empty(n, dtype=torch.uint8, device=dev) if status is None else status
+    _need(host, torch.int32, (n,), "host")
+    _need(iters, torch.int32, (n,), "iters")
+    _need(status, torch.uint8, (n,), "status")
+    _check(lib().cnnsns_locate3d(mesh.handle, n, _ptr(xp), _ptr(start), int(max_iter), _ptr(host), _ptr(iters),
+                                 _ptr(status), _stream(stream)))
     return host, iters, status
 
 

@@ -125,6 +125,48 @@ int cnnsns_locate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* sta
     });
 }
 
+int cnnsns_build_mesh3d(const double* xyz, int64_t n_nodes, const int32_t* tet, int64_t n_tet, int32_t overlay_side,
+                        void* stream, cnnsns_mesh3* out)
+{
+    return guarded([&] {
+        if (!xyz || !tet || !out) fail(CNNSNS_EINVAL, "build_mesh3d: NULL argument");
+        *out = nullptr;
+        if (n_nodes < 4 || n_tet < 1) fail(CNNSNS_EINVAL, "build_mesh3d: need n_nodes >= 4 and n_tet >= 1");
+        if (n_tet > (int64_t)INT32_MAX / 4 || n_nodes >= (int64_t)INT32_MAX)
+            fail(CNNSNS_EINVAL, "build_mesh3d: ids must fit in int32");
+        if (overlay_side < 0 || overlay_side > 1024) fail(CNNSNS_EINVAL, "build_mesh3d: overlay_side out of range");
+        *out = build_mesh3(xyz, n_nodes, tet, n_tet, overlay_side, static_cast<hipStream_t>(stream));
+    });
+}
+
+int cnnsns_mesh3d_info(cnnsns_mesh3 m, int64_t* n_tet, int32_t* overlay_side, int64_t* device_bytes)
+{
+    return guarded([&] {
+        if (!m) fail(CNNSNS_EINVAL, "mesh3d_info: NULL mesh");
+        if (n_tet) *n_tet = m->n_tet;
+        if (overlay_side) *overlay_side = m->G;
+        if (device_bytes) *device_bytes = m->device_bytes;
+    });
+}
+
+int cnnsns_destroy_mesh3d(cnnsns_mesh3 m)
+{
+    return guarded([&] { destroy_mesh3(m); });
+}
+
+int cnnsns_locate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int32_t* start, int32_t max_iter, int32_t* host,
+                    int32_t* iters, uint8_t* status, void* stream)
+{
+    return guarded([&] {
+        if (!m) fail(CNNSNS_EINVAL, "locate3d: NULL mesh");
+        if (n < 0) fail(CNNSNS_EINVAL, "locate3d: n must be >= 0");
+        if (n == 0) return;
+        if (!xp || !host) fail(CNNSNS_EINVAL, "locate3d: xp and host must not be NULL");
+        DeviceScope ds(m->device);
+        launch_locate3(*m, n, xp, start, max_iter, host, iters, status, static_cast<hipStream_t>(stream));
+    });
+}
+
 int cnnsns_interpolate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
                        double* out, void* stream)
 {

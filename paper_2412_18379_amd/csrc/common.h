@@ -21,6 +21,16 @@ struct alignas(64) ElemRec {
 };
 static_assert(sizeof(ElemRec) == 64, "element record must be 64 bytes");
 
+// One tetrahedron as the 3D walk reads it: its four positively oriented
+// vertices, the neighbour across the face opposite each (-1 on the
+// boundary) and the four node ids, in one 128-byte record (one line per hop).
+struct alignas(128) TetRec {
+    double v[4][3];
+    int32_t nbr[4];
+    int32_t id[4];
+};
+static_assert(sizeof(TetRec) == 128, "tetrahedron record must be 128 bytes");
+
 // Error with a status code; thrown inside the library and turned into a
 // return code plus a thread-local message at the C boundary.
 struct Error {
@@ -49,7 +59,24 @@ struct cnnsns_mesh_s {
     size_t cnn_ws_bytes = 0;
 };
 
+struct cnnsns_mesh3_s {
+    int device = 0;
+    int64_t n_nodes = 0;
+    int64_t n_tet = 0;
+    int32_t G = 0;
+    cnnsns::TetRec* rec = nullptr;  // device [n_tet]
+    int32_t* lookup = nullptr;      // device [G][G][G]
+    int64_t device_bytes = 0;
+};
+
 namespace cnnsns {
+
+// mesh3d.hip
+cnnsns_mesh3 build_mesh3(const double* xyz, int64_t n_nodes, const int32_t* tet, int64_t n_tet, int32_t G,
+                         hipStream_t stream);
+void destroy_mesh3(cnnsns_mesh3 m);
+void launch_locate3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const int32_t* start, int32_t max_iter,
+                    int32_t* host, int32_t* iters, uint8_t* status, hipStream_t stream);
 
 // mesh.hip
 cnnsns_mesh build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, int64_t n_tri, int32_t G,

@@ -1,0 +1,421 @@
+// The SNS walk on tetrahedral meshes: the paper's own setting (Sec. 2.2 with
+// four nodes and four neighbours per element; Alg. 1), with the starts of the
+// 2D build: the element before movement, or the overlay lookup of the cell
+// holding x_p (a G x G x G grid on the unit cube).
+//
+// Mesh residency is built on the device as in 2D: positive orientation,
+// node -> tetrahedron incidence lists, the neighbour across each face, one
+// 128-byte record per tetrahedron (four vertices, four neighbours, four node
+// ids: one hop is one 128-byte line) and the overlay lookup.
+//
+// Barycentric numerators: s_j = |S_j| is the volume determinant with vertex
+// j replaced by x_p.  Moving x_p to the front gives s_j = sigma_j det[F - p]
+// with F the other three vertices in the element's order and sigma =
+// (+, -, +, -).  Each face is evaluated with its vertices sorted by node id
+// (the sign of that permutation applied), so the two elements that share a
+// face compute the same number for it and their numerators are exact
+// negatives: FP64, no fused multiply-add, expressions as written.
+#pragma clang fp contract(off)
+
+#include <hipcub/hipcub.hpp>
+
+#include <climits>
+#include <cmath>
+
+#include "common.h"
+
+namespace cnnsns {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int64_t kChunk = 512;  // points per wavefront
+
+enum : int { ERR_INDEX = 1, ERR_VOLUME = 2, ERR_FACE3 = 4, ERR_OVERLAP = 8 };
+
+inline unsigned grid_for(int64_t n)
+{
+    return (unsigned)((n + kBlock - 1) / kBlock);
+}
+
+// det[a - p, b - p, c - p] = ax (by cz - bz cy) - ay (bx cz - bz cx) + az (bx cy - by cx)
+__device__ __forceinline__ double orient3(const double3& p, const double3& a, const double3& b, const double3& c)
+{
+    const double ax = a.x - p.x, ay = a.y - p.y, az = a.z - p.z;
+    const double bx = b.x - p.x, by = b.y - p.y, bz = b.z - p.z;
+    const double cx = c.x - p.x, cy = c.y - p.y, cz = c.z - p.z;
+    const double t1 = by * cz - bz * cy, t2 = bx * cz - bz * cx, t3 = bx * cy - by * cx;
+    return ax * t1 - ay * t2 + az * t3;
+}
+
+// Numerator of the face opposite vertex j (vertices f0 < f1 < f2 in element order), with the
+// face's vertices put in node-id order by the three compare-exchanges (0,1), (1,2), (0,1).
+__device__ __forceinline__ double face_numerator(const double3& p, const double3* v, const int32_t* id, int j)
+{
+    int f0 = j == 0 ? 1 : 0, f1 = j <= 1 ? 2 : 1, f2 = j <= 2 ? 3 : 2;
+    bool neg = (j & 1) != 0;
+    if (id[f0] > id[f1]) { const int t = f0; f0 = f1; f1 = t; neg = !neg; }
+    if (id[f1] > id[f2]) { const int t = f1; f1 = f2; f2 = t; neg = !neg; }
+    if (id[f0] > id[f1]) { const int t = f0; f0 = f1; f1 = t; neg = !neg; }
+    const double d = orient3(p, v[f0], v[f1], v[f2]);
+    return neg ? -d : d;
+}
+
+__device__ __forceinline__ double3 d3(const double* q)
+{
+    return double3{ q[0], q[1], q[2] };
+}
+
+// Positive orientation (det[b - a, c - a, d - a] > 0): swap the 3rd and 4th vertex when negative.
+__global__ void k3_canonicalise(int64_t n_tet, int64_t n_nodes, const double* __restrict__ xyz,
+                                const int32_t* __restrict__ tet_in, int32_t* __restrict__ tet, int* err)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tet) return;
+    int32_t q[4];
+    for (int k = 0; k < 4; ++k) q[k] = tet_in[4 * t + k];
+    for (int k = 0; k < 4; ++k)
+        if (q[k] < 0 || q[k] >= n_nodes) {
+            atomicOr(err, ERR_INDEX);
+            for (int m = 0; m < 4; ++m) tet[4 * t + m] = 0;
+            return;
+        }
+    const double vol = orient3(d3(xyz + 3 * (int64_t)q[0]), d3(xyz + 3 * (int64_t)q[1]), d3(xyz + 3 * (int64_t)q[2]),
+                               d3(xyz + 3 * (int64_t)q[3]));
+    if (!(vol > 0.0 || vol < 0.0) || !isfinite(vol)) atomicOr(err, ERR_VOLUME);  // zero, NaN or infinite
+    tet[4 * t] = q[0];
+    tet[4 * t + 1] = q[1];
+    tet[4 * t + 2] = vol < 0.0 ? q[3] : q[2];
+    tet[4 * t + 3] = vol < 0.0 ? q[2] : q[3];
+}
+
+__global__ void k3_degree(int64_t n_tet, const int32_t* __restrict__ tet, unsigned long long* deg)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 4 * n_tet) return;
+    atomicAdd(&deg[tet[k]], 1ull);
+}
+
+__global__ void k3_fill(int64_t n_tet, const int32_t* __restrict__ tet, unsigned long long* cursor,
+                        int32_t* __restrict__ inc)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 4 * n_tet) return;
+    const unsigned long long pos = atomicAdd(&cursor[tet[k]], 1ull);
+    inc[pos] = (int32_t)(k / 4);
+}
+
+// Neighbour across the face opposite vertex j of t: the one other tetrahedron around the face's
+// smallest node that holds all three face nodes.  A third holder is an error, and so is a
+// neighbour on the same side of the face as t (the two would overlap).
+__global__ void k3_neighbours(int64_t n_tet, const double* __restrict__ xyz, const int32_t* __restrict__ tet,
+                              const unsigned long long* __restrict__ first, const int32_t* __restrict__ inc,
+                              int32_t* __restrict__ nbr, int* err)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 4 * n_tet) return;
+    const int64_t t = k / 4;
+    const int j = (int)(k - 4 * t);
+    int32_t f[3], m = 0;
+    for (int a = 0; a < 4; ++a)
+        if (a != j) f[m++] = tet[4 * t + a];
+    int32_t lo = f[0] < f[1] ? (f[0] < f[2] ? f[0] : f[2]) : (f[1] < f[2] ? f[1] : f[2]);
+    int32_t found = -1;
+    int bad = 0;
+    for (unsigned long long q = first[lo]; q < first[lo + 1]; ++q) {
+        const int32_t s = inc[q];
+        if (s == t) continue;
+        int hits = 0, other = -1;
+        for (int a = 0; a < 4; ++a) {
+            const int32_t x = tet[4 * (int64_t)s + a];
+            if (x == f[0] || x == f[1] || x == f[2]) ++hits;
+            else other = x;
+        }
+        if (hits != 3) continue;
+        if (found >= 0) bad |= ERR_FACE3;
+        found = s;
+        // the neighbour's fourth node must lie on the other side of the face from t's own
+        const double3 A = d3(xyz + 3 * (int64_t)f[0]), B = d3(xyz + 3 * (int64_t)f[1]), C = d3(xyz + 3 * (int64_t)f[2]);
+        const double own = orient3(d3(xyz + 3 * (int64_t)tet[4 * t + j]), A, B, C);
+        const double opp = orient3(d3(xyz + 3 * (int64_t)other), A, B, C);
+        if ((own > 0.0 && opp > 0.0) || (own < 0.0 && opp < 0.0)) bad |= ERR_OVERLAP;
+    }
+    if (bad) atomicOr(err, bad);
+    nbr[k] = found;
+}
+
+__global__ void k3_pack(int64_t n_tet, const double* __restrict__ xyz, const int32_t* __restrict__ tet,
+                        const int32_t* __restrict__ nbr, TetRec* __restrict__ rec)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tet) return;
+    TetRec r;
+    for (int k = 0; k < 4; ++k) {
+        const int32_t v = tet[4 * t + k];
+        r.v[k][0] = xyz[3 * (int64_t)v];
+        r.v[k][1] = xyz[3 * (int64_t)v + 1];
+        r.v[k][2] = xyz[3 * (int64_t)v + 2];
+        r.nbr[k] = nbr[4 * t + k];
+        r.id[k] = v;
+    }
+    rec[t] = r;
+}
+
+__device__ __forceinline__ void load_tet(const TetRec* __restrict__ rec, int64_t t, double3* v, int32_t* nb,
+                                         int32_t* id)
+{
+    const double2* q = reinterpret_cast<const double2*>(rec + t);
+    const double2 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4], f = q[5];
+    v[0] = double3{ a.x, a.y, b.x };
+    v[1] = double3{ b.y, c.x, c.y };
+    v[2] = double3{ d.x, d.y, e.x };
+    v[3] = double3{ e.y, f.x, f.y };
+    const int4 n4 = reinterpret_cast<const int4*>(rec + t)[6], i4 = reinterpret_cast<const int4*>(rec + t)[7];
+    nb[0] = n4.x; nb[1] = n4.y; nb[2] = n4.z; nb[3] = n4.w;
+    id[0] = i4.x; id[1] = i4.y; id[2] = i4.z; id[3] = i4.w;
+}
+
+__global__ void k3_fill_i32(int64_t n, int32_t* p, int32_t v)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+__global__ void k3_lookup_finish(int64_t n, int32_t* p)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n && p[k] == INT_MAX) p[k] = -1;
+}
+
+__device__ __forceinline__ int32_t cell3(double x, int32_t G)
+{
+    return (int32_t)fmin(fmax(floor(x * (double)G), 0.0), (double)(G - 1));
+}
+
+// The overlay cells whose centres a tetrahedron contains: its bounding box grown by one cell,
+// each centre tested with the walk's numerators; the smallest containing id wins.
+__global__ void k3_lookup_raster(int64_t n_tet, const TetRec* __restrict__ rec, int32_t G, int32_t* lookup)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tet) return;
+    double3 v[4];
+    int32_t nb[4], id[4];
+    load_tet(rec, t, v, nb, id);
+    const double g = (double)G;
+    int32_t lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        double mn = d == 0 ? v[0].x : (d == 1 ? v[0].y : v[0].z), mx = mn;
+        for (int k = 1; k < 4; ++k) {
+            const double c = d == 0 ? v[k].x : (d == 1 ? v[k].y : v[k].z);
+            mn = fmin(mn, c);
+            mx = fmax(mx, c);
+        }
+        // clamped before conversion (fmax and fmin return the number when the other is NaN)
+        const double f0 = fmax(floor(mn * g - 0.5) - 1.0, 0.0), f1 = fmin(ceil(mx * g - 0.5) + 1.0, g - 1.0);
+        lo[d] = f0 > g - 1.0 ? G : (int32_t)f0;
+        hi[d] = f1 < 0.0 ? -1 : (int32_t)f1;
+    }
+    for (int32_t cz = lo[2]; cz <= hi[2]; ++cz)
+        for (int32_t cy = lo[1]; cy <= hi[1]; ++cy)
+            for (int32_t cx = lo[0]; cx <= hi[0]; ++cx) {
+                const double3 p{ ((double)cx + 0.5) / g, ((double)cy + 0.5) / g, ((double)cz + 0.5) / g };
+                bool in = true;
+                for (int j = 0; j < 4 && in; ++j) in = face_numerator(p, v, id, j) >= 0.0;
+                if (in) atomicMin(&lookup[((int64_t)cz * G + cy) * G + cx], (int32_t)t);
+            }
+}
+
+// Alg. 1 for a batch of points, one lane per point with the wave-local refill of the 2D walk:
+// a wavefront owns kChunk consecutive points and hands unstarted ones to lanes that finish.
+template <bool GIVEN>
+__global__ __launch_bounds__(kBlock) void k3_locate(const TetRec* __restrict__ rec, int64_t n_tet, int64_t n,
+                                                    const double* __restrict__ xp, const int32_t* __restrict__ start,
+                                                    const int32_t* __restrict__ lookup, int32_t G, int32_t max_iter,
+                                                    int32_t* __restrict__ host, int32_t* __restrict__ iters,
+                                                    uint8_t* __restrict__ status)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int64_t base = wave * kChunk;
+    const int64_t n_slots = n - base < kChunk ? n - base : kChunk;
+    if (n_slots <= 0) return;
+    int64_t next = 0;
+    bool active = false;
+    int64_t idx = 0;
+    double3 p{ 0.0, 0.0, 0.0 };
+    int32_t K = 0, I = 0;
+    for (;;) {
+        const uint64_t idle = __ballot(!active);
+        if (idle != 0 && next < n_slots) {
+            const uint32_t lo = (uint32_t)idle, hi = (uint32_t)(idle >> 32);
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+            if (!active && next + rank < n_slots) {
+                idx = base + next + rank;
+                p = double3{ xp[3 * idx], xp[3 * idx + 1], xp[3 * idx + 2] };
+                if (GIVEN) {
+                    K = start[idx];
+                } else {
+                    K = lookup[((int64_t)cell3(p.z, G) * G + cell3(p.y, G)) * G + cell3(p.x, G)];
+                    if (K < 0) K = 0;  // a cell with no element: start at element 0
+                }
+                I = 0;
+                if (K < 0 || K >= n_tet) {
+                    host[idx] = -1;
+                    if (iters) iters[idx] = 0;
+                    if (status) status[idx] = CNNSNS_BADSTART;
+                } else {
+                    active = true;
+                }
+            }
+            next += __popcll(idle);
+        }
+        if (__ballot(active) == 0) {
+            if (next >= n_slots) break;
+            continue;
+        }
+        if (active) {
+            I = I + 1;
+            double3 v[4];
+            int32_t nb[4], id[4];
+            load_tet(rec, K, v, nb, id);
+            double s[4];
+            for (int j = 0; j < 4; ++j) s[j] = face_numerator(p, v, id, j);
+            int fin = -1;
+            if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0 && s[3] >= 0.0) {
+                fin = CNNSNS_FOUND;
+            } else {
+                // eq. (5): the smallest coordinate, ties to the lowest index
+                int jm = 0;
+                for (int j = 1; j < 4; ++j)
+                    if (s[j] < s[jm]) jm = j;
+                const int32_t m = nb[jm];
+                if (m == -1) {
+                    fin = CNNSNS_OUTSIDE;
+                } else {
+                    K = m;
+                    if (I >= max_iter) fin = CNNSNS_MAXITER;
+                }
+            }
+            if (fin >= 0) {
+                host[idx] = K;
+                if (iters) iters[idx] = I;
+                if (status) status[idx] = (uint8_t)fin;
+                active = false;
+            }
+        }
+    }
+}
+
+template <class T>
+struct DevBuf3 {
+    T* p = nullptr;
+    explicit DevBuf3(size_t count)
+    {
+        if (count == 0) count = 1;
+        if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(CNNSNS_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+    }
+    ~DevBuf3() { if (p) (void)hipFree(p); }
+    T* release() { T* q = p; p = nullptr; return q; }
+    DevBuf3(const DevBuf3&) = delete;
+    DevBuf3& operator=(const DevBuf3&) = delete;
+};
+
+}  // namespace
+
+cnnsns_mesh3 build_mesh3(const double* xyz, int64_t n_nodes, const int32_t* tet, int64_t n_tet, int32_t G,
+                         hipStream_t stream)
+{
+    if (G == 0) {
+        const int e = (int)std::ceil(std::log2(std::cbrt((double)n_tet)));
+        G = 1 << (e < 0 ? 0 : (e > 10 ? 10 : e));
+    }
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    DevBuf3<double> d_xyz((size_t)(3 * n_nodes));
+    DevBuf3<int32_t> d_in((size_t)(4 * n_tet)), d_tet((size_t)(4 * n_tet)), d_nbr((size_t)(4 * n_tet)),
+        d_inc((size_t)(4 * n_tet));
+    DevBuf3<unsigned long long> d_deg((size_t)n_nodes + 1), d_first((size_t)n_nodes + 1), d_cursor((size_t)n_nodes + 1);
+    DevBuf3<int> d_err(1);
+    DevBuf3<TetRec> d_rec((size_t)n_tet);
+    const int64_t ncell = (int64_t)G * G * G;
+    DevBuf3<int32_t> d_lookup((size_t)ncell);
+
+    hip_check(hipMemcpyAsync(d_xyz.p, xyz, sizeof(double) * 3 * (size_t)n_nodes, hipMemcpyHostToDevice, stream),
+              "copy xyz");
+    hip_check(hipMemcpyAsync(d_in.p, tet, sizeof(int32_t) * 4 * (size_t)n_tet, hipMemcpyHostToDevice, stream),
+              "copy tet");
+    hip_check(hipMemsetAsync(d_err.p, 0, sizeof(int), stream), "memset");
+    hip_check(hipMemsetAsync(d_deg.p, 0, sizeof(unsigned long long) * ((size_t)n_nodes + 1), stream), "memset");
+    k3_canonicalise<<<grid_for(n_tet), kBlock, 0, stream>>>(n_tet, n_nodes, d_xyz.p, d_in.p, d_tet.p, d_err.p);
+    k3_degree<<<grid_for(4 * n_tet), kBlock, 0, stream>>>(n_tet, d_tet.p, d_deg.p);
+    size_t tmp_bytes = 0;
+    hip_check(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, d_deg.p, d_first.p, (int)(n_nodes + 1), stream),
+              "scan size");
+    {
+        DevBuf3<unsigned char> d_tmp(tmp_bytes);
+        hip_check(hipcub::DeviceScan::ExclusiveSum(d_tmp.p, tmp_bytes, d_deg.p, d_first.p, (int)(n_nodes + 1), stream),
+                  "scan");
+        hip_check(hipMemcpyAsync(d_cursor.p, d_first.p, sizeof(unsigned long long) * ((size_t)n_nodes + 1),
+                                 hipMemcpyDeviceToDevice, stream), "copy cursor");
+        k3_fill<<<grid_for(4 * n_tet), kBlock, 0, stream>>>(n_tet, d_tet.p, d_cursor.p, d_inc.p);
+        k3_neighbours<<<grid_for(4 * n_tet), kBlock, 0, stream>>>(n_tet, d_xyz.p, d_tet.p, d_first.p, d_inc.p,
+                                                                  d_nbr.p, d_err.p);
+        k3_pack<<<grid_for(n_tet), kBlock, 0, stream>>>(n_tet, d_xyz.p, d_tet.p, d_nbr.p, d_rec.p);
+        k3_fill_i32<<<grid_for(ncell), kBlock, 0, stream>>>(ncell, d_lookup.p, INT_MAX);
+        k3_lookup_raster<<<grid_for(n_tet), kBlock, 0, stream>>>(n_tet, d_rec.p, G, d_lookup.p);
+        k3_lookup_finish<<<grid_for(ncell), kBlock, 0, stream>>>(ncell, d_lookup.p);
+        hip_check(hipGetLastError(), "3D mesh build kernels");
+        int err = 0;
+        hip_check(hipMemcpyAsync(&err, d_err.p, sizeof(int), hipMemcpyDeviceToHost, stream), "copy err");
+        hip_check(hipStreamSynchronize(stream), "3D mesh build");
+        if (err & ERR_INDEX) fail(CNNSNS_EMESH, "build_mesh3d: node index out of range");
+        if (err & ERR_VOLUME) fail(CNNSNS_EMESH, "build_mesh3d: a tetrahedron of zero or non-finite volume");
+        if (err & ERR_FACE3) fail(CNNSNS_EMESH, "build_mesh3d: a face is shared by more than two tetrahedra");
+        if (err & ERR_OVERLAP) fail(CNNSNS_EMESH, "build_mesh3d: two tetrahedra overlap across a face");
+    }
+    auto* m = new cnnsns_mesh3_s();
+    m->device = dev;
+    m->n_nodes = n_nodes;
+    m->n_tet = n_tet;
+    m->G = G;
+    m->rec = d_rec.release();
+    m->lookup = d_lookup.release();
+    m->device_bytes = (int64_t)(sizeof(TetRec) * (size_t)n_tet + sizeof(int32_t) * (size_t)ncell);
+    return m;
+}
+
+void destroy_mesh3(cnnsns_mesh3 m)
+{
+    if (!m) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(m->rec);
+    (void)hipFree(m->lookup);
+    (void)hipSetDevice(cur);
+    delete m;
+}
+
+void launch_locate3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const int32_t* start, int32_t max_iter,
+                    int32_t* host, int32_t* iters, uint8_t* status, hipStream_t stream)
+{
+    if (n == 0) return;
+    if (max_iter <= 0) max_iter = 1 << 20;
+    const int64_t waves = (n + kChunk - 1) / kChunk;
+    const int64_t blocks = (waves * kWave + kBlock - 1) / kBlock;
+    if (blocks > (int64_t)INT32_MAX) fail(CNNSNS_EINVAL, "locate3d: too many points");
+    if (start)
+        k3_locate<true><<<(unsigned)blocks, kBlock, 0, stream>>>(m.rec, m.n_tet, n, xp, start, m.lookup, m.G, max_iter,
+                                                                 host, iters, status);
+    else
+        k3_locate<false><<<(unsigned)blocks, kBlock, 0, stream>>>(m.rec, m.n_tet, n, xp, start, m.lookup, m.G,
+                                                                  max_iter, host, iters, status);
+    hip_check(hipGetLastError(), "locate3d launch");
+}
+
+}  // namespace cnnsns

@@ -34,6 +34,8 @@ SOURCES = {
     "k_locate_plain": ("sns_walk.hip",),
     "k_locate_cnn": ("sns_walk.hip",),
     "k_interp": ("sns_walk.hip",),
+    "k3_locate_plain": ("mesh3d.hip",),
+    "k3_locate_lookup": ("mesh3d.hip",),
 }
 
 

@@ -71,6 +71,18 @@ void launch_interp(const cnnsns_mesh_s&, int64_t, const double*, const int32_t*,
 {
 }
 
+cnnsns_mesh3 build_mesh3(const double*, int64_t, const int32_t*, int64_t, int32_t, hipStream_t)
+{
+    fail(CNNSNS_EINVAL, "the mock runtime has no 3D meshes");
+}
+
+void destroy_mesh3(cnnsns_mesh3) {}
+
+void launch_locate3(const cnnsns_mesh3_s&, int64_t, const double*, const int32_t*, int32_t, int32_t*, int32_t*,
+                    uint8_t*, hipStream_t)
+{
+}
+
 void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t*, const double* origin,
                    const float* disp, int32_t, int32_t* host, int32_t* iters, uint8_t*, hipStream_t)
 {
