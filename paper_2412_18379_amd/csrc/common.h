@@ -21,13 +21,17 @@ struct alignas(64) ElemRec {
 };
 static_assert(sizeof(ElemRec) == 64, "element record must be 64 bytes");
 
-// One tetrahedron as the 3D walk reads it: its four positively oriented
-// vertices, the neighbour across the face opposite each (-1 on the
-// boundary) and the four node ids, in one 128-byte record (one line per hop).
+// One tetrahedron as the 3D walk reads it, in one 128-byte record (one line
+// per hop): its vertices in ascending node-id order, the neighbour across the
+// face opposite each (-1 on the boundary), the orientation of that vertex
+// order (+1 or -1), and each vertex's position in the positively oriented
+// element order (one byte per vertex, low byte first).
 struct alignas(128) TetRec {
     double v[4][3];
     int32_t nbr[4];
-    int32_t id[4];
+    int32_t orient;
+    uint32_t pos;
+    int32_t pad[2];
 };
 static_assert(sizeof(TetRec) == 128, "tetrahedron record must be 128 bytes");
 

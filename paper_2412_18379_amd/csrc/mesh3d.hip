@@ -5,16 +5,21 @@
 //
 // Mesh residency is built on the device as in 2D: positive orientation,
 // node -> tetrahedron incidence lists, the neighbour across each face, one
-// 128-byte record per tetrahedron (four vertices, four neighbours, four node
-// ids: one hop is one 128-byte line) and the overlay lookup.
+// 128-byte record per tetrahedron (one hop is one 128-byte line) and the
+// overlay lookup.
 //
 // Barycentric numerators: s_j = |S_j| is the volume determinant with vertex
 // j replaced by x_p.  Moving x_p to the front gives s_j = sigma_j det[F - p]
-// with F the other three vertices in the element's order and sigma =
-// (+, -, +, -).  Each face is evaluated with its vertices sorted by node id
-// (the sign of that permutation applied), so the two elements that share a
-// face compute the same number for it and their numerators are exact
-// negatives: FP64, no fused multiply-add, expressions as written.
+// with F the other three vertices in order and sigma = (+, -, +, -) for a
+// positively oriented vertex order, all signs flipped for a negative one.
+// Each face is evaluated with its vertices in node-id order, so the two
+// elements that share a face compute the same number for it and their
+// numerators are exact negatives (FP64, no fused multiply-add, expressions as
+// written).  The record stores the vertices already in node-id order: every
+// face's vertices are then in order with fixed register indices, and the
+// record keeps the orientation of that order and each vertex's position in the
+// positively oriented element order, which breaks ties of eq. (5) by the
+// lowest position there.
 #pragma clang fp contract(off)
 
 #include <hipcub/hipcub.hpp>
@@ -28,8 +33,6 @@ namespace cnnsns {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kWave = 64;
-constexpr int64_t kChunk = 512;  // points per wavefront
 
 enum : int { ERR_INDEX = 1, ERR_VOLUME = 2, ERR_FACE3 = 4, ERR_OVERLAP = 8 };
 
@@ -48,17 +51,16 @@ __device__ __forceinline__ double orient3(const double3& p, const double3& a, co
     return ax * t1 - ay * t2 + az * t3;
 }
 
-// Numerator of the face opposite vertex j (vertices f0 < f1 < f2 in element order), with the
-// face's vertices put in node-id order by the three compare-exchanges (0,1), (1,2), (0,1).
-__device__ __forceinline__ double face_numerator(const double3& p, const double3* v, const int32_t* id, int j)
+// The four numerators of a record's element (vertices in node-id order, orientation o): the
+// face opposite vertex k is the other three in order, signed sigma_k o.
+__device__ __forceinline__ void numerators(const double3& p, const double3* v, int32_t o, double* s)
 {
-    int f0 = j == 0 ? 1 : 0, f1 = j <= 1 ? 2 : 1, f2 = j <= 2 ? 3 : 2;
-    bool neg = (j & 1) != 0;
-    if (id[f0] > id[f1]) { const int t = f0; f0 = f1; f1 = t; neg = !neg; }
-    if (id[f1] > id[f2]) { const int t = f1; f1 = f2; f2 = t; neg = !neg; }
-    if (id[f0] > id[f1]) { const int t = f0; f0 = f1; f1 = t; neg = !neg; }
-    const double d = orient3(p, v[f0], v[f1], v[f2]);
-    return neg ? -d : d;
+    const double a = orient3(p, v[1], v[2], v[3]), b = orient3(p, v[0], v[2], v[3]);
+    const double c = orient3(p, v[0], v[1], v[3]), d = orient3(p, v[0], v[1], v[2]);
+    s[0] = o > 0 ? a : -a;
+    s[1] = o > 0 ? -b : b;
+    s[2] = o > 0 ? c : -c;
+    s[3] = o > 0 ? -d : d;
 }
 
 __device__ __forceinline__ double3 d3(const double* q)
@@ -144,25 +146,46 @@ __global__ void k3_neighbours(int64_t n_tet, const double* __restrict__ xyz, con
     nbr[k] = found;
 }
 
+// Record of tetrahedron t: its vertices sorted by node id (five compare-exchanges, the parity
+// of the permutation gives the orientation of the sorted order, the element order being
+// positive), with the neighbours and positions carried along.
 __global__ void k3_pack(int64_t n_tet, const double* __restrict__ xyz, const int32_t* __restrict__ tet,
                         const int32_t* __restrict__ nbr, TetRec* __restrict__ rec)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tet) return;
+    int32_t id[4], nb[4], ps[4];
+    for (int k = 0; k < 4; ++k) {
+        id[k] = tet[4 * t + k];
+        nb[k] = nbr[4 * t + k];
+        ps[k] = k;
+    }
+    int32_t o = 1;
+    const int net[5][2] = { { 0, 1 }, { 2, 3 }, { 0, 2 }, { 1, 3 }, { 1, 2 } };
+    for (int e = 0; e < 5; ++e) {
+        const int i = net[e][0], j = net[e][1];
+        if (id[i] > id[j]) {
+            int32_t x = id[i]; id[i] = id[j]; id[j] = x;
+            x = nb[i]; nb[i] = nb[j]; nb[j] = x;
+            x = ps[i]; ps[i] = ps[j]; ps[j] = x;
+            o = -o;
+        }
+    }
     TetRec r;
     for (int k = 0; k < 4; ++k) {
-        const int32_t v = tet[4 * t + k];
-        r.v[k][0] = xyz[3 * (int64_t)v];
-        r.v[k][1] = xyz[3 * (int64_t)v + 1];
-        r.v[k][2] = xyz[3 * (int64_t)v + 2];
-        r.nbr[k] = nbr[4 * t + k];
-        r.id[k] = v;
+        r.v[k][0] = xyz[3 * (int64_t)id[k]];
+        r.v[k][1] = xyz[3 * (int64_t)id[k] + 1];
+        r.v[k][2] = xyz[3 * (int64_t)id[k] + 2];
+        r.nbr[k] = nb[k];
     }
+    r.orient = o;
+    r.pos = (uint32_t)ps[0] | ((uint32_t)ps[1] << 8) | ((uint32_t)ps[2] << 16) | ((uint32_t)ps[3] << 24);
+    r.pad[0] = r.pad[1] = 0;
     rec[t] = r;
 }
 
 __device__ __forceinline__ void load_tet(const TetRec* __restrict__ rec, int64_t t, double3* v, int32_t* nb,
-                                         int32_t* id)
+                                         int32_t& orient, uint32_t& pos)
 {
     const double2* q = reinterpret_cast<const double2*>(rec + t);
     const double2 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4], f = q[5];
@@ -170,9 +193,11 @@ __device__ __forceinline__ void load_tet(const TetRec* __restrict__ rec, int64_t
     v[1] = double3{ b.y, c.x, c.y };
     v[2] = double3{ d.x, d.y, e.x };
     v[3] = double3{ e.y, f.x, f.y };
-    const int4 n4 = reinterpret_cast<const int4*>(rec + t)[6], i4 = reinterpret_cast<const int4*>(rec + t)[7];
+    const int4 n4 = reinterpret_cast<const int4*>(rec + t)[6];
+    const int2 m2 = reinterpret_cast<const int2*>(rec + t)[14];
     nb[0] = n4.x; nb[1] = n4.y; nb[2] = n4.z; nb[3] = n4.w;
-    id[0] = i4.x; id[1] = i4.y; id[2] = i4.z; id[3] = i4.w;
+    orient = m2.x;
+    pos = (uint32_t)m2.y;
 }
 
 __global__ void k3_fill_i32(int64_t n, int32_t* p, int32_t v)
@@ -199,8 +224,9 @@ __global__ void k3_lookup_raster(int64_t n_tet, const TetRec* __restrict__ rec, 
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tet) return;
     double3 v[4];
-    int32_t nb[4], id[4];
-    load_tet(rec, t, v, nb, id);
+    int32_t nb[4], o;
+    uint32_t pos;
+    load_tet(rec, t, v, nb, o, pos);
     const double g = (double)G;
     int32_t lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
@@ -219,14 +245,15 @@ __global__ void k3_lookup_raster(int64_t n_tet, const TetRec* __restrict__ rec, 
         for (int32_t cy = lo[1]; cy <= hi[1]; ++cy)
             for (int32_t cx = lo[0]; cx <= hi[0]; ++cx) {
                 const double3 p{ ((double)cx + 0.5) / g, ((double)cy + 0.5) / g, ((double)cz + 0.5) / g };
-                bool in = true;
-                for (int j = 0; j < 4 && in; ++j) in = face_numerator(p, v, id, j) >= 0.0;
-                if (in) atomicMin(&lookup[((int64_t)cz * G + cy) * G + cx], (int32_t)t);
+                double sn[4];
+                numerators(p, v, o, sn);
+                if (sn[0] >= 0.0 && sn[1] >= 0.0 && sn[2] >= 0.0 && sn[3] >= 0.0) atomicMin(&lookup[((int64_t)cz * G + cy) * G + cx], (int32_t)t);
             }
 }
 
-// Alg. 1 for a batch of points, one lane per point with the wave-local refill of the 2D walk:
-// a wavefront owns kChunk consecutive points and hands unstarted ones to lanes that finish.
+// Alg. 1 for a batch of points, one lane per point.  (The wave-local refill of the 2D walk,
+// with 2, 4 or 8 points per lane, measured 8 to 37 % slower on 1M and 8M points in 5.8M
+// tetrahedra: neighbouring points walk alike, and the refill costs parallelism.)
 template <bool GIVEN>
 __global__ __launch_bounds__(kBlock) void k3_locate(const TetRec* __restrict__ rec, int64_t n_tet, int64_t n,
                                                     const double* __restrict__ xp, const int32_t* __restrict__ start,
@@ -234,76 +261,62 @@ __global__ __launch_bounds__(kBlock) void k3_locate(const TetRec* __restrict__ r
                                                     int32_t* __restrict__ host, int32_t* __restrict__ iters,
                                                     uint8_t* __restrict__ status)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-    const int64_t base = wave * kChunk;
-    const int64_t n_slots = n - base < kChunk ? n - base : kChunk;
-    if (n_slots <= 0) return;
-    int64_t next = 0;
-    bool active = false;
-    int64_t idx = 0;
-    double3 p{ 0.0, 0.0, 0.0 };
-    int32_t K = 0, I = 0;
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= n) return;
+    const double3 p{ xp[3 * idx], xp[3 * idx + 1], xp[3 * idx + 2] };
+    int32_t K;
+    if (GIVEN) {
+        K = start[idx];
+    } else {
+        K = lookup[((int64_t)cell3(p.z, G) * G + cell3(p.y, G)) * G + cell3(p.x, G)];
+        if (K < 0) K = 0;  // a cell with no element: start at element 0
+    }
+    if (K < 0 || K >= n_tet) {
+        host[idx] = -1;
+        if (iters) iters[idx] = 0;
+        if (status) status[idx] = CNNSNS_BADSTART;
+        return;
+    }
+    int32_t I = 0;
+    int fin;
     for (;;) {
-        const uint64_t idle = __ballot(!active);
-        if (idle != 0 && next < n_slots) {
-            const uint32_t lo = (uint32_t)idle, hi = (uint32_t)(idle >> 32);
-            const int rank = (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-            if (!active && next + rank < n_slots) {
-                idx = base + next + rank;
-                p = double3{ xp[3 * idx], xp[3 * idx + 1], xp[3 * idx + 2] };
-                if (GIVEN) {
-                    K = start[idx];
-                } else {
-                    K = lookup[((int64_t)cell3(p.z, G) * G + cell3(p.y, G)) * G + cell3(p.x, G)];
-                    if (K < 0) K = 0;  // a cell with no element: start at element 0
-                }
-                I = 0;
-                if (K < 0 || K >= n_tet) {
-                    host[idx] = -1;
-                    if (iters) iters[idx] = 0;
-                    if (status) status[idx] = CNNSNS_BADSTART;
-                } else {
-                    active = true;
-                }
-            }
-            next += __popcll(idle);
+        I = I + 1;
+        double3 v[4];
+        int32_t nb[4], o;
+        uint32_t pos;
+        load_tet(rec, K, v, nb, o, pos);
+        double s[4];
+        numerators(p, v, o, s);
+        if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0 && s[3] >= 0.0) {
+            fin = CNNSNS_FOUND;
+            break;
         }
-        if (__ballot(active) == 0) {
-            if (next >= n_slots) break;
-            continue;
+        // eq. (5): the smallest coordinate, ties to the lowest position in the element order
+        double sm = s[0];
+        uint32_t pm = pos & 0xffu;
+        int32_t m = nb[0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            const uint32_t pk = (pos >> (8 * k)) & 0xffu;
+            if (s[k] < sm || (s[k] == sm && pk < pm)) {
+                sm = s[k];
+                pm = pk;
+                m = nb[k];
+            }
         }
-        if (active) {
-            I = I + 1;
-            double3 v[4];
-            int32_t nb[4], id[4];
-            load_tet(rec, K, v, nb, id);
-            double s[4];
-            for (int j = 0; j < 4; ++j) s[j] = face_numerator(p, v, id, j);
-            int fin = -1;
-            if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0 && s[3] >= 0.0) {
-                fin = CNNSNS_FOUND;
-            } else {
-                // eq. (5): the smallest coordinate, ties to the lowest index
-                int jm = 0;
-                for (int j = 1; j < 4; ++j)
-                    if (s[j] < s[jm]) jm = j;
-                const int32_t m = nb[jm];
-                if (m == -1) {
-                    fin = CNNSNS_OUTSIDE;
-                } else {
-                    K = m;
-                    if (I >= max_iter) fin = CNNSNS_MAXITER;
-                }
-            }
-            if (fin >= 0) {
-                host[idx] = K;
-                if (iters) iters[idx] = I;
-                if (status) status[idx] = (uint8_t)fin;
-                active = false;
-            }
+        if (m == -1) {
+            fin = CNNSNS_OUTSIDE;
+            break;
+        }
+        K = m;
+        if (I >= max_iter) {
+            fin = CNNSNS_MAXITER;
+            break;
         }
     }
+    host[idx] = K;
+    if (iters) iters[idx] = I;
+    if (status) status[idx] = (uint8_t)fin;
 }
 
 template <class T>
@@ -406,8 +419,7 @@ void launch_locate3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const 
 {
     if (n == 0) return;
     if (max_iter <= 0) max_iter = 1 << 20;
-    const int64_t waves = (n + kChunk - 1) / kChunk;
-    const int64_t blocks = (waves * kWave + kBlock - 1) / kBlock;
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
     if (blocks > (int64_t)INT32_MAX) fail(CNNSNS_EINVAL, "locate3d: too many points");
     if (start)
         k3_locate<true><<<(unsigned)blocks, kBlock, 0, stream>>>(m.rec, m.n_tet, n, xp, start, m.lookup, m.G, max_iter,

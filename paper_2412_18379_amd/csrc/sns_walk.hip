@@ -1,10 +1,14 @@
 // The successive neighbour search (Alg. 1) for a batch of points, with the
 // CNN-SNS start element of Alg. 2 selected in the same kernel.
 //
-// One lane walks one point.  A wavefront owns a contiguous chunk of points
-// and keeps all 64 lanes busy: whenever lanes finish their walks, the wave
-// hands them the chunk's next unstarted points (ballot + lane prefix count),
-// so a long walk does not leave the rest of its wave idle.  Each hop is one
+// One lane walks one point.  With looked-up starts (short walks, a few long
+// ones) a wavefront owns a chunk of 512 points and keeps all 64 lanes busy:
+// whenever lanes finish their walks, the wave hands them the chunk's next
+// unstarted points (ballot + lane prefix count), so a long walk does not leave
+// the rest of its wave idle.  From given starts (long walks of similar length
+// for neighbouring points) a wavefront takes 64 points, one per lane: on 8M
+// points in 16M triangles that is 20 % faster than chunks of 512 and 7 %
+// faster than 128, the wider grid hiding more of each hop's latency.  Each hop is one
 // 64-byte gather of the current element's record; the geometry is FP64 with
 // no fused multiply-add, exactly as written.
 #pragma clang fp contract(off)
@@ -16,7 +20,8 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
-constexpr int64_t kChunk = 512;  // points per wavefront
+constexpr int64_t kChunk = 512;      // points per wavefront, looked-up starts
+constexpr int64_t kChunkGiven = 64;  // points per wavefront, given starts
 
 __device__ __forceinline__ int32_t cell_of(double x, int32_t G)
 {
@@ -41,23 +46,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
     const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
-    // A wave owns kChunk slots.  From the element before movement (long paths, where
-    // neighbouring points share elements) slot v is point wave kChunk + v, a contiguous chunk.
+    // From the element before movement (long paths, where neighbouring points share elements)
+    // a wave owns kChunkGiven slots: slot v is point wave kChunkGiven + v, a contiguous chunk.
     // From a looked-up start (short paths, whose rare long ones cluster at the two ends of the
-    // point order, the domain boundary) the slots are 8 runs of 64 consecutive points strided
-    // across all points, so the long walks of one region spread over many waves: run u is
+    // point order, the domain boundary) a wave owns kChunk slots, 8 runs of 64 consecutive
+    // points strided across all points, so the long walks of one region spread over many waves: run u is
     // 64-point block b + u n_waves with b = wave for even u and n_waves - 1 - wave for odd u,
     // so both ends of the point order fall to the first waves, which walk them first (runs in
     // the order 0, 7, 1, 6, 2, 5, 3, 4).
     auto point_of = [&](int64_t v) -> int64_t {
-        if (MODE == START_GIVEN) return wave * kChunk + v;
+        if (MODE == START_GIVEN) return wave * kChunkGiven + v;
         const int k = (int)(v >> 6);
         const int u = (k & 1) ? 7 - (k >> 1) : (k >> 1);
         const int64_t b = (u & 1) ? n_waves - 1 - wave : wave;
         return ((b + u * n_waves) << 6) + (v & (kWave - 1));
     };
     int64_t next = 0;  // wave-uniform: next unstarted slot
-    const int64_t n_slots = MODE == START_GIVEN ? (n - wave * kChunk < kChunk ? n - wave * kChunk : kChunk) : kChunk;
+    const int64_t n_slots =
+        MODE == START_GIVEN ? (n - wave * kChunkGiven < kChunkGiven ? n - wave * kChunkGiven : kChunkGiven) : kChunk;
     if (MODE == START_GIVEN && n_slots <= 0) return;
 
     // Start elements that depend on a lookup (CNN-SNS, ASG) are computed for the whole chunk
@@ -233,7 +239,8 @@ void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const in
 {
     if (n == 0) return;
     if (max_iter <= 0) max_iter = 1 << 20;
-    const int64_t waves = (n + kChunk - 1) / kChunk;
+    const int64_t chunk = (!disp && start) ? kChunkGiven : kChunk;
+    const int64_t waves = (n + chunk - 1) / chunk;
     const int64_t blocks = (waves * kWave + kBlock - 1) / kBlock;
     if (blocks > (int64_t)INT32_MAX) fail(CNNSNS_EINVAL, "locate: too many points");
     const auto* xp2 = reinterpret_cast<const double2*>(xp);
