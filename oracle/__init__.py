@@ -18,6 +18,18 @@ Parity status of each function (what pins it, see ``tests/test_oracle_*.py``):
                               responses; constructed pass-through weights
   cnnsns_start              - closed-form cells on hand-made cases
   brute_force               - exact-rational containment
+  canonicalise3, neighbours3 - numpy volumes, Kuhn boundary face count,
+                              symmetry, Euler characteristic of a ball
+  sns3                      - numpy barycentric solve (host contains x_p, the
+                              unique strict container); Kuhn closed form; ties
+                              found in exact rational arithmetic
+  lookup3, brute_force3     - their definitions by brute force
+  cnn3_window / cnn3_forward - torch.nn.functional.conv3d in float64; impulse
+                              responses; in-grid tap counts of a constant
+                              input; constructed pass-through weights
+  cnnsns3_start             - zero displacement at cell centres gives the
+                              lookup; clamping; x = 1 maps to cell G-1;
+                              fallback of empty cells
 """
 from __future__ import annotations
 
@@ -75,6 +87,8 @@ def _L():
             "orc3_sns": [i64, vp, vp, vp, i64, vp, vp, i32, vp, vp, vp],
             "orc3_lookup": [i64, vp, vp, i32, vp],
             "orc3_brute_force": [i64, vp, vp, i64, vp, vp],
+            "orc3_cnn_window": [i32, vp, vp, vp, vp, vp, vp, vp],
+            "orc3_cnnsns_start": [i64, vp, i32, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -279,3 +293,44 @@ def brute_force3(xyz, tet_pos, xp):
     _check(_L().orc3_brute_force(tet_pos.shape[0], _p(xyz), _p(tet_pos), xp.shape[0], _p(xp), _p(host)),
            "brute_force3")
     return host
+
+
+def cnn3_window(vel, ws, bs, origin3, size3):
+    """Four-layer 3D CNN output on the window [z0, z0+d) x [y0, y0+h) x [x0, x0+w) of the G^3 grid:
+    FP64 [C_out][d][h][w].  vel FP32 [C_in][G][G][G]; ws[l] FP32 [C_out][C_in][3][3][3]."""
+    vel = np.ascontiguousarray(vel, dtype=np.float32)
+    G = vel.shape[-1]
+    ws = [np.ascontiguousarray(x, dtype=np.float32) for x in ws]
+    bs = [np.ascontiguousarray(x, dtype=np.float32) for x in bs]
+    chan = np.array([ws[0].shape[1]] + [x.shape[0] for x in ws], dtype=np.int32)
+    wp = (ctypes.c_void_p * 4)(*[x.ctypes.data for x in ws])
+    bp = (ctypes.c_void_p * 4)(*[x.ctypes.data for x in bs])
+    o3 = np.ascontiguousarray(origin3, dtype=np.int64)
+    s3 = np.ascontiguousarray(size3, dtype=np.int64)
+    out = np.empty((chan[4], *[int(v) for v in s3]), np.float64)
+    _check(_L().orc3_cnn_window(G, _p(vel), _p(chan), wp, bp, _p(o3), _p(s3), _p(out)), "cnn3_window")
+    return out
+
+
+def cnn3_forward(vel, ws, bs):
+    G = vel.shape[-1]
+    return cnn3_window(vel, ws, bs, (0, 0, 0), (G, G, G))
+
+
+def cnnsns3_start(origin, disp, lookup_grid, fallback=None):
+    """Alg. 2 start element in 3D from the predicted displacement (FP64 [3][G][G][G])."""
+    origin = np.ascontiguousarray(origin, dtype=np.float64)
+    disp = np.ascontiguousarray(disp, dtype=np.float64)
+    lk = np.ascontiguousarray(lookup_grid, dtype=np.int32)
+    fb = None if fallback is None else np.ascontiguousarray(fallback, dtype=np.int32)
+    n = origin.shape[0]
+    out = np.empty(n, np.int32)
+    _check(_L().orc3_cnnsns_start(n, _p(origin), lk.shape[0], _p(disp), _p(lk), _p(fb), _p(out)), "cnnsns3_start")
+    return out
+
+
+def cnnsns3(xyz, tet_pos, nbr, lookup_grid, origin, xp, disp, fallback=None, max_iter: int = 0):
+    """Alg. 2 end to end on tetrahedra from a given displacement grid: (start, host, iters, status)."""
+    st = cnnsns3_start(origin, disp, lookup_grid, fallback)
+    h, it, s = sns3(xyz, tet_pos, nbr, xp, st, max_iter)
+    return st, h, it, s

@@ -700,3 +700,132 @@ int orc3_brute_force(int64_t n_tet, const double* xyz, const int32_t* tet, int64
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* 3D displacement CNN (Sec. 2.3 with 3 x 3 x 3 kernels on a G x G x G grid) */
+
+/*
+ * One layer of 3 x 3 x 3 convolution with zero padding of one cell, on
+ * windows of the G^3 grid (axes z, y, x, x fastest):
+ *   y[o][z][y][x] = b[o] + sum_i sum_{dz,dy,dx in -1..1}
+ *                   W[o][i][dz+1][dy+1][dx+1] * x[i][z+dz][y+dy][x+dx],
+ * with x zero outside [0, G)^3.  The input window starts at iw0 = (z, y, x)
+ * with sizes in_ = (d, h, w); the output window at ow0 with sizes on_, and
+ * every in-grid tap of an output cell falls inside the input window.
+ */
+static void conv3x3x3(int32_t G, const double* x, int32_t cin, const int64_t iw0[3], const int64_t in_[3],
+                      double* y, int32_t cout, const int64_t ow0[3], const int64_t on_[3], const double* W,
+                      const double* b, int relu)
+{
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t zz = 0; zz < on_[0]; ++zz) {
+        for (int64_t yy = 0; yy < on_[1]; ++yy) {
+            for (int32_t o = 0; o < cout; ++o) {
+                for (int64_t xx = 0; xx < on_[2]; ++xx) {
+                    const int64_t z = ow0[0] + zz, yv = ow0[1] + yy, xv = ow0[2] + xx;
+                    double acc = b[o];
+                    for (int32_t i = 0; i < cin; ++i)
+                        for (int dz = -1; dz <= 1; ++dz)
+                            for (int dy = -1; dy <= 1; ++dy)
+                                for (int dx = -1; dx <= 1; ++dx) {
+                                    const int64_t Z = z + dz, Y = yv + dy, X = xv + dx;
+                                    if (Z < 0 || Z >= G || Y < 0 || Y >= G || X < 0 || X >= G) continue;
+                                    const double v =
+                                        x[(((int64_t)i * in_[0] + (Z - iw0[0])) * in_[1] + (Y - iw0[1])) * in_[2] +
+                                          (X - iw0[2])];
+                                    acc += W[((((int64_t)o * cin + i) * 3 + (dz + 1)) * 3 + (dy + 1)) * 3 + (dx + 1)] * v;
+                                }
+                    if (relu && acc < 0.0) acc = 0.0;
+                    y[(((int64_t)o * on_[0] + zz) * on_[1] + yy) * on_[2] + xx] = acc;
+                }
+            }
+        }
+    }
+}
+
+/*
+ * Four-layer 3D displacement CNN, channels chan[0] -> ... -> chan[4]
+ * (3 -> 32 -> 32 -> 32 -> 3 for velocity to displacement), ReLU after layers
+ * 1-3.  Output on the window starting at (z0, y0, x0) of sizes (d, h, w) of
+ * the G^3 grid; each inner layer is evaluated on the window grown by one cell
+ * per remaining layer (clipped to the grid), so the result equals the
+ * full-grid pass restricted to the window.
+ *   vel: FP32 [chan0][G][G][G]; w[l]: FP32 [chan(l+1)][chan(l)][3][3][3];
+ *   b[l]: FP32 [chan(l+1)]; out: FP64 [chan4][d][h][w].
+ */
+int orc3_cnn_window(int32_t G, const float* vel, const int32_t* chan, const float* const* w, const float* const* b,
+                    const int64_t* origin3, const int64_t* size3, double* out)
+{
+    if (G <= 0) return ORC_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (size3[a] <= 0 || origin3[a] < 0 || origin3[a] + size3[a] > G) return ORC_EINVAL;
+    int64_t w0[5][3], wn[5][3];
+    for (int l = 0; l <= 4; ++l)
+        for (int a = 0; a < 3; ++a) {
+            const int64_t grow = 4 - l;
+            int64_t lo = origin3[a] - grow, hi = origin3[a] + size3[a] + grow;
+            if (lo < 0) lo = 0;
+            if (hi > G) hi = G;
+            w0[l][a] = lo;
+            wn[l][a] = hi - lo;
+        }
+    double* act[5] = { 0 };
+    double* Wd[4] = { 0 };
+    double* bd[4] = { 0 };
+    int rc = ORC_OK;
+    for (int l = 0; l <= 4; ++l) {
+        act[l] = (double*)malloc(sizeof(double) * (size_t)(chan[l] * wn[l][0] * wn[l][1] * wn[l][2]));
+        if (!act[l]) rc = ORC_ENOMEM;
+    }
+    for (int l = 0; l < 4; ++l) {
+        Wd[l] = (double*)malloc(sizeof(double) * (size_t)(chan[l + 1] * chan[l] * 27));
+        bd[l] = (double*)malloc(sizeof(double) * (size_t)chan[l + 1]);
+        if (!Wd[l] || !bd[l]) rc = ORC_ENOMEM;
+    }
+    if (rc == ORC_OK) {
+        for (int l = 0; l < 4; ++l) {
+            for (int64_t k = 0; k < (int64_t)chan[l + 1] * chan[l] * 27; ++k) Wd[l][k] = (double)w[l][k];
+            for (int32_t k = 0; k < chan[l + 1]; ++k) bd[l][k] = (double)b[l][k];
+        }
+        for (int32_t i = 0; i < chan[0]; ++i)
+            for (int64_t z = 0; z < wn[0][0]; ++z)
+                for (int64_t y = 0; y < wn[0][1]; ++y)
+                    for (int64_t x = 0; x < wn[0][2]; ++x)
+                        act[0][(((int64_t)i * wn[0][0] + z) * wn[0][1] + y) * wn[0][2] + x] =
+                            (double)vel[(((int64_t)i * G + (w0[0][0] + z)) * G + (w0[0][1] + y)) * G + (w0[0][2] + x)];
+        for (int l = 0; l < 4; ++l)
+            conv3x3x3(G, act[l], chan[l], w0[l], wn[l], act[l + 1], chan[l + 1], w0[l + 1], wn[l + 1], Wd[l], bd[l],
+                      l < 3);
+        memcpy(out, act[4], sizeof(double) * (size_t)(chan[4] * size3[0] * size3[1] * size3[2]));
+    }
+    for (int l = 0; l <= 4; ++l) free(act[l]);
+    for (int l = 0; l < 4; ++l) { free(Wd[l]); free(bd[l]); }
+    return rc;
+}
+
+/*
+ * CNN-SNS start element in 3D (Alg. 2): x_hat = clamp(x_i + D, 0, 1) per axis,
+ * D the predicted displacement of the overlay cell holding x_i, and K_p the
+ * 3D overlay lookup of the cell holding x_hat (fallback[i], else element 0,
+ * where that cell has no element).
+ *   origin: [n][3]; disp: [3][G][G][G] (x, y, z components); lookup: [G][G][G].
+ */
+int orc3_cnnsns_start(int64_t n, const double* origin, int32_t G, const double* disp, const int32_t* lookup,
+                      const int32_t* fallback, int32_t* start_out)
+{
+    if (n < 0 || G <= 0) return ORC_EINVAL;
+    const int64_t nc = (int64_t)G * G * G;
+    for (int64_t i = 0; i < n; ++i) {
+        const double* o = origin + 3 * i;
+        const int64_t c = (cell_of(o[2], G) * G + cell_of(o[1], G)) * G + cell_of(o[0], G);
+        double h[3];
+        for (int a = 0; a < 3; ++a) {
+            h[a] = o[a] + disp[a * nc + c];
+            h[a] = h[a] < 0.0 ? 0.0 : (h[a] > 1.0 ? 1.0 : h[a]);
+        }
+        int32_t k = lookup[(cell_of(h[2], G) * G + cell_of(h[1], G)) * G + cell_of(h[0], G)];
+        if (k < 0) k = fallback ? fallback[i] : 0;
+        start_out[i] = k;
+    }
+    return ORC_OK;
+}

@@ -417,6 +417,15 @@ class ABCFlow:
         return u, v, w
 
 
+def overlay_velocity_3d(flow, G: int) -> np.ndarray:
+    """A 3D flow sampled at the centres ((c + 1/2) / G per axis) of a G^3 overlay: FP32 [3][G][G][G]
+    (component, z, y, x)."""
+    c = (np.arange(G) + 0.5) / G
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    u, v, w = flow(X, Y, Z)
+    return np.ascontiguousarray(np.stack([u, v, w]).astype(np.float32))
+
+
 def tet_longest_edges(xyz: np.ndarray, tet: np.ndarray) -> np.ndarray:
     best = np.zeros(tet.shape[0])
     for a in range(4):

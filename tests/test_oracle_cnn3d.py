@@ -1,0 +1,186 @@
+"""Pins of the oracle's 3D displacement CNN (Sec. 2.3 with 3 x 3 x 3 kernels) and of
+its CNN-SNS start element in 3D (Alg. 2).
+
+The network's definition (cross-correlation with OIDHW weights, zero padding of
+one cell, bias, ReLU after layers 1-3) is checked against torch's float64
+conv3d, against impulse responses that read the weights back (which catches a
+flipped kernel or swapped axes), against the count of in-grid taps of a
+constant input (8 at corners, 12 on edges, 18 on faces, 27 inside), against
+zero weights (biases only) and against a constructed pass-through net whose
+output is -dt u exactly.  Windows equal the full pass restricted.  The start
+element is pinned by closed-form cells.
+"""
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+CH = (3, 32, 32, 32, 3)
+
+
+def _rand_net(rng, ch=CH, scale=1.0):
+    ws = [(rng.standard_normal((ch[l + 1], ch[l], 3, 3, 3)) * scale * np.sqrt(2.0 / (27 * ch[l]))).astype(np.float32)
+          for l in range(4)]
+    bs = [(0.1 * rng.standard_normal(ch[l + 1])).astype(np.float32) for l in range(4)]
+    return ws, bs
+
+
+def _torch_forward(vel, ws, bs):
+    x = torch.from_numpy(vel.astype(np.float64))[None]
+    for l in range(4):
+        x = F.conv3d(x, torch.from_numpy(ws[l].astype(np.float64)), torch.from_numpy(bs[l].astype(np.float64)),
+                     padding=1)
+        if l < 3:
+            x = torch.relu(x)
+    return x[0].numpy()
+
+
+@pytest.mark.parametrize("G", [1, 2, 5, 9])
+def test_against_torch_conv3d(oracle_mod, G):
+    rng = np.random.default_rng(G)
+    vel = rng.standard_normal((3, G, G, G)).astype(np.float32)
+    ws, bs = _rand_net(rng)
+    got = oracle_mod.cnn3_forward(vel, ws, bs)
+    want = _torch_forward(vel, ws, bs)
+    assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
+def _identity(c):
+    w = np.zeros((c, c, 3, 3, 3), np.float32)
+    for k in range(c):
+        w[k, k, 1, 1, 1] = 1.0
+    return w
+
+
+def test_impulse_reads_back_the_first_layer(oracle_mod):
+    """A unit impulse in channel i at cell p: layer 1's output at p - d is W[o][i][d + 1] (cross-
+    correlation), passed unchanged through identity layers (weights non-negative so ReLU keeps them)."""
+    G, c = 7, 4
+    rng = np.random.default_rng(3)
+    w1 = rng.uniform(0.1, 1.0, size=(c, 3, 3, 3, 3)).astype(np.float32)
+    ws = [w1, _identity(c), _identity(c), _identity(c)]
+    bs = [np.zeros(c, np.float32) for _ in range(4)]
+    for i in range(3):
+        vel = np.zeros((3, G, G, G), np.float32)
+        p = (3, 2, 4)
+        vel[i][p] = 1.0
+        out = oracle_mod.cnn3_forward(vel, ws, bs)
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    got = out[:, p[0] - dz, p[1] - dy, p[2] - dx]
+                    assert np.array_equal(got, w1[:, i, dz + 1, dy + 1, dx + 1].astype(np.float64))
+        assert np.count_nonzero(out) == c * 27
+
+
+def test_constant_input_counts_in_grid_taps(oracle_mod):
+    G = 5
+    ones = np.ones((1, 1, 3, 3, 3), np.float32)
+    ws = [ones, _identity(1), _identity(1), _identity(1)]
+    bs = [np.zeros(1, np.float32) for _ in range(4)]
+    out = oracle_mod.cnn3_forward(np.ones((1, G, G, G), np.float32), ws, bs)[0]
+    n = np.array([2, 3, 3, 3, 2])  # taps inside the grid along one axis
+    want = n[:, None, None] * n[None, :, None] * n[None, None, :]
+    assert np.array_equal(out, want.astype(np.float64))
+    assert out[0, 0, 0] == 8 and out[0, 0, 2] == 12 and out[0, 2, 2] == 18 and out[2, 2, 2] == 27
+
+
+def test_zero_weights_give_the_bias_chain(oracle_mod):
+    G = 4
+    rng = np.random.default_rng(5)
+    ws = [np.zeros((CH[l + 1], CH[l], 3, 3, 3), np.float32) for l in range(4)]
+    bs = [rng.standard_normal(CH[l + 1]).astype(np.float32) for l in range(4)]
+    out = oracle_mod.cnn3_forward(rng.standard_normal((3, G, G, G)).astype(np.float32), ws, bs)
+    assert np.array_equal(out, np.broadcast_to(bs[3].astype(np.float64)[:, None, None, None], out.shape))
+
+
+def constructed_net(dt):
+    """3 -> 32 -> 32 -> 32 -> 3 weights whose output is -dt u exactly: layer 1 puts relu(u_a) and
+    relu(-u_a) in channels 2a and 2a+1, layers 2-3 pass them on, layer 4 forms -dt (u+ - u-)."""
+    w1 = np.zeros((32, 3, 3, 3, 3), np.float32)
+    for a in range(3):
+        w1[2 * a, a, 1, 1, 1] = 1.0
+        w1[2 * a + 1, a, 1, 1, 1] = -1.0
+    w4 = np.zeros((3, 32, 3, 3, 3), np.float32)
+    for a in range(3):
+        w4[a, 2 * a, 1, 1, 1] = -dt
+        w4[a, 2 * a + 1, 1, 1, 1] = dt
+    ws = [w1, _identity(32), _identity(32), w4]
+    bs = [np.zeros(c, np.float32) for c in (32, 32, 32, 3)]
+    return ws, bs
+
+
+def test_constructed_weights_give_minus_dt_u(oracle_mod):
+    G = 6
+    rng = np.random.default_rng(6)
+    vel = rng.standard_normal((3, G, G, G)).astype(np.float32)
+    dt = 0.0123
+    ws, bs = constructed_net(dt)
+    out = oracle_mod.cnn3_forward(vel, ws, bs)
+    assert np.array_equal(out, np.float64(np.float32(-dt)) * vel.astype(np.float64))
+
+
+def test_windows_equal_the_full_pass(oracle_mod):
+    G = 9
+    rng = np.random.default_rng(7)
+    vel = rng.standard_normal((3, G, G, G)).astype(np.float32)
+    ws, bs = _rand_net(rng)
+    full = oracle_mod.cnn3_forward(vel, ws, bs)
+    for o, s in [((0, 0, 0), (1, 1, 1)), ((3, 4, 2), (2, 3, 4)), ((8, 0, 5), (1, 9, 4)), ((4, 4, 4), (1, 1, 1))]:
+        win = oracle_mod.cnn3_window(vel, ws, bs, o, s)
+        assert np.array_equal(win, full[:, o[0]:o[0] + s[0], o[1]:o[1] + s[1], o[2]:o[2] + s[2]])
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.cnn3_window(vel, ws, bs, (8, 0, 0), (2, 1, 1))
+
+
+def test_cnnsns3_start_closed_form_cells(oracle_mod):
+    G = 4
+    lk = np.arange(G ** 3, dtype=np.int32).reshape(G, G, G)  # cell (z, y, x) -> its own index
+    c = (np.arange(G) + 0.5) / G
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    origin = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    zero = np.zeros((3, G, G, G))
+    assert np.array_equal(oracle_mod.cnnsns3_start(origin, zero, lk), lk.ravel())  # D = 0: the own cell
+    # a displacement of one cell in +x (and the last column clamped to the face x = 1 -> cell G - 1)
+    d = np.zeros((3, G, G, G))
+    d[0] = 1.0 / G
+    got = oracle_mod.cnnsns3_start(origin, d, lk)
+    iz, iy, ix = (np.floor(a.ravel() * G).astype(int) for a in (Z, Y, X))
+    want = lk[iz, iy, np.minimum(ix + 1, G - 1)]
+    assert np.array_equal(got, want)
+    # far displacements clamp to the corner cells; x = 1.0 itself lies in cell G - 1
+    big = np.full((3, G, G, G), 5.0)
+    assert np.all(oracle_mod.cnnsns3_start(origin, big, lk) == G ** 3 - 1)
+    assert np.all(oracle_mod.cnnsns3_start(origin, -big, lk) == 0)
+    assert oracle_mod.cnnsns3_start(np.array([[1.0, 1.0, 1.0]]), zero, lk)[0] == G ** 3 - 1
+    # an origin's displacement is read from the cell of the origin, component a from channel a
+    d = np.zeros((3, G, G, G))
+    d[2, 0, 0, 0] = 2.0 / G  # +2 cells in z for the origin cell (0, 0, 0) only
+    got = oracle_mod.cnnsns3_start(origin, d, lk)
+    assert got[0] == lk[2, 0, 0] and np.array_equal(got[1:], lk.ravel()[1:])
+    # cells without an element fall back to the given start, else element 0
+    lk2 = lk.copy()
+    lk2[0, 0, 0] = -1
+    assert oracle_mod.cnnsns3_start(origin[:1], zero, lk2)[0] == 0
+    assert oracle_mod.cnnsns3_start(origin[:1], zero, lk2, fallback=np.array([17], np.int32))[0] == 17
+
+
+def test_cnnsns3_end_to_end_hosts_equal_plain(oracle_mod, wl):
+    """Whatever the start, the walk ends in an element holding x_p: with the constructed net's
+    displacement the hosts equal the plain walk's except for points on a face shared by both
+    elements (here the points clamped onto the cube's boundary), and paths are shorter."""
+    w = wl.build_3d("t1")
+    tp, nbr = oracle_mod.prepare_mesh3(w.xyz, w.tet)
+    lk = oracle_mod.lookup3(w.xyz, tp, w.G)
+    vel = wl.overlay_velocity_3d(w.flow, w.G)
+    ws, bs = constructed_net(w.dt)
+    disp = oracle_mod.cnn3_forward(vel, ws, bs)
+    st, h, it, s = oracle_mod.cnnsns3(w.xyz, tp, nbr, lk, w.xyz, w.xp, disp, fallback=w.start)
+    hp, itp, sp = oracle_mod.sns3(w.xyz, tp, nbr, w.xp, w.start)
+    assert np.all(s == 0) and np.all(sp == 0)
+    diff = np.nonzero(h != hp)[0]
+    for hh in (h, hp):
+        again, _, st2 = oracle_mod.sns3(w.xyz, tp, nbr, w.xp[diff], hh[diff], max_iter=1)
+        assert np.array_equal(again, hh[diff]) and np.all(st2 == 0)  # both hold x_p
+    assert np.all(np.any((w.xp[diff] == 0.0) | (w.xp[diff] == 1.0), axis=1))
+    assert it.mean() < 0.25 * itp.mean()
