@@ -40,6 +40,7 @@ REC_BYTES = 60  # algorithmic bytes of one element record: 6 FP64 coordinates + 
 # one tetrahedron record: 12 FP64 coordinates, 4 int32 neighbours and the 4 int32 node ids that put
 # each face's nodes in a fixed order
 TET_REC_BYTES = 128
+CNN3_MACS_PER_CELL = 3 * 32 * 27 + 2 * 32 * 32 * 27 + 32 * 3 * 27  # 60,480
 
 
 def log(msg):
@@ -152,6 +153,32 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
 
     plain_ms, it_p, st_p, host_p = timed(start=start)
     asg_ms, it_a, st_a, host_a = timed()
+    # CNN-SNS in 3D: the 3D CNN on the G^3 overlay, then the walk from its start (Alg. 2).  The
+    # weights are the constructed pass-through net (displacement -dt u of the origin's cell), a
+    # stand-in for a trained net.
+    ws, bs = W.passthrough_weights_3d(w.dt)
+    wts = C.Weights3D(ws, bs, device=dev)
+    vel = torch.from_numpy(W.overlay_velocity_3d(w.flow, w.G)).to(dev)
+    origin = torch.from_numpy(w.xyz).to(dev)
+    disp = torch.empty((3, w.G, w.G, w.G), dtype=torch.float32, device=dev)
+    for _ in range(warmup):
+        C.predict3d(mesh, vel, wts, disp=disp)
+        C.locate3d(mesh, xp, start=start, origin=origin, disp=disp, host=host, iters=iters, status=status)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    for k in range(K):
+        ev[k][0].record(stream)
+        C.predict3d(mesh, vel, wts, disp=disp)
+        ev[k][1].record(stream)
+        C.locate3d(mesh, xp, start=start, origin=origin, disp=disp, host=host, iters=iters, status=status)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    p3_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
+    l3_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
+    it_c, st_c, host_c = iters.cpu().numpy(), status.cpu().numpy(), host.cpu().numpy()
+    log(f"3D CNN-SNS: predict {p3_ms.mean():.3f} ms, locate {l3_ms.mean():.3f} ms, mean I_t {it_c.mean():.2f}")
+    cnn3_flops = 2.0 * CNN3_MACS_PER_CELL * w.G ** 3
+    cnn3_tf = cnn3_flops / (p3_ms.mean() / 1e3) / 1e12
     log(f"3D plain SNS: {plain_ms.mean():.3f} ms, mean I_t {it_p.mean():.2f}; "
         f"3D lookup start: {asg_ms.mean():.3f} ms, mean I_t {it_a.mean():.2f}")
     # one 128-byte element record per iteration; per point x_p 24 B, the start (or lookup entry)
@@ -173,6 +200,21 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
                          "path_length_p50_p99_max": [pct(it_a, 50), pct(it_a, 99), int(it_a.max())],
                          "found_frac": float(np.mean(st_a == C.FOUND)),
                          "host_agreement_with_plain": float(np.mean(host_a == host_p))},
+        "cnn_sns": {"weights": "constructed pass-through (-dt u of the origin's cell), not trained",
+                    "predict_ms": round(float(p3_ms.mean()), 4), "locate_ms": round(float(l3_ms.mean()), 4),
+                    "step_ms": round(float((p3_ms + l3_ms).mean()), 4),
+                    "points_per_s": round(n / ((p3_ms + l3_ms).mean() / 1e3), 1),
+                    "speedup_vs_plain_sns": round(float(plain_ms.mean() / (p3_ms + l3_ms).mean()), 4),
+                    "mean_path_length": round(float(it_c.mean()), 3),
+                    "path_length_p50_p99_max": [pct(it_c, 50), pct(it_c, 99), int(it_c.max())],
+                    "found_frac": float(np.mean(st_c == C.FOUND)),
+                    "host_agreement_with_plain": float(np.mean(host_c == host_p)),
+                    "cnn_roofline": {"kernel": "3D cnn forward (k3c_conv1 + 2 x k3c_conv32 + k3c_conv4)",
+                                     "bound": "mfma", "achieved": round(cnn3_tf, 3), "peak": PEAK["f32_TFLOPs"],
+                                     "unit": "TFLOP/s", "frac": round(cnn3_tf / PEAK["f32_TFLOPs"], 4),
+                                     "traffic": traffic_for("cnn3_forward_f32", name),
+                                     "algorithmic_per_launch": f"{cnn3_flops:.4e} FLOP (2 x 60480 MAC x G^3, "
+                                                               f"G={w.G})"}},
         "roofline": {"kernel": "k3_locate (plain SNS leg)", "bound": "hbm", "achieved": round(g_plain, 1),
                      "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": round(g_plain / PEAK["hbm_GBps"], 4),
                      "frac_of_measured_copy": round(g_plain / copy_gbps, 4),

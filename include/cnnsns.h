@@ -220,23 +220,47 @@ int cnnsns_mesh3d_info(cnnsns_mesh3 m, int64_t* n_tet, int32_t* overlay_side, in
 int cnnsns_destroy_mesh3d(cnnsns_mesh3 m);
 
 /*
+ * The 3D displacement CNN (Sec. 2.3 with 3 x 3 x 3 kernels) on the mesh's
+ * G x G x G overlay: 3 -> 32 -> 32 -> 32 -> 3 channels, zero padding of one
+ * cell, bias, ReLU after layers 1-3, cross-correlation.  DEVICE arrays:
+ *   vel   FP32 [3][G][G][G] (component, z, y, x) velocity at the cell centres.
+ *   w     weights as in cnnsns_predict, with 3 x 3 x 3 kernels: w[0] FP32
+ *         [32][3][3][3][3], w[1], w[2] [32][32][3][3][3], w[3] [3][32][3][3][3]
+ *         (OIDHW); b[0..2] [32], b[3] [3]; fp8_scale unused.
+ *   precision  CNNSNS_F32 (the only one implemented in 3D).
+ *   disp  FP32 [3][G][G][G] out: the predicted displacement per cell.
+ * Uses a workspace of the mesh (2 G^3 x 32 FP32 activations plus 216 KiB),
+ * allocated on the first call; calls on one mesh must not overlap.
+ * Asynchronous on `stream`.  Errors: EINVAL (null argument, precision not
+ * CNNSNS_F32), ENOMEM (workspace), EHIP.
+ */
+int cnnsns_predict3d(cnnsns_mesh3 m, const float* vel, const cnnsns_cnn* w, int32_t precision, float* disp,
+                     void* stream);
+
+/*
  * Locate n points in a tetrahedral mesh (Alg. 1 with four barycentric
  * coordinates).  The numerator of coordinate j is the volume determinant of
  * the tetrahedron with node j replaced by x_p, det[F - p] over the other three
  * nodes F taken in node-id order with the sign of that permutation applied,
  * so both tetrahedra of a face compute it identically; containment is closed
- * (all >= 0), the smallest coordinate picks the face (ties to the lowest j)
- * and the walk steps across it.  DEVICE arrays:
+ * (all >= 0), the smallest coordinate picks the face (ties to the lowest j of
+ * the positively oriented node order) and the walk steps across it.  DEVICE
+ * arrays:
  *   xp      FP64 [n][3] query points.
- *   start   int32 [n] start elements, or NULL for the overlay lookup of the cell
- *           holding x_p (cell of a coordinate: min(G-1, max(0, floor(x G)));
- *           element 0 where the cell has no element).
+ *   start   int32 [n] start elements (plain SNS), or NULL.
+ *   origin  FP64 [n][3] positions before movement x_i, with disp, or NULL.
+ *   disp    FP32 [3][G][G][G] from cnnsns_predict3d, or NULL.  With disp the
+ *           start is CNN-SNS (Alg. 2): the overlay lookup of the cell holding
+ *           clamp(x_i + D[cell(x_i)], 0, 1), or start[i] (else element 0)
+ *           where that cell has no element.  Without disp and start: the
+ *           overlay lookup of the cell holding x_p (element 0 for an empty
+ *           cell).  Cell of a coordinate: min(G-1, max(0, floor(x G))).
  *   max_iter, host, iters, status as in cnnsns_locate.
  * Asynchronous on `stream`.  n == 0 is a no-op.  Errors: EINVAL (null mesh,
- * xp or host, n < 0), EHIP.
+ * xp or host, n < 0, disp without origin), EHIP.
  */
-int cnnsns_locate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int32_t* start, int32_t max_iter, int32_t* host,
-                    int32_t* iters, uint8_t* status, void* stream);
+int cnnsns_locate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int32_t* start, const double* origin,
+                    const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status, void* stream);
 
 /*
  * Serving loop: a host scheduler that takes CNN-SNS tracking jobs on

@@ -23,7 +23,8 @@ PRECISIONS = {"f32": F32, "bf16": BF16, "fp8": FP8E4M3}
 
 EXPORTS = (
     "cnnsns_build_mesh", "cnnsns_mesh_info", "cnnsns_destroy_mesh", "cnnsns_predict", "cnnsns_locate",
-    "cnnsns_interpolate", "cnnsns_build_mesh3d", "cnnsns_mesh3d_info", "cnnsns_destroy_mesh3d", "cnnsns_locate3d",
+    "cnnsns_interpolate", "cnnsns_build_mesh3d", "cnnsns_mesh3d_info", "cnnsns_destroy_mesh3d", "cnnsns_predict3d",
+    "cnnsns_locate3d",
     "cnnsns_server_create", "cnnsns_submit", "cnnsns_poll", "cnnsns_wait", "cnnsns_server_destroy",
     "cnnsns_last_error",
 )
@@ -60,7 +61,8 @@ def lib():
             "cnnsns_build_mesh3d": [vp, i64, vp, i64, i32, vp, ctypes.POINTER(vp)],
             "cnnsns_mesh3d_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64)],
             "cnnsns_destroy_mesh3d": [vp],
-            "cnnsns_locate3d": [vp, i64, vp, vp, i32, vp, vp, vp, vp],
+            "cnnsns_predict3d": [vp, vp, ctypes.POINTER(_Cnn), i32, vp, vp],
+            "cnnsns_locate3d": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp],
             "cnnsns_server_create": [i64, i32, i32, i32, ctypes.POINTER(_Cnn), ctypes.POINTER(vp)],
             "cnnsns_submit": [vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)],
             "cnnsns_poll": [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
@@ -220,12 +222,48 @@ class Mesh3D:
             pass
 
 
-def locate3d(mesh: Mesh3D, xp: torch.Tensor, start: torch.Tensor = None, max_iter: int = 0,
-             host: torch.Tensor = None, iters: torch.Tensor = None, status: torch.Tensor = None, stream=None):
-    """Alg. 1 on a tetrahedral mesh (cnnsns_locate3d): (host, iters, status)."""
+class Weights3D:
+    """3D CNN weights as device tensors (FP32 OIDHW + bias, 3-32-32-32-3 with 3x3x3 kernels)."""
+
+    def __init__(self, ws: Sequence, bs: Sequence, device="cuda"):
+        self.w = [torch.as_tensor(w, dtype=torch.float32).to(device).contiguous() for w in ws]
+        self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in bs]
+        if len(self.w) != 4 or len(self.b) != 4:
+            raise ValueError("four layers expected")
+        chans = [self.w[0].shape[1]] + [w.shape[0] for w in self.w]
+        if chans != [3, 32, 32, 32, 3] or any(tuple(w.shape[2:]) != (3, 3, 3) for w in self.w):
+            raise ValueError(f"expected a 3-32-32-32-3 3x3x3 net, got {chans}")
+        if [b.shape[0] for b in self.b] != chans[1:]:
+            raise ValueError("bias sizes must match the output channels")
+        self.struct = _Cnn()
+        for l in range(4):
+            self.struct.w[l] = self.w[l].data_ptr()
+            self.struct.b[l] = self.b[l].data_ptr()
+
+
+def predict3d(mesh: Mesh3D, vel: torch.Tensor, weights: Weights3D, disp: torch.Tensor = None,
+              stream=None) -> torch.Tensor:
+    """The 3D displacement CNN on the mesh's G^3 overlay (cnnsns_predict3d, FP32)."""
+    G = mesh.G
+    _need(vel, torch.float32, (3, G, G, G), "vel")
+    if disp is None:
+        disp = torch.empty((3, G, G, G), dtype=torch.float32, device=vel.device)
+    _need(disp, torch.float32, (3, G, G, G), "disp")
+    _check(lib().cnnsns_predict3d(mesh.handle, _ptr(vel), ctypes.byref(weights.struct), PRECISIONS["f32"],
+                                  _ptr(disp), _stream(stream)))
+    return disp
+
+
+def locate3d(mesh: Mesh3D, xp: torch.Tensor, start: torch.Tensor = None, origin: torch.Tensor = None,
+             disp: torch.Tensor = None, max_iter: int = 0, host: torch.Tensor = None, iters: torch.Tensor = None,
+             status: torch.Tensor = None, stream=None):
+    """Alg. 1 on a tetrahedral mesh (cnnsns_locate3d): (host, iters, status).  Starts: `start`, or
+    CNN-SNS from `origin` and `disp` (Alg. 2), or the overlay lookup of x_p."""
     n = xp.shape[0]
     _need(xp, torch.float64, (n, 3), "xp")
     _need(start, torch.int32, (n,), "start")
+    _need(origin, torch.float64, (n, 3), "origin")
+    _need(disp, torch.float32, (3, mesh.G, mesh.G, mesh.G), "disp")
     dev = xp.device
     host = torch.empty(n, dtype=torch.int32, device=dev) if host is None else host
     iters = torch.empty(n, dtype=torch.int32, device=dev) if iters is None else iters
@@ -233,8 +271,8 @@ def locate3d(mesh: Mesh3D, xp: torch.Tensor, start: torch.Tensor = None, max_ite
     _need(host, torch.int32, (n,), "host")
     _need(iters, torch.int32, (n,), "iters")
     _need(status, torch.uint8, (n,), "status")
-    _check(lib().cnnsns_locate3d(mesh.handle, n, _ptr(xp), _ptr(start), int(max_iter), _ptr(host), _ptr(iters),
-                                 _ptr(status), _stream(stream)))
+    _check(lib().cnnsns_locate3d(mesh.handle, n, _ptr(xp), _ptr(start), _ptr(origin), _ptr(disp), int(max_iter),
+                                 _ptr(host), _ptr(iters), _ptr(status), _stream(stream)))
     return host, iters, status
 
 

@@ -154,16 +154,31 @@ int cnnsns_destroy_mesh3d(cnnsns_mesh3 m)
     return guarded([&] { destroy_mesh3(m); });
 }
 
-int cnnsns_locate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int32_t* start, int32_t max_iter, int32_t* host,
-                    int32_t* iters, uint8_t* status, void* stream)
+int cnnsns_predict3d(cnnsns_mesh3 m, const float* vel, const cnnsns_cnn* w, int32_t precision, float* disp,
+                     void* stream)
+{
+    return guarded([&] {
+        if (!m || !vel || !w || !disp) fail(CNNSNS_EINVAL, "predict3d: NULL argument");
+        for (int l = 0; l < 4; ++l)
+            if (!w->w[l] || !w->b[l]) fail(CNNSNS_EINVAL, "predict3d: NULL weight or bias pointer");
+        if (precision != CNNSNS_F32) fail(CNNSNS_EINVAL, "predict3d: only CNNSNS_F32 is implemented in 3D");
+        DeviceScope ds(m->device);
+        run_predict3(*m, vel, *w, disp, static_cast<hipStream_t>(stream));
+    });
+}
+
+int cnnsns_locate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int32_t* start, const double* origin,
+                    const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status, void* stream)
 {
     return guarded([&] {
         if (!m) fail(CNNSNS_EINVAL, "locate3d: NULL mesh");
         if (n < 0) fail(CNNSNS_EINVAL, "locate3d: n must be >= 0");
         if (n == 0) return;
         if (!xp || !host) fail(CNNSNS_EINVAL, "locate3d: xp and host must not be NULL");
+        if (disp && !origin) fail(CNNSNS_EINVAL, "locate3d: disp given without origin");
         DeviceScope ds(m->device);
-        launch_locate3(*m, n, xp, start, max_iter, host, iters, status, static_cast<hipStream_t>(stream));
+        launch_locate3(*m, n, xp, start, origin, disp, max_iter, host, iters, status,
+                       static_cast<hipStream_t>(stream));
     });
 }
 

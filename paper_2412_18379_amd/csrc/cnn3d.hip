@@ -1,0 +1,260 @@
+// The displacement CNN in 3D (Sec. 2.3 with 3 x 3 x 3 kernels on a G x G x G
+// overlay): 3 -> 32 -> 32 -> 32 -> 3 channels, zero padding of one cell, bias,
+// ReLU after layers 1-3, FP32.
+//
+// Layers 2 and 3 (32 -> 32, 94 % of the work) are dense contractions over
+// 27 taps x 32 input channels per output cell and run on the matrix cores
+// (v_mfma_f32_16x16x4f32, D = A B): A holds the weights (row = output
+// channel, k = input channel), B the input activations (column = one of 16
+// consecutive cells along x, k = input channel).  Lane l supplies output
+// channel 16 nb + l%16 (A) and cell l%16 (B), both for input channel
+// 8 (l/16) + 4h + j in k-step j of channel half h, and receives output
+// channels 16 nb + 4 (l/16) + r (r = 0..3) of cell l%16: four consecutive
+// channels, stored as one 16-byte write.  A wavefront computes 64 cells of one
+// x row (four 16-cell blocks) for all 32 output channels; the 27 taps' weights
+// sit in LDS in operand order (108 KiB, loaded once per block), the
+// activations come through the caches (a cell's 32 channels are one 128-byte
+// line).  Layers 1 and 4 (3 -> 32, 32 -> 3) are 9 % of the work and run on the
+// vector ALUs, one cell per lane.
+//
+// Activations between layers: FP32 [G^3][32], cell-major (z, y, x; x fastest),
+// 32 channels per cell.  Input velocity and output displacement: FP32
+// [3][G][G][G] (component, z, y, x).
+#include <mutex>
+
+#include "common.h"
+
+namespace cnnsns {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int C = 32;             // hidden channels
+constexpr int CIO = 3;            // velocity / displacement components
+constexpr int TAPS = 27;
+constexpr int NWT = TAPS * 4 * 64 * 4;  // operand-ordered weights of one 32 -> 32 layer (floats)
+constexpr int kBlock = 256;       // vector-ALU layers
+constexpr int kWaves32 = 16;      // matrix layers: waves per block
+constexpr int kSeg = 64;          // cells per wavefront work item (four 16-cell blocks)
+
+// wt[((tap * 2 + nb) * 2 + h) * 64 + l) * 4 + j] = W[16 nb + l%16][8 (l/16) + 4h + j][tap]
+__global__ void k3c_wprep(const float* __restrict__ w, float* __restrict__ wt)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NWT) return;
+    const int j = k & 3, l = (k >> 2) & 63, h = (k >> 8) & 1, nb = (k >> 9) & 1, tap = k >> 10;
+    const int o = 16 * nb + (l & 15), ci = 8 * (l >> 4) + 4 * h + j;
+    wt[k] = w[(o * C + ci) * TAPS + tap];
+}
+
+// Layer 1: 3 -> 32 with ReLU, one cell per lane; weights in LDS as [cin][tap][32].
+__global__ __launch_bounds__(kBlock) void k3c_conv1(int32_t G, const float* __restrict__ vel,
+                                                     const float* __restrict__ w, const float* __restrict__ b,
+                                                     float* __restrict__ out)
+{
+    __shared__ float s_w[CIO * TAPS * C];
+    __shared__ float s_b[C];
+    for (int k = threadIdx.x; k < CIO * TAPS * C; k += kBlock) {
+        const int o = k % C, ct = k / C;  // ct = cin * 27 + tap
+        s_w[k] = w[o * CIO * TAPS + ct];
+    }
+    if (threadIdx.x < C) s_b[threadIdx.x] = b[threadIdx.x];
+    __syncthreads();
+    const int64_t n = (int64_t)G * G * G;
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n) return;
+    const int x = (int)(v % G), y = (int)((v / G) % G), z = (int)(v / ((int64_t)G * G));
+    float acc[C];
+#pragma unroll
+    for (int o = 0; o < C; ++o) acc[o] = s_b[o];
+    for (int ci = 0; ci < CIO; ++ci) {
+        const float* plane = vel + (int64_t)ci * n;
+        for (int t = 0; t < TAPS; ++t) {
+            const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, X = x + t % 3 - 1;
+            if (Z < 0 || Z >= G || Y < 0 || Y >= G || X < 0 || X >= G) continue;
+            const float a = plane[((int64_t)Z * G + Y) * G + X];
+            const v4f* wr = reinterpret_cast<const v4f*>(s_w + (ci * TAPS + t) * C);
+#pragma unroll
+            for (int q = 0; q < C / 4; ++q) {
+                const v4f wq = wr[q];
+                acc[4 * q] += wq.x * a;
+                acc[4 * q + 1] += wq.y * a;
+                acc[4 * q + 2] += wq.z * a;
+                acc[4 * q + 3] += wq.w * a;
+            }
+        }
+    }
+    v4f* dst = reinterpret_cast<v4f*>(out + v * C);
+#pragma unroll
+    for (int q = 0; q < C / 4; ++q)
+        dst[q] = v4f{ fmaxf(acc[4 * q], 0.f), fmaxf(acc[4 * q + 1], 0.f), fmaxf(acc[4 * q + 2], 0.f),
+                      fmaxf(acc[4 * q + 3], 0.f) };
+}
+
+// Layers 2 and 3: 32 -> 32 with ReLU on the matrix cores.  Persistent blocks of 16 wavefronts;
+// the blocks of one XCD take contiguous ranges of work items (a work item is 64 cells of an x
+// row), so the rows above and below, which the taps read, are shared in that XCD's L2.
+__global__ __launch_bounds__(kWaves32 * 64) void k3c_conv32(int32_t G, const float* __restrict__ in,
+                                                            const float* __restrict__ wt,
+                                                            const float* __restrict__ bias,
+                                                            float* __restrict__ out)
+{
+    __shared__ v4f s_w[NWT / 4];
+    for (int k = threadIdx.x; k < NWT / 4; k += kWaves32 * 64) s_w[k] = reinterpret_cast<const v4f*>(wt)[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int segs = (G + kSeg - 1) / kSeg;
+    const int64_t n_items = (int64_t)G * G * segs;
+    // block -> contiguous item range, the blocks of one XCD (block id mod 8) next to each other
+    const int64_t nblk = gridDim.x;
+    int64_t lb = blockIdx.x;
+    if (nblk % 8 == 0) lb = (blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8;
+    const int64_t per = (n_items + nblk - 1) / nblk;
+    const int64_t i0 = lb * per, i1 = i0 + per < n_items ? i0 + per : n_items;
+    v4f bv[2];
+    bv[0] = *reinterpret_cast<const v4f*>(bias + 4 * grp);
+    bv[1] = *reinterpret_cast<const v4f*>(bias + 16 + 4 * grp);
+    for (int64_t item = i0 + wave; item < i1; item += kWaves32) {
+        const int seg = (int)(item % segs);
+        const int64_t row = item / segs;  // z G + y
+        const int y = (int)(row % G), z = (int)(row / G);
+        const int x0 = seg * kSeg;
+        v4f acc[4][2];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            acc[mb][0] = bv[0];
+            acc[mb][1] = bv[1];
+        }
+        for (int t = 0; t < TAPS; ++t) {
+            const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, dx = t % 3 - 1;
+            if (Z < 0 || Z >= G || Y < 0 || Y >= G) continue;  // a zero plane or row: no contribution
+            const float* src = in + ((int64_t)Z * G + Y) * G * C + 8 * grp;
+            v4f bop[4][2];
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) {
+                const int X = x0 + 16 * mb + col + dx;
+                if (X >= 0 && X < G) {
+                    const v4f* p = reinterpret_cast<const v4f*>(src + (int64_t)X * C);
+                    bop[mb][0] = p[0];
+                    bop[mb][1] = p[1];
+                } else {
+                    bop[mb][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
+                    bop[mb][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
+                }
+            }
+            v4f aop[2][2];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) aop[nb][h] = s_w[((t * 2 + nb) * 2 + h) * 64 + lane];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                        for (int nb = 0; nb < 2; ++nb)
+                            acc[mb][nb] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(aop[nb][h][j], bop[mb][h][j], acc[mb][nb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            const int X = x0 + 16 * mb + col;
+            if (X >= G) continue;
+            v4f* dst = reinterpret_cast<v4f*>(out + (row * G + X) * C + 4 * grp);
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const v4f a = acc[mb][nb];
+                dst[4 * nb] = v4f{ fmaxf(a.x, 0.f), fmaxf(a.y, 0.f), fmaxf(a.z, 0.f), fmaxf(a.w, 0.f) };
+            }
+        }
+    }
+}
+
+// Layer 4: 32 -> 3, no ReLU, one cell per lane; weights in LDS as [tap][cin][3].
+__global__ __launch_bounds__(kBlock) void k3c_conv4(int32_t G, const float* __restrict__ in,
+                                                     const float* __restrict__ w, const float* __restrict__ b,
+                                                     float* __restrict__ disp)
+{
+    __shared__ float s_w[TAPS * C * CIO];
+    for (int k = threadIdx.x; k < TAPS * C * CIO; k += kBlock) {
+        const int o = k % CIO, ci = (k / CIO) % C, t = k / (CIO * C);
+        s_w[k] = w[(o * C + ci) * TAPS + t];
+    }
+    __syncthreads();
+    const int64_t n = (int64_t)G * G * G;
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n) return;
+    const int x = (int)(v % G), y = (int)((v / G) % G), z = (int)(v / ((int64_t)G * G));
+    float acc[CIO] = { b[0], b[1], b[2] };
+    for (int t = 0; t < TAPS; ++t) {
+        const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, X = x + t % 3 - 1;
+        if (Z < 0 || Z >= G || Y < 0 || Y >= G || X < 0 || X >= G) continue;
+        const v4f* a4 = reinterpret_cast<const v4f*>(in + (((int64_t)Z * G + Y) * G + X) * C);
+        const float* wr = s_w + t * C * CIO;
+#pragma unroll
+        for (int q = 0; q < C / 4; ++q) {
+            const v4f a = a4[q];
+#pragma unroll
+            for (int o = 0; o < CIO; ++o)
+                acc[o] += wr[(4 * q) * CIO + o] * a.x + wr[(4 * q + 1) * CIO + o] * a.y +
+                          wr[(4 * q + 2) * CIO + o] * a.z + wr[(4 * q + 3) * CIO + o] * a.w;
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < CIO; ++o) disp[(int64_t)o * n + v] = acc[o];
+}
+
+unsigned blocks_for(int64_t n)
+{
+    return (unsigned)((n + kBlock - 1) / kBlock);
+}
+
+}  // namespace
+
+size_t cnn3_workspace_bytes(int32_t G)
+{
+    const size_t cells = (size_t)G * G * G;
+    return 2 * cells * C * sizeof(float) + 2 * (size_t)NWT * sizeof(float);
+}
+
+void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, float* disp, hipStream_t stream)
+{
+    const size_t need = cnn3_workspace_bytes(m.G);
+    {
+        std::lock_guard<std::mutex> lock(m.ws_mutex);
+        if (m.cnn_ws_bytes < need) {
+            if (m.cnn_ws) {
+                hip_check(hipDeviceSynchronize(), "predict3d workspace");
+                hip_check(hipFree(m.cnn_ws), "predict3d workspace free");
+                m.cnn_ws = nullptr;
+                m.cnn_ws_bytes = 0;
+            }
+            if (hipMalloc(&m.cnn_ws, need) != hipSuccess) {
+                m.cnn_ws = nullptr;
+                (void)hipGetLastError();
+                fail(CNNSNS_ENOMEM, "predict3d: workspace of " + std::to_string(need) + " bytes");
+            }
+            m.cnn_ws_bytes = need;
+        }
+    }
+    const int32_t G = m.G;
+    const int64_t cells = (int64_t)G * G * G;
+    float* act0 = static_cast<float*>(m.cnn_ws);
+    float* act1 = act0 + cells * C;
+    float* wt2 = act1 + cells * C;
+    float* wt3 = wt2 + NWT;
+    k3c_wprep<<<(NWT + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[1], wt2);
+    k3c_wprep<<<(NWT + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[2], wt3);
+    k3c_conv1<<<blocks_for(cells), kBlock, 0, stream>>>(G, vel, w.w[0], w.b[0], act0);
+    const unsigned grid = cnn_persistent_grid();
+    k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act0, wt2, w.b[1], act1);
+    k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act1, wt3, w.b[2], act0);
+    k3c_conv4<<<blocks_for(cells), kBlock, 0, stream>>>(G, act0, w.w[3], w.b[3], disp);
+    hip_check(hipGetLastError(), "predict3d launch");
+}
+
+}  // namespace cnnsns

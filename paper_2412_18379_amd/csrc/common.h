@@ -71,6 +71,10 @@ struct cnnsns_mesh3_s {
     cnnsns::TetRec* rec = nullptr;  // device [n_tet]
     int32_t* lookup = nullptr;      // device [G][G][G]
     int64_t device_bytes = 0;
+    // 3D CNN workspace, allocated on the first cnnsns_predict3d of this mesh
+    std::mutex ws_mutex;
+    void* cnn_ws = nullptr;
+    size_t cnn_ws_bytes = 0;
 };
 
 namespace cnnsns {
@@ -79,8 +83,12 @@ namespace cnnsns {
 cnnsns_mesh3 build_mesh3(const double* xyz, int64_t n_nodes, const int32_t* tet, int64_t n_tet, int32_t G,
                          hipStream_t stream);
 void destroy_mesh3(cnnsns_mesh3 m);
-void launch_locate3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const int32_t* start, int32_t max_iter,
-                    int32_t* host, int32_t* iters, uint8_t* status, hipStream_t stream);
+void launch_locate3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const int32_t* start, const double* origin,
+                    const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status,
+                    hipStream_t stream);
+// cnn3d.hip
+size_t cnn3_workspace_bytes(int32_t G);
+void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, float* disp, hipStream_t stream);
 
 // mesh.hip
 cnnsns_mesh build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, int64_t n_tri, int32_t G,

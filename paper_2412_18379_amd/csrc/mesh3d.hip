@@ -251,12 +251,23 @@ __global__ void k3_lookup_raster(int64_t n_tet, const TetRec* __restrict__ rec, 
             }
 }
 
+__device__ __forceinline__ double clamp01(double v)
+{
+    return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+}
+
+enum { S3_GIVEN = 0, S3_LOOKUP = 1, S3_CNN = 2 };
+
 // Alg. 1 for a batch of points, one lane per point.  (The wave-local refill of the 2D walk,
 // with 2, 4 or 8 points per lane, measured 8 to 37 % slower on 1M and 8M points in 5.8M
 // tetrahedra: neighbouring points walk alike, and the refill costs parallelism.)
-template <bool GIVEN>
+// Starts: given (K_m); the overlay lookup of x_p's cell; or CNN-SNS (Alg. 2): the lookup of
+// the cell holding x_hat = clamp(x_i + D[cell(x_i)], 0, 1), falling back to the given start
+// (else element 0) where that cell holds no element.
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k3_locate(const TetRec* __restrict__ rec, int64_t n_tet, int64_t n,
                                                     const double* __restrict__ xp, const int32_t* __restrict__ start,
+                                                    const double* __restrict__ origin, const float* __restrict__ disp,
                                                     const int32_t* __restrict__ lookup, int32_t G, int32_t max_iter,
                                                     int32_t* __restrict__ host, int32_t* __restrict__ iters,
                                                     uint8_t* __restrict__ status)
@@ -265,11 +276,19 @@ __global__ __launch_bounds__(kBlock) void k3_locate(const TetRec* __restrict__ r
     if (idx >= n) return;
     const double3 p{ xp[3 * idx], xp[3 * idx + 1], xp[3 * idx + 2] };
     int32_t K;
-    if (GIVEN) {
+    if (MODE == S3_GIVEN) {
         K = start[idx];
     } else {
-        K = lookup[((int64_t)cell3(p.z, G) * G + cell3(p.y, G)) * G + cell3(p.x, G)];
-        if (K < 0) K = 0;  // a cell with no element: start at element 0
+        double3 q = p;
+        if (MODE == S3_CNN) {
+            const double3 o{ origin[3 * idx], origin[3 * idx + 1], origin[3 * idx + 2] };
+            const int64_t nc = (int64_t)G * G * G;
+            const int64_t c = ((int64_t)cell3(o.z, G) * G + cell3(o.y, G)) * G + cell3(o.x, G);
+            q = double3{ clamp01(o.x + (double)disp[c]), clamp01(o.y + (double)disp[nc + c]),
+                         clamp01(o.z + (double)disp[2 * nc + c]) };
+        }
+        K = lookup[((int64_t)cell3(q.z, G) * G + cell3(q.y, G)) * G + cell3(q.x, G)];
+        if (K < 0) K = (MODE == S3_CNN && start) ? start[idx] : 0;  // a cell with no element
     }
     if (K < 0 || K >= n_tet) {
         host[idx] = -1;
@@ -410,23 +429,29 @@ void destroy_mesh3(cnnsns_mesh3 m)
     (void)hipDeviceSynchronize();
     (void)hipFree(m->rec);
     (void)hipFree(m->lookup);
+    if (m->cnn_ws) (void)hipFree(m->cnn_ws);
     (void)hipSetDevice(cur);
     delete m;
 }
 
-void launch_locate3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const int32_t* start, int32_t max_iter,
-                    int32_t* host, int32_t* iters, uint8_t* status, hipStream_t stream)
+void launch_locate3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const int32_t* start, const double* origin,
+                    const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status,
+                    hipStream_t stream)
 {
     if (n == 0) return;
     if (max_iter <= 0) max_iter = 1 << 20;
     const int64_t blocks = (n + kBlock - 1) / kBlock;
     if (blocks > (int64_t)INT32_MAX) fail(CNNSNS_EINVAL, "locate3d: too many points");
-    if (start)
-        k3_locate<true><<<(unsigned)blocks, kBlock, 0, stream>>>(m.rec, m.n_tet, n, xp, start, m.lookup, m.G, max_iter,
-                                                                 host, iters, status);
+    const unsigned g = (unsigned)blocks;
+    if (disp)
+        k3_locate<S3_CNN><<<g, kBlock, 0, stream>>>(m.rec, m.n_tet, n, xp, start, origin, disp, m.lookup, m.G,
+                                                    max_iter, host, iters, status);
+    else if (start)
+        k3_locate<S3_GIVEN><<<g, kBlock, 0, stream>>>(m.rec, m.n_tet, n, xp, start, origin, disp, m.lookup, m.G,
+                                                      max_iter, host, iters, status);
     else
-        k3_locate<false><<<(unsigned)blocks, kBlock, 0, stream>>>(m.rec, m.n_tet, n, xp, start, m.lookup, m.G,
-                                                                  max_iter, host, iters, status);
+        k3_locate<S3_LOOKUP><<<g, kBlock, 0, stream>>>(m.rec, m.n_tet, n, xp, start, origin, disp, m.lookup, m.G,
+                                                       max_iter, host, iters, status);
     hip_check(hipGetLastError(), "locate3d launch");
 }
 

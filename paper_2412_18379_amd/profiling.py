@@ -36,6 +36,8 @@ SOURCES = {
     "k_interp": ("sns_walk.hip",),
     "k3_locate_plain": ("mesh3d.hip",),
     "k3_locate_lookup": ("mesh3d.hip",),
+    "k3_locate_cnn": ("mesh3d.hip",),
+    "cnn3_forward_f32": ("cnn3d.hip",),
 }
 
 

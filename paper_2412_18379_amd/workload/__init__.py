@@ -426,6 +426,26 @@ def overlay_velocity_3d(flow, G: int) -> np.ndarray:
     return np.ascontiguousarray(np.stack([u, v, w]).astype(np.float32))
 
 
+def passthrough_weights_3d(dt: float):
+    """3D CNN weights (3 -> 32 -> 32 -> 32 -> 3, 3x3x3, OIDHW) whose output is -dt u at every cell:
+    layer 1 puts relu(u_a) and relu(-u_a) in channels 2a and 2a+1, layers 2 and 3 pass them on,
+    layer 4 forms -dt (u+ - u-).  A constructed stand-in for a trained net: the displacement of
+    one explicit step with the velocity of the origin's cell."""
+    w1 = np.zeros((32, 3, 3, 3, 3), np.float32)
+    w4 = np.zeros((3, 32, 3, 3, 3), np.float32)
+    for a in range(3):
+        w1[2 * a, a, 1, 1, 1] = 1.0
+        w1[2 * a + 1, a, 1, 1, 1] = -1.0
+        w4[a, 2 * a, 1, 1, 1] = -dt
+        w4[a, 2 * a + 1, 1, 1, 1] = dt
+    ident = np.zeros((32, 32, 3, 3, 3), np.float32)
+    for k in range(32):
+        ident[k, k, 1, 1, 1] = 1.0
+    ws = [w1, ident, ident.copy(), w4]
+    bs = [np.zeros(c, np.float32) for c in (32, 32, 32, 3)]
+    return ws, bs
+
+
 def tet_longest_edges(xyz: np.ndarray, tet: np.ndarray) -> np.ndarray:
     best = np.zeros(tet.shape[0])
     for a in range(4):
@@ -472,7 +492,9 @@ CONFIGS_3D = {
     # name: grid side, mesh seed, displacement in mean element diameters
     "t1": dict(n_side=16, seed=41, k=4.0),
     "t2": dict(n_side=48, seed=42, k=10.0),
-    "t3": dict(n_side=100, seed=43, k=10.0),
+    # the 1M-point mesh takes an overlay of about two cells per point (the default side for its
+    # 5.8M tetrahedra would be 256, 16.8M cells for the 3D CNN)
+    "t3": dict(n_side=100, seed=43, k=10.0, G=128),
 }
 
 
@@ -487,5 +509,5 @@ def build_3d(name: str) -> Workload3D:
     dt = cfg["k"] * dbar / float(np.mean(np.sqrt(u * u + v * v + w * w)))
     xp = np.clip(xyz - dt * np.stack([u, v, w], axis=1), 0.0, 1.0)
     return Workload3D(name=name, n_side=cfg["n_side"], xyz=xyz, tet=tet, xp=np.ascontiguousarray(xp),
-                      start=node_start_tets(xyz.shape[0], tet), G=overlay_side_for_3d(tet.shape[0]), dt=dt,
+                      start=node_start_tets(xyz.shape[0], tet), G=cfg.get("G", overlay_side_for_3d(tet.shape[0])), dt=dt,
                       dbar=dbar, flow=fl)

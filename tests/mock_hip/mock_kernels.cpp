@@ -78,10 +78,14 @@ cnnsns_mesh3 build_mesh3(const double*, int64_t, const int32_t*, int64_t, int32_
 
 void destroy_mesh3(cnnsns_mesh3) {}
 
-void launch_locate3(const cnnsns_mesh3_s&, int64_t, const double*, const int32_t*, int32_t, int32_t*, int32_t*,
-                    uint8_t*, hipStream_t)
+void launch_locate3(const cnnsns_mesh3_s&, int64_t, const double*, const int32_t*, const double*, const float*,
+                    int32_t, int32_t*, int32_t*, uint8_t*, hipStream_t)
 {
 }
+
+size_t cnn3_workspace_bytes(int32_t) { return 0; }
+
+void run_predict3(cnnsns_mesh3_s&, const float*, const cnnsns_cnn&, float*, hipStream_t) {}
 
 void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t*, const double* origin,
                    const float* disp, int32_t, int32_t* host, int32_t* iters, uint8_t*, hipStream_t)

@@ -108,14 +108,16 @@ def test_edge_cases(C, wl):
     h, it, st = C.locate3d(mesh, _dev(np.zeros((0, 3))))
     assert h.shape == (0,)
     lib = C.lib()
-    assert lib.cnnsns_locate3d(mesh.handle, -1, None, None, 0, None, None, None, None) == C.EINVAL
-    assert lib.cnnsns_locate3d(mesh.handle, 4, None, None, 0, None, None, None, None) == C.EINVAL
-    assert lib.cnnsns_locate3d(None, 0, None, None, 0, None, None, None, None) == C.EINVAL
-    assert lib.cnnsns_locate3d(mesh.handle, 0, None, None, 0, None, None, None, None) == C.OK
+    nulls = (None, None, None, None, 0, None, None, None, None)
+    assert lib.cnnsns_locate3d(mesh.handle, -1, *nulls) == C.EINVAL
+    assert lib.cnnsns_locate3d(mesh.handle, 4, *nulls) == C.EINVAL
+    assert lib.cnnsns_locate3d(None, 0, *nulls) == C.EINVAL
+    assert lib.cnnsns_locate3d(mesh.handle, 0, *nulls) == C.OK
     # iters and status may be NULL
     xp = _dev(w.xp[:1000])
     host = torch.empty(1000, dtype=torch.int32, device="cuda")
-    assert lib.cnnsns_locate3d(mesh.handle, 1000, xp.data_ptr(), None, 0, host.data_ptr(), None, None, None) == C.OK
+    assert lib.cnnsns_locate3d(mesh.handle, 1000, xp.data_ptr(), None, None, None, 0, host.data_ptr(), None, None,
+                               None) == C.OK
     ref, _, _ = C.locate3d(mesh, xp)
     assert torch.equal(host, ref)
 

@@ -95,19 +95,9 @@ def test_zero_weights_give_the_bias_chain(oracle_mod):
 
 
 def constructed_net(dt):
-    """3 -> 32 -> 32 -> 32 -> 3 weights whose output is -dt u exactly: layer 1 puts relu(u_a) and
-    relu(-u_a) in channels 2a and 2a+1, layers 2-3 pass them on, layer 4 forms -dt (u+ - u-)."""
-    w1 = np.zeros((32, 3, 3, 3, 3), np.float32)
-    for a in range(3):
-        w1[2 * a, a, 1, 1, 1] = 1.0
-        w1[2 * a + 1, a, 1, 1, 1] = -1.0
-    w4 = np.zeros((3, 32, 3, 3, 3), np.float32)
-    for a in range(3):
-        w4[a, 2 * a, 1, 1, 1] = -dt
-        w4[a, 2 * a + 1, 1, 1, 1] = dt
-    ws = [w1, _identity(32), _identity(32), w4]
-    bs = [np.zeros(c, np.float32) for c in (32, 32, 32, 3)]
-    return ws, bs
+    """The input generator's pass-through net (output -dt u)."""
+    from paper_2412_18379_amd import workload as W
+    return W.passthrough_weights_3d(dt)
 
 
 def test_constructed_weights_give_minus_dt_u(oracle_mod):
