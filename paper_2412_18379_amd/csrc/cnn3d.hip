@@ -15,7 +15,8 @@
 // sit in LDS in operand order (108 KiB, loaded once per block), the
 // activations come through the caches (a cell's 32 channels are one 128-byte
 // line).  Layers 1 and 4 (3 -> 32, 32 -> 3) are 9 % of the work and run on the
-// vector ALUs, one cell per lane.
+// vector ALUs: layer 1 one cell per lane, layer 4 four lanes per cell (each with
+// 8 of the 32 input channels, read as the matrix layers read them).
 //
 // Activations between layers: FP32 [G^3][32], cell-major (z, y, x; x fastest),
 // 32 channels per cell.  Input velocity and output displacement: FP32
@@ -34,7 +35,8 @@ constexpr int CIO = 3;            // velocity / displacement components
 constexpr int TAPS = 27;
 constexpr int NWT = TAPS * 4 * 64 * 4;  // operand-ordered weights of one 32 -> 32 layer (floats)
 constexpr int kBlock = 256;       // vector-ALU layers
-constexpr int kWaves32 = 16;      // matrix layers: waves per block
+constexpr int kWaves32 = 8;       // matrix layers: waves per block (168 registers each)
+constexpr int kWaves4 = 16;       // layer 4: waves per block
 constexpr int kSeg = 64;          // cells per wavefront work item (four 16-cell blocks)
 
 // wt[((tap * 2 + nb) * 2 + h) * 64 + l) * 4 + j] = W[16 nb + l%16][8 (l/16) + 4h + j][tap]
@@ -91,9 +93,23 @@ __global__ __launch_bounds__(kBlock) void k3c_conv1(int32_t G, const float* __re
                       fmaxf(acc[4 * q + 3], 0.f) };
 }
 
-// Layers 2 and 3: 32 -> 32 with ReLU on the matrix cores.  Persistent blocks of 16 wavefronts;
-// the blocks of one XCD take contiguous ranges of work items (a work item is 64 cells of an x
-// row), so the rows above and below, which the taps read, are shared in that XCD's L2.
+// The work items (64 cells of an x row) of a persistent block: the blocks of one XCD (block id
+// mod 8) take neighbouring contiguous ranges, so the rows above and below and the neighbouring
+// planes, which the taps read, are shared in that XCD's L2.
+__device__ __forceinline__ void item_range(int64_t n_items, int64_t& i0, int64_t& i1)
+{
+    const int64_t nblk = gridDim.x;
+    int64_t lb = blockIdx.x;
+    if (nblk % 8 == 0) lb = (blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8;
+    const int64_t per = (n_items + nblk - 1) / nblk;
+    i0 = lb * per;
+    i1 = i0 + per < n_items ? i0 + per : n_items;
+}
+
+// Layers 2 and 3: 32 -> 32 with ReLU on the matrix cores, persistent blocks of 8 wavefronts (two
+// per SIMD).  The next tap's activations are loaded while this tap's 64 matrix instructions run:
+// that needs 168 registers, so two wavefronts per SIMD instead of four without the prefetch
+// (3.43 -> 3.25 ms for the whole pass at G = 128; four wavefronts with the prefetch spill).
 __global__ __launch_bounds__(kWaves32 * 64) void k3c_conv32(int32_t G, const float* __restrict__ in,
                                                             const float* __restrict__ wt,
                                                             const float* __restrict__ bias,
@@ -107,12 +123,8 @@ __global__ __launch_bounds__(kWaves32 * 64) void k3c_conv32(int32_t G, const flo
     const int col = lane & 15, grp = lane >> 4;
     const int segs = (G + kSeg - 1) / kSeg;
     const int64_t n_items = (int64_t)G * G * segs;
-    // block -> contiguous item range, the blocks of one XCD (block id mod 8) next to each other
-    const int64_t nblk = gridDim.x;
-    int64_t lb = blockIdx.x;
-    if (nblk % 8 == 0) lb = (blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8;
-    const int64_t per = (n_items + nblk - 1) / nblk;
-    const int64_t i0 = lb * per, i1 = i0 + per < n_items ? i0 + per : n_items;
+    int64_t i0, i1;
+    item_range(n_items, i0, i1);
     v4f bv[2];
     bv[0] = *reinterpret_cast<const v4f*>(bias + 4 * grp);
     bv[1] = *reinterpret_cast<const v4f*>(bias + 16 + 4 * grp);
@@ -127,23 +139,27 @@ __global__ __launch_bounds__(kWaves32 * 64) void k3c_conv32(int32_t G, const flo
             acc[mb][0] = bv[0];
             acc[mb][1] = bv[1];
         }
-        for (int t = 0; t < TAPS; ++t) {
+        auto load = [&](int t, v4f (&bo)[4][2]) {
             const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, dx = t % 3 - 1;
-            if (Z < 0 || Z >= G || Y < 0 || Y >= G) continue;  // a zero plane or row: no contribution
-            const float* src = in + ((int64_t)Z * G + Y) * G * C + 8 * grp;
-            v4f bop[4][2];
+            const bool ok = Z >= 0 && Z < G && Y >= 0 && Y < G;
+            const float* src = in + ((int64_t)(ok ? Z : 0) * G + (ok ? Y : 0)) * G * C + 8 * grp;
 #pragma unroll
             for (int mb = 0; mb < 4; ++mb) {
                 const int X = x0 + 16 * mb + col + dx;
-                if (X >= 0 && X < G) {
+                if (ok && X >= 0 && X < G) {
                     const v4f* p = reinterpret_cast<const v4f*>(src + (int64_t)X * C);
-                    bop[mb][0] = p[0];
-                    bop[mb][1] = p[1];
+                    bo[mb][0] = p[0];
+                    bo[mb][1] = p[1];
                 } else {
-                    bop[mb][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
-                    bop[mb][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
+                    bo[mb][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
+                    bo[mb][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
                 }
             }
+        };
+        v4f bop[4][2], bnx[4][2];
+        load(0, bop);
+        for (int t = 0; t < TAPS; ++t) {
+            if (t + 1 < TAPS) load(t + 1, bnx);
             v4f aop[2][2];
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb)
@@ -159,6 +175,11 @@ __global__ __launch_bounds__(kWaves32 * 64) void k3c_conv32(int32_t G, const flo
                         for (int nb = 0; nb < 2; ++nb)
                             acc[mb][nb] =
                                 __builtin_amdgcn_mfma_f32_16x16x4f32(aop[nb][h][j], bop[mb][h][j], acc[mb][nb], 0, 0, 0);
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) {
+                bop[mb][0] = bnx[mb][0];
+                bop[mb][1] = bnx[mb][1];
+            }
         }
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
@@ -174,38 +195,88 @@ __global__ __launch_bounds__(kWaves32 * 64) void k3c_conv32(int32_t G, const flo
     }
 }
 
-// Layer 4: 32 -> 3, no ReLU, one cell per lane; weights in LDS as [tap][cin][3].
-__global__ __launch_bounds__(kBlock) void k3c_conv4(int32_t G, const float* __restrict__ in,
-                                                     const float* __restrict__ w, const float* __restrict__ b,
-                                                     float* __restrict__ disp)
+__device__ __forceinline__ void conv4_item(int32_t G, const float* __restrict__ in, const v4f* s_w, int segs,
+                                           int64_t item, int col, int grp, int64_t n, float bias,
+                                           float* __restrict__ disp)
 {
-    __shared__ float s_w[TAPS * C * CIO];
-    for (int k = threadIdx.x; k < TAPS * C * CIO; k += kBlock) {
-        const int o = k % CIO, ci = (k / CIO) % C, t = k / (CIO * C);
-        s_w[k] = w[(o * C + ci) * TAPS + t];
-    }
-    __syncthreads();
-    const int64_t n = (int64_t)G * G * G;
-    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (v >= n) return;
-    const int x = (int)(v % G), y = (int)((v / G) % G), z = (int)(v / ((int64_t)G * G));
-    float acc[CIO] = { b[0], b[1], b[2] };
+    const int seg = (int)(item % segs);
+    const int64_t row = item / segs;
+    const int y = (int)(row % G), z = (int)(row / G);
+    const int x0 = seg * kSeg;
+    float acc[4][CIO];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int o = 0; o < CIO; ++o) acc[mb][o] = 0.f;
     for (int t = 0; t < TAPS; ++t) {
-        const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, X = x + t % 3 - 1;
-        if (Z < 0 || Z >= G || Y < 0 || Y >= G || X < 0 || X >= G) continue;
-        const v4f* a4 = reinterpret_cast<const v4f*>(in + (((int64_t)Z * G + Y) * G + X) * C);
-        const float* wr = s_w + t * C * CIO;
+        const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, dx = t % 3 - 1;
+        if (Z < 0 || Z >= G || Y < 0 || Y >= G) continue;
+        const float* src = in + ((int64_t)Z * G + Y) * G * C + 8 * grp;
+        const v4f* wq = s_w + (t * 4 + grp) * 6;  // 24 floats: [channel][output]
+        const v4f w0 = wq[0], w1 = wq[1], w2 = wq[2], w3 = wq[3], w4 = wq[4], w5 = wq[5];
+        const float wv[24] = { w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w, w2.x, w2.y, w2.z, w2.w,
+                               w3.x, w3.y, w3.z, w3.w, w4.x, w4.y, w4.z, w4.w, w5.x, w5.y, w5.z, w5.w };
 #pragma unroll
-        for (int q = 0; q < C / 4; ++q) {
-            const v4f a = a4[q];
+        for (int mb = 0; mb < 4; ++mb) {
+            const int X = x0 + 16 * mb + col + dx;
+            if (X < 0 || X >= G) continue;
+            const v4f* p = reinterpret_cast<const v4f*>(src + (int64_t)X * C);
+            const v4f a0 = p[0], a1 = p[1];
+            const float av[8] = { a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w };
 #pragma unroll
-            for (int o = 0; o < CIO; ++o)
-                acc[o] += wr[(4 * q) * CIO + o] * a.x + wr[(4 * q + 1) * CIO + o] * a.y +
-                          wr[(4 * q + 2) * CIO + o] * a.z + wr[(4 * q + 3) * CIO + o] * a.w;
+            for (int c = 0; c < 8; ++c)
+#pragma unroll
+                for (int o = 0; o < CIO; ++o) acc[mb][o] += wv[c * CIO + o] * av[c];
         }
     }
+    // add the four lane groups (lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same cell)
 #pragma unroll
-    for (int o = 0; o < CIO; ++o) disp[(int64_t)o * n + v] = acc[o];
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int o = 0; o < CIO; ++o) {
+            float v = acc[mb][o];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            acc[mb][o] = v;
+        }
+    // lane group g < 3 writes output component g for the 64 cells
+    if (grp < CIO) {
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            const int X = x0 + 16 * mb + col;
+            if (X >= G) continue;
+            const float v = grp == 0 ? acc[mb][0] : (grp == 1 ? acc[mb][1] : acc[mb][2]);
+            disp[(int64_t)grp * n + row * G + X] = v + bias;
+        }
+    }
+}
+
+
+// Layer 4: 32 -> 3, no ReLU.  A wavefront takes a work item of 64 cells of an x row as the
+// matrix layers do, and reads activations the same way: lane l loads channels 8 (l/16) .. +7 of
+// cell l%16 of each 16-cell block (four lanes cover a cell's 128-byte line), forms the partial
+// sums of its 8 channels for the 3 outputs, and the four lane groups' sums are added across lanes.
+// Weights in LDS as [tap][lane group][8 channels][3].
+__global__ __launch_bounds__(kWaves4 * 64) void k3c_conv4(int32_t G, const float* __restrict__ in,
+                                                           const float* __restrict__ w, const float* __restrict__ b,
+                                                           float* __restrict__ disp)
+{
+    __shared__ v4f s_w[TAPS * C * CIO / 4];
+    float* const sw = reinterpret_cast<float*>(s_w);
+    for (int k = threadIdx.x; k < TAPS * C * CIO; k += kWaves4 * 64) {
+        const int o = k % CIO, ci = (k / CIO) % C, t = k / (CIO * C);  // ci = 8 group + channel
+        sw[k] = w[(o * C + ci) * TAPS + t];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, grp = lane >> 4;
+    const int segs = (G + kSeg - 1) / kSeg;
+    const int64_t n = (int64_t)G * G * G;
+    const float bias = b[grp < CIO ? grp : 0];
+    int64_t i0, i1;
+    item_range((int64_t)G * G * segs, i0, i1);
+    for (int64_t item = i0 + (threadIdx.x >> 6); item < i1; item += kWaves4)
+        conv4_item(G, in, s_w, segs, item, col, grp, n, bias, disp);
 }
 
 unsigned blocks_for(int64_t n)
@@ -253,7 +324,7 @@ void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, floa
     const unsigned grid = cnn_persistent_grid();
     k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act0, wt2, w.b[1], act1);
     k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act1, wt3, w.b[2], act0);
-    k3c_conv4<<<blocks_for(cells), kBlock, 0, stream>>>(G, act0, w.w[3], w.b[3], disp);
+    k3c_conv4<<<grid, kWaves4 * 64, 0, stream>>>(G, act0, w.w[3], w.b[3], disp);
     hip_check(hipGetLastError(), "predict3d launch");
 }
 
