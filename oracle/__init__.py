@@ -27,6 +27,8 @@ Parity status of each function (what pins it, see ``tests/test_oracle_*.py``):
   cnn3_window / cnn3_forward - torch.nn.functional.conv3d in float64; impulse
                               responses; in-grid tap counts of a constant
                               input; constructed pass-through weights
+  interpolate3              - linear fields, constants, node values, numpy
+                              barycentric solve, convex-field bound
   cnnsns3_start             - zero displacement at cell centres gives the
                               lookup; clamping; x = 1 maps to cell G-1;
                               fallback of empty cells
@@ -88,6 +90,7 @@ def _L():
             "orc3_lookup": [i64, vp, vp, i32, vp],
             "orc3_brute_force": [i64, vp, vp, i64, vp, vp],
             "orc3_cnn_window": [i32, vp, vp, vp, vp, vp, vp, vp],
+            "orc3_interp": [i64, vp, vp, vp, i64, vp, vp, vp],
             "orc3_cnnsns_start": [i64, vp, i32, vp, vp, vp, vp],
         }
         for name, args in sig.items():
@@ -334,3 +337,17 @@ def cnnsns3(xyz, tet_pos, nbr, lookup_grid, origin, xp, disp, fallback=None, max
     st = cnnsns3_start(origin, disp, lookup_grid, fallback)
     h, it, s = sns3(xyz, tet_pos, nbr, xp, st, max_iter)
     return st, h, it, s
+
+
+def interpolate3(xyz, tet_pos, nodal, xp, host):
+    """P1 interpolation of a nodal field FP64 [n_nodes][3] at the points in their host tetrahedra."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    nodal = np.ascontiguousarray(nodal, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    host = np.ascontiguousarray(host, dtype=np.int32)
+    if nodal.shape != (xyz.shape[0], 3):
+        raise ValueError("nodal must be [n_nodes][3]")
+    out = np.empty((xp.shape[0], 3), np.float64)
+    _check(_L().orc3_interp(tet_pos.shape[0], _p(xyz), _p(tet_pos), _p(nodal), xp.shape[0], _p(xp), _p(host),
+                            _p(out)), "interpolate3")
+    return out

@@ -640,6 +640,50 @@ int orc3_sns(int64_t n_tet, const double* xyz, const int32_t* tet, const int32_t
 }
 
 /*
+ * P1 interpolation at x_p in its host tetrahedron (Sec. 2.1 after eq. 4 with
+ * the nodal basis of Sec. 2.2): u(x_p) = sum_j (s_j / V) u(n_j), with s_j the
+ * four barycentric numerators and V = det[b - a, c - a, d - a] > 0 six times
+ * the volume.  V is evaluated with the vertices in ascending node id (the sign
+ * of that permutation applied) and the sum runs over the vertices in
+ * ascending node id, so the value does not depend on the element's vertex
+ * order.  nodal: [n_nodes][3]; out: [n][3]; a host outside [0, n_tet) gives NaN.
+ */
+int orc3_interp(int64_t n_tet, const double* xyz, const int32_t* tet, const double* nodal, int64_t n,
+                const double* xp, const int32_t* host, double* out)
+{
+    if (n < 0 || n_tet < 0) return ORC_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t t = host[i];
+        if (t < 0 || t >= n_tet) {
+            out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = NAN;
+            continue;
+        }
+        const double* v[4];
+        int32_t id[4];
+        double s[4];
+        tet_vertices(xyz, tet, t, v, id);
+        bary3_numerators(v, id, xp + 3 * i, s);
+        int ord[4] = { 0, 1, 2, 3 }, sign = 1;
+        for (int a = 1; a < 4; ++a) /* insertion sort by node id, one sign flip per swap */
+            for (int b = a; b > 0 && id[ord[b - 1]] > id[ord[b]]; --b) {
+                const int x = ord[b];
+                ord[b] = ord[b - 1];
+                ord[b - 1] = x;
+                sign = -sign;
+            }
+        double V = orient3(v[ord[0]], v[ord[1]], v[ord[2]], v[ord[3]]);
+        if (sign < 0) V = -V;
+        for (int c = 0; c < 3; ++c) {
+            double f = 0.0;
+            for (int k = 0; k < 4; ++k) f += (s[ord[k]] / V) * nodal[3 * (int64_t)id[ord[k]] + c];
+            out[3 * i + c] = f;
+        }
+    }
+    return ORC_OK;
+}
+
+/*
  * 3D overlay: lookup[(cz G + cy) G + cx] is the smallest id of a tetrahedron
  * whose closed region contains the cell centre ((c + 1/2) / G per axis), or
  * -1.  Tetrahedra in increasing id test the centres in their bounding box;
