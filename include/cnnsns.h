@@ -263,6 +263,24 @@ int cnnsns_locate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int32_t* 
                     const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status, void* stream);
 
 /*
+ * P1 interpolation of a nodal field at points in their host tetrahedra
+ * (Sec. 2.1 after eq. 4; the nodal basis functions are the barycentric
+ * coordinates of Sec. 2.2): u(x_p) = sum_j (s_j / V) u(n_j), with s_j the
+ * numerators of cnnsns_locate3d and V six times the element's volume,
+ * evaluated with the nodes in ascending id, the sum taken over the nodes in
+ * ascending id (FP64, no fused multiply-add).  DEVICE arrays:
+ *   xp     FP64 [n][3] points.
+ *   host   int32 [n] host tetrahedra (from cnnsns_locate3d); an id outside
+ *          [0, n_tet) gives NaN in all three components.
+ *   nodal  FP64 [n_nodes][3] field values at the mesh nodes.
+ *   out    FP64 [n][3] interpolated values.
+ * Asynchronous on `stream`.  n == 0 is a no-op.  Errors: EINVAL (null mesh or
+ * array, n < 0), EHIP.
+ */
+int cnnsns_interpolate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
+                         double* out, void* stream);
+
+/*
  * Serving loop: a host scheduler that takes CNN-SNS tracking jobs on
  * resident meshes as they arrive and runs them with continuous batching.
  * Each job is one CNN forward pass over its mesh's overlay (in `precision`)

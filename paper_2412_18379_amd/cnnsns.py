@@ -24,7 +24,7 @@ PRECISIONS = {"f32": F32, "bf16": BF16, "fp8": FP8E4M3}
 EXPORTS = (
     "cnnsns_build_mesh", "cnnsns_mesh_info", "cnnsns_destroy_mesh", "cnnsns_predict", "cnnsns_locate",
     "cnnsns_interpolate", "cnnsns_build_mesh3d", "cnnsns_mesh3d_info", "cnnsns_destroy_mesh3d", "cnnsns_predict3d",
-    "cnnsns_locate3d",
+    "cnnsns_locate3d", "cnnsns_interpolate3d",
     "cnnsns_server_create", "cnnsns_submit", "cnnsns_poll", "cnnsns_wait", "cnnsns_server_destroy",
     "cnnsns_last_error",
 )
@@ -63,6 +63,7 @@ def lib():
             "cnnsns_destroy_mesh3d": [vp],
             "cnnsns_predict3d": [vp, vp, ctypes.POINTER(_Cnn), i32, vp, vp],
             "cnnsns_locate3d": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp],
+            "cnnsns_interpolate3d": [vp, i64, vp, vp, vp, vp, vp],
             "cnnsns_server_create": [i64, i32, i32, i32, ctypes.POINTER(_Cnn), ctypes.POINTER(vp)],
             "cnnsns_submit": [vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)],
             "cnnsns_poll": [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
@@ -209,6 +210,7 @@ class Mesh3D:
         n_tet, G, nbytes = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
         _check(lib().cnnsns_mesh3d_info(h, ctypes.byref(n_tet), ctypes.byref(G), ctypes.byref(nbytes)))
         self.n_tet, self.G, self.device_bytes = n_tet.value, G.value, nbytes.value
+        self.n_nodes = int(xyz.shape[0])
 
     def close(self):
         if self.handle:
@@ -274,6 +276,22 @@ def locate3d(mesh: Mesh3D, xp: torch.Tensor, start: torch.Tensor = None, origin:
     _check(lib().cnnsns_locate3d(mesh.handle, n, _ptr(xp), _ptr(start), _ptr(origin), _ptr(disp), int(max_iter),
                                  _ptr(host), _ptr(iters), _ptr(status), _stream(stream)))
     return host, iters, status
+
+
+def interpolate3d(mesh: Mesh3D, xp: torch.Tensor, host: torch.Tensor, nodal: torch.Tensor, out: torch.Tensor = None,
+                  stream=None) -> torch.Tensor:
+    """P1 interpolation of a nodal field (FP64 [n_nodes][3]) at points in their host tetrahedra
+    (cnnsns_interpolate3d)."""
+    n = xp.shape[0]
+    _need(xp, torch.float64, (n, 3), "xp")
+    _need(host, torch.int32, (n,), "host")
+    _need(nodal, torch.float64, (mesh.n_nodes, 3), "nodal")
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float64, device=xp.device)
+    _need(out, torch.float64, (n, 3), "out")
+    _check(lib().cnnsns_interpolate3d(mesh.handle, n, _ptr(xp), _ptr(host), _ptr(nodal), _ptr(out),
+                                      _stream(stream)))
+    return out
 
 
 def interpolate(mesh: Mesh, xp: torch.Tensor, host: torch.Tensor, nodal: torch.Tensor, out: torch.Tensor = None,

@@ -182,6 +182,19 @@ int cnnsns_locate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int32_t* 
     });
 }
 
+int cnnsns_interpolate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
+                         double* out, void* stream)
+{
+    return guarded([&] {
+        if (!m) fail(CNNSNS_EINVAL, "interpolate3d: NULL mesh");
+        if (n < 0) fail(CNNSNS_EINVAL, "interpolate3d: n must be >= 0");
+        if (n == 0) return;
+        if (!xp || !host || !nodal || !out) fail(CNNSNS_EINVAL, "interpolate3d: NULL argument");
+        DeviceScope ds(m->device);
+        launch_interp3(*m, n, xp, host, nodal, out, static_cast<hipStream_t>(stream));
+    });
+}
+
 int cnnsns_interpolate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
                        double* out, void* stream)
 {

@@ -69,6 +69,7 @@ struct cnnsns_mesh3_s {
     int64_t n_tet = 0;
     int32_t G = 0;
     cnnsns::TetRec* rec = nullptr;  // device [n_tet]
+    int32_t* ids = nullptr;         // device [n_tet][4] node ids, in the records' (ascending id) order
     int32_t* lookup = nullptr;      // device [G][G][G]
     int64_t device_bytes = 0;
     // 3D CNN workspace, allocated on the first cnnsns_predict3d of this mesh
@@ -86,6 +87,8 @@ void destroy_mesh3(cnnsns_mesh3 m);
 void launch_locate3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const int32_t* start, const double* origin,
                     const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status,
                     hipStream_t stream);
+void launch_interp3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
+                    double* out, hipStream_t stream);
 // cnn3d.hip
 size_t cnn3_workspace_bytes(int32_t G);
 void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, float* disp, hipStream_t stream);

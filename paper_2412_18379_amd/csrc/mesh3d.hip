@@ -150,7 +150,7 @@ __global__ void k3_neighbours(int64_t n_tet, const double* __restrict__ xyz, con
 // of the permutation gives the orientation of the sorted order, the element order being
 // positive), with the neighbours and positions carried along.
 __global__ void k3_pack(int64_t n_tet, const double* __restrict__ xyz, const int32_t* __restrict__ tet,
-                        const int32_t* __restrict__ nbr, TetRec* __restrict__ rec)
+                        const int32_t* __restrict__ nbr, TetRec* __restrict__ rec, int4* __restrict__ ids)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tet) return;
@@ -182,6 +182,7 @@ __global__ void k3_pack(int64_t n_tet, const double* __restrict__ xyz, const int
     r.pos = (uint32_t)ps[0] | ((uint32_t)ps[1] << 8) | ((uint32_t)ps[2] << 16) | ((uint32_t)ps[3] << 24);
     r.pad[0] = r.pad[1] = 0;
     rec[t] = r;
+    ids[t] = int4{ id[0], id[1], id[2], id[3] };
 }
 
 __device__ __forceinline__ void load_tet(const TetRec* __restrict__ rec, int64_t t, double3* v, int32_t* nb,
@@ -338,6 +339,47 @@ __global__ __launch_bounds__(kBlock) void k3_locate(const TetRec* __restrict__ r
     if (status) status[idx] = (uint8_t)fin;
 }
 
+// P1 interpolation at x_p in its host tetrahedron (Sec. 2.1 after eq. 4): u(x_p) = sum_k
+// (s_k / V) u(n_k) over the vertices in ascending node id (the record's order), with s_k the
+// walk's numerators and V = det[v1 - v0, v2 - v0, v3 - v0] in that order times its orientation
+// (six times the volume, > 0).  A host outside [0, n_tet) gives NaN.
+__global__ __launch_bounds__(kBlock) void k3_interp(const TetRec* __restrict__ rec, const int4* __restrict__ ids,
+                                                    int64_t n_tet, int64_t n, const double* __restrict__ xp,
+                                                    const int32_t* __restrict__ host,
+                                                    const double* __restrict__ nodal, double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t K = host[i];
+    if (K < 0 || K >= n_tet) {
+        out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = __builtin_nan("");
+        return;
+    }
+    const double3 p{ xp[3 * i], xp[3 * i + 1], xp[3 * i + 2] };
+    double3 v[4];
+    int32_t nb[4], o;
+    uint32_t pos;
+    load_tet(rec, K, v, nb, o, pos);
+    double s[4];
+    numerators(p, v, o, s);
+    const double d = orient3(v[0], v[1], v[2], v[3]);
+    const double V = o > 0 ? d : -d;
+    const int4 id = ids[K];
+    const int32_t nid[4] = { id.x, id.y, id.z, id.w };
+    double f[3] = { 0.0, 0.0, 0.0 };
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double l = s[k] / V;
+        const double* u = nodal + 3 * (int64_t)nid[k];
+        f[0] = f[0] + l * u[0];
+        f[1] = f[1] + l * u[1];
+        f[2] = f[2] + l * u[2];
+    }
+    out[3 * i] = f[0];
+    out[3 * i + 1] = f[1];
+    out[3 * i + 2] = f[2];
+}
+
 template <class T>
 struct DevBuf3 {
     T* p = nullptr;
@@ -373,6 +415,7 @@ cnnsns_mesh3 build_mesh3(const double* xyz, int64_t n_nodes, const int32_t* tet,
     DevBuf3<unsigned long long> d_deg((size_t)n_nodes + 1), d_first((size_t)n_nodes + 1), d_cursor((size_t)n_nodes + 1);
     DevBuf3<int> d_err(1);
     DevBuf3<TetRec> d_rec((size_t)n_tet);
+    DevBuf3<int4> d_ids((size_t)n_tet);
     const int64_t ncell = (int64_t)G * G * G;
     DevBuf3<int32_t> d_lookup((size_t)ncell);
 
@@ -396,7 +439,7 @@ cnnsns_mesh3 build_mesh3(const double* xyz, int64_t n_nodes, const int32_t* tet,
         k3_fill<<<grid_for(4 * n_tet), kBlock, 0, stream>>>(n_tet, d_tet.p, d_cursor.p, d_inc.p);
         k3_neighbours<<<grid_for(4 * n_tet), kBlock, 0, stream>>>(n_tet, d_xyz.p, d_tet.p, d_first.p, d_inc.p,
                                                                   d_nbr.p, d_err.p);
-        k3_pack<<<grid_for(n_tet), kBlock, 0, stream>>>(n_tet, d_xyz.p, d_tet.p, d_nbr.p, d_rec.p);
+        k3_pack<<<grid_for(n_tet), kBlock, 0, stream>>>(n_tet, d_xyz.p, d_tet.p, d_nbr.p, d_rec.p, d_ids.p);
         k3_fill_i32<<<grid_for(ncell), kBlock, 0, stream>>>(ncell, d_lookup.p, INT_MAX);
         k3_lookup_raster<<<grid_for(n_tet), kBlock, 0, stream>>>(n_tet, d_rec.p, G, d_lookup.p);
         k3_lookup_finish<<<grid_for(ncell), kBlock, 0, stream>>>(ncell, d_lookup.p);
@@ -415,8 +458,9 @@ cnnsns_mesh3 build_mesh3(const double* xyz, int64_t n_nodes, const int32_t* tet,
     m->n_tet = n_tet;
     m->G = G;
     m->rec = d_rec.release();
+    m->ids = reinterpret_cast<int32_t*>(d_ids.release());
     m->lookup = d_lookup.release();
-    m->device_bytes = (int64_t)(sizeof(TetRec) * (size_t)n_tet + sizeof(int32_t) * (size_t)ncell);
+    m->device_bytes = (int64_t)((sizeof(TetRec) + sizeof(int4)) * (size_t)n_tet + sizeof(int32_t) * (size_t)ncell);
     return m;
 }
 
@@ -428,6 +472,7 @@ void destroy_mesh3(cnnsns_mesh3 m)
     (void)hipSetDevice(m->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(m->rec);
+    (void)hipFree(m->ids);
     (void)hipFree(m->lookup);
     if (m->cnn_ws) (void)hipFree(m->cnn_ws);
     (void)hipSetDevice(cur);
@@ -453,6 +498,17 @@ void launch_locate3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const 
         k3_locate<S3_LOOKUP><<<g, kBlock, 0, stream>>>(m.rec, m.n_tet, n, xp, start, origin, disp, m.lookup, m.G,
                                                        max_iter, host, iters, status);
     hip_check(hipGetLastError(), "locate3d launch");
+}
+
+void launch_interp3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
+                    double* out, hipStream_t stream)
+{
+    if (n == 0) return;
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > (int64_t)INT32_MAX) fail(CNNSNS_EINVAL, "interpolate3d: too many points");
+    k3_interp<<<(unsigned)blocks, kBlock, 0, stream>>>(m.rec, reinterpret_cast<const int4*>(m.ids), m.n_tet, n, xp,
+                                                       host, nodal, out);
+    hip_check(hipGetLastError(), "interpolate3d launch");
 }
 
 }  // namespace cnnsns

@@ -85,6 +85,10 @@ void launch_locate3(const cnnsns_mesh3_s&, int64_t, const double*, const int32_t
 
 size_t cnn3_workspace_bytes(int32_t) { return 0; }
 
+void launch_interp3(const cnnsns_mesh3_s&, int64_t, const double*, const int32_t*, const double*, double*, hipStream_t)
+{
+}
+
 void run_predict3(cnnsns_mesh3_s&, const float*, const cnnsns_cnn&, float*, hipStream_t) {}
 
 void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t*, const double* origin,

@@ -55,7 +55,7 @@ def test_given_start_bitwise(C, oracle_mod, wl, name):
     w = wl.build_3d(name)
     print(f"[locate3d] {name}: {w.n_tet} tetrahedra, {w.n_points} points, G={w.G}", flush=True)
     mesh = C.Mesh3D(w.xyz, w.tet, overlay_side=w.G)
-    assert mesh.n_tet == w.n_tet and mesh.G == w.G and mesh.device_bytes == 128 * w.n_tet + 4 * w.G ** 3
+    assert mesh.n_tet == w.n_tet and mesh.G == w.G and mesh.device_bytes == (128 + 16) * w.n_tet + 4 * w.G ** 3
     tp, nbr = oracle_mod.prepare_mesh3(w.xyz, w.tet)
     h, it, st = _np(*C.locate3d(mesh, _dev(w.xp), start=_dev(w.start)))
     rh, rit, rst = oracle_mod.sns3(w.xyz, tp, nbr, w.xp, w.start)
