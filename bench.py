@@ -177,6 +177,23 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
     l3_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
     it_c, st_c, host_c = iters.cpu().numpy(), status.cpu().numpy(), host.cpu().numpy()
     log(f"3D CNN-SNS: predict {p3_ms.mean():.3f} ms, locate {l3_ms.mean():.3f} ms, mean I_t {it_c.mean():.2f}")
+    # the step after location: the velocity at x_p, P1-interpolated in the host tetrahedron
+    fu, fv, fw = w.flow(w.xyz[:, 0], w.xyz[:, 1], w.xyz[:, 2])
+    nodal = torch.from_numpy(np.ascontiguousarray(np.stack([fu, fv, fw], axis=1))).to(dev)
+    u_xp = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        C.interpolate3d(mesh, xp, host, nodal, out=u_xp)
+    torch.cuda.synchronize()
+    ei = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for k in range(K):
+        ei[k][0].record(stream)
+        C.interpolate3d(mesh, xp, host, nodal, out=u_xp)
+        ei[k][1].record(stream)
+    torch.cuda.synchronize()
+    i3_ms = np.array([a.elapsed_time(b) for a, b in ei])
+    # x_p 24 + host 4 + vertices 96 and orientation 4 + node ids 16 + four nodal values 96 + result 24
+    b_i3 = n * (24 + 4 + 96 + 4 + 16 + 96 + 24)
+    g_i3 = b_i3 / (i3_ms.mean() / 1e3) / 1e9
     cnn3_flops = 2.0 * CNN3_MACS_PER_CELL * w.G ** 3
     cnn3_tf = cnn3_flops / (p3_ms.mean() / 1e3) / 1e12
     log(f"3D plain SNS: {plain_ms.mean():.3f} ms, mean I_t {it_p.mean():.2f}; "
@@ -215,6 +232,11 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
                                      "traffic": traffic_for("cnn3_forward_f32", name),
                                      "algorithmic_per_launch": f"{cnn3_flops:.4e} FLOP (2 x 60480 MAC x G^3, "
                                                                f"G={w.G})"}},
+        "interp_leg": {"kernel": "k3_interp (P1 velocity at x_p in its host tetrahedron)",
+                       "ms": round(float(i3_ms.mean()), 4), "points_per_s": round(n / (i3_ms.mean() / 1e3), 1),
+                       "bound": "hbm", "achieved": round(g_i3, 1), "unit": "GB/s",
+                       "frac": round(g_i3 / PEAK["hbm_GBps"], 4), "traffic": traffic_for("k3_interp", name),
+                       "algorithmic_per_launch": f"{b_i3:.4e} B (264 B x n)"},
         "roofline": {"kernel": "k3_locate (plain SNS leg)", "bound": "hbm", "achieved": round(g_plain, 1),
                      "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": round(g_plain / PEAK["hbm_GBps"], 4),
                      "frac_of_measured_copy": round(g_plain / copy_gbps, 4),
