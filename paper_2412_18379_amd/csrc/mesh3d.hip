@@ -218,18 +218,11 @@ __device__ __forceinline__ int32_t cell3(double x, int32_t G)
     return (int32_t)fmin(fmax(floor(x * (double)G), 0.0), (double)(G - 1));
 }
 
-// The overlay cells whose centres a tetrahedron contains: its bounding box grown by one cell,
-// each centre tested with the walk's numerators; the smallest containing id wins.
-__global__ void k3_lookup_raster(int64_t n_tet, const TetRec* __restrict__ rec, int32_t G, int32_t* lookup)
+// The overlay cells a tetrahedron's centres can lie in: its bounding box grown by one cell,
+// clipped to the grid (lo > hi on an axis when it misses the grid).
+__device__ __forceinline__ void tet_box(const double3* v, int32_t G, int32_t (&lo)[3], int32_t (&hi)[3])
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tet) return;
-    double3 v[4];
-    int32_t nb[4], o;
-    uint32_t pos;
-    load_tet(rec, t, v, nb, o, pos);
     const double g = (double)G;
-    int32_t lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
         double mn = d == 0 ? v[0].x : (d == 1 ? v[0].y : v[0].z), mx = mn;
         for (int k = 1; k < 4; ++k) {
@@ -242,14 +235,67 @@ __global__ void k3_lookup_raster(int64_t n_tet, const TetRec* __restrict__ rec, 
         lo[d] = f0 > g - 1.0 ? G : (int32_t)f0;
         hi[d] = f1 < 0.0 ? -1 : (int32_t)f1;
     }
+}
+
+__device__ __forceinline__ bool holds_centre3(const double3* v, int32_t o, int32_t cx, int32_t cy, int32_t cz,
+                                              int32_t G)
+{
+    const double g = (double)G;
+    const double3 p{ ((double)cx + 0.5) / g, ((double)cy + 0.5) / g, ((double)cz + 0.5) / g };
+    double sn[4];
+    numerators(p, v, o, sn);
+    return sn[0] >= 0.0 && sn[1] >= 0.0 && sn[2] >= 0.0 && sn[3] >= 0.0;
+}
+
+constexpr int64_t kBigBox = 512;  // cells; larger boxes go to the block-parallel pass
+
+// The overlay cells whose centres a tetrahedron contains, one tetrahedron per thread over its
+// cell box (the walk's numerators at each centre); the smallest containing id wins.
+// Tetrahedra with large boxes (a coarse mesh under a fine overlay) are listed for
+// k3_lookup_raster_big instead.
+__global__ void k3_lookup_raster(int64_t n_tet, const TetRec* __restrict__ rec, int32_t G, int32_t* lookup,
+                                 int32_t* big, unsigned* n_big)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tet) return;
+    double3 v[4];
+    int32_t nb[4], o;
+    uint32_t pos;
+    load_tet(rec, t, v, nb, o, pos);
+    int32_t lo[3], hi[3];
+    tet_box(v, G, lo, hi);
+    if (hi[0] < lo[0] || hi[1] < lo[1] || hi[2] < lo[2]) return;
+    if ((int64_t)(hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1) > kBigBox) {
+        big[atomicAdd(n_big, 1u)] = (int32_t)t;
+        return;
+    }
     for (int32_t cz = lo[2]; cz <= hi[2]; ++cz)
         for (int32_t cy = lo[1]; cy <= hi[1]; ++cy)
-            for (int32_t cx = lo[0]; cx <= hi[0]; ++cx) {
-                const double3 p{ ((double)cx + 0.5) / g, ((double)cy + 0.5) / g, ((double)cz + 0.5) / g };
-                double sn[4];
-                numerators(p, v, o, sn);
-                if (sn[0] >= 0.0 && sn[1] >= 0.0 && sn[2] >= 0.0 && sn[3] >= 0.0) atomicMin(&lookup[((int64_t)cz * G + cy) * G + cx], (int32_t)t);
-            }
+            for (int32_t cx = lo[0]; cx <= hi[0]; ++cx)
+                if (holds_centre3(v, o, cx, cy, cz, G))
+                    atomicMin(&lookup[((int64_t)cz * G + cy) * G + cx], (int32_t)t);
+}
+
+// Listed tetrahedra: blockIdx.y picks the tetrahedron, all blocks along x and their threads
+// stride over its cells.
+__global__ void k3_lookup_raster_big(const TetRec* __restrict__ rec, const int32_t* __restrict__ big, unsigned n_big,
+                                     int32_t G, int32_t* lookup)
+{
+    for (unsigned k = blockIdx.y; k < n_big; k += gridDim.y) {
+        const int32_t t = big[k];
+        double3 v[4];
+        int32_t nb[4], o;
+        uint32_t pos;
+        load_tet(rec, t, v, nb, o, pos);
+        int32_t lo[3], hi[3];
+        tet_box(v, G, lo, hi);
+        const int64_t wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, n = wx * wy * (hi[2] - lo[2] + 1);
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+            const int32_t cx = lo[0] + (int32_t)(c % wx), cy = lo[1] + (int32_t)((c / wx) % wy),
+                          cz = lo[2] + (int32_t)(c / (wx * wy));
+            if (holds_centre3(v, o, cx, cy, cz, G)) atomicMin(&lookup[((int64_t)cz * G + cy) * G + cx], t);
+        }
+    }
 }
 
 __device__ __forceinline__ double clamp01(double v)
@@ -441,7 +487,17 @@ cnnsns_mesh3 build_mesh3(const double* xyz, int64_t n_nodes, const int32_t* tet,
                                                                   d_nbr.p, d_err.p);
         k3_pack<<<grid_for(n_tet), kBlock, 0, stream>>>(n_tet, d_xyz.p, d_tet.p, d_nbr.p, d_rec.p, d_ids.p);
         k3_fill_i32<<<grid_for(ncell), kBlock, 0, stream>>>(ncell, d_lookup.p, INT_MAX);
-        k3_lookup_raster<<<grid_for(n_tet), kBlock, 0, stream>>>(n_tet, d_rec.p, G, d_lookup.p);
+        DevBuf3<int32_t> d_big((size_t)n_tet);
+        DevBuf3<unsigned> d_nbig(1);
+        hip_check(hipMemsetAsync(d_nbig.p, 0, sizeof(unsigned), stream), "memset");
+        k3_lookup_raster<<<grid_for(n_tet), kBlock, 0, stream>>>(n_tet, d_rec.p, G, d_lookup.p, d_big.p, d_nbig.p);
+        unsigned n_big = 0;
+        hip_check(hipMemcpyAsync(&n_big, d_nbig.p, sizeof(unsigned), hipMemcpyDeviceToHost, stream), "copy n_big");
+        hip_check(hipStreamSynchronize(stream), "3D lookup raster");
+        if (n_big > 0) {
+            const dim3 grid(64, n_big < 4096u ? n_big : 4096u);
+            k3_lookup_raster_big<<<grid, kBlock, 0, stream>>>(d_rec.p, d_big.p, n_big, G, d_lookup.p);
+        }
         k3_lookup_finish<<<grid_for(ncell), kBlock, 0, stream>>>(ncell, d_lookup.p);
         hip_check(hipGetLastError(), "3D mesh build kernels");
         int err = 0;

@@ -177,3 +177,15 @@ def test_full_size_sampled(C, oracle_mod, wl):
     cen = (cells + 0.5) / w.G
     hc, itc, stc = _np(*C.locate3d(mesh, _dev(cen), max_iter=1))
     assert np.array_equal(hc, oracle_mod.brute_force3(w.xyz, tp, cen)) and np.all(stc == C.FOUND)
+
+
+def test_coarse_mesh_under_a_fine_overlay(C, oracle_mod, wl):
+    """Tetrahedra whose cell boxes are large (48 tetrahedra under a 64^3 overlay) take the
+    block-parallel raster; the whole table still equals the oracle's."""
+    xyz, tet = wl.kuhn_mesh(3, seed=5, jitter=0.1)
+    G = 64
+    mesh = C.Mesh3D(xyz, tet, overlay_side=G)
+    tp, _ = oracle_mod.prepare_mesh3(xyz, tet)
+    lk = oracle_mod.lookup3(xyz, tp, G)
+    h, it, st = _np(*C.locate3d(mesh, _dev(_centres(G)), max_iter=1))
+    assert np.array_equal(h, lk.ravel()) and np.all(st == C.FOUND)
