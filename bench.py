@@ -177,6 +177,25 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
     l3_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
     it_c, st_c, host_c = iters.cpu().numpy(), status.cpu().numpy(), host.cpu().numpy()
     log(f"3D CNN-SNS: predict {p3_ms.mean():.3f} ms, locate {l3_ms.mean():.3f} ms, mean I_t {it_c.mean():.2f}")
+    cnn3_flops = 2.0 * CNN3_MACS_PER_CELL * w.G ** 3
+    cnn3_tf = cnn3_flops / (p3_ms.mean() / 1e3) / 1e12
+    # the same step with the BF16 3D CNN (precision variant)
+    for _ in range(warmup):
+        C.predict3d(mesh, vel, wts, "bf16", disp=disp)
+    torch.cuda.synchronize()
+    eb = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    for k in range(K):
+        eb[k][0].record(stream)
+        C.predict3d(mesh, vel, wts, "bf16", disp=disp)
+        eb[k][1].record(stream)
+        C.locate3d(mesh, xp, start=start, origin=origin, disp=disp, host=host, iters=iters, status=status)
+        eb[k][2].record(stream)
+    torch.cuda.synchronize()
+    pb_ms = np.array([a.elapsed_time(b) for a, b, _ in eb])
+    lb_ms = np.array([b.elapsed_time(c) for _, b, c in eb])
+    it_b = iters.cpu().numpy()
+    log(f"3D CNN-SNS, BF16 CNN: predict {pb_ms.mean():.3f} ms, locate {lb_ms.mean():.3f} ms, mean I_t {it_b.mean():.2f}")
+    cnn3_tf_b = cnn3_flops / (pb_ms.mean() / 1e3) / 1e12
     # the step after location: the velocity at x_p, P1-interpolated in the host tetrahedron
     fu, fv, fw = w.flow(w.xyz[:, 0], w.xyz[:, 1], w.xyz[:, 2])
     nodal = torch.from_numpy(np.ascontiguousarray(np.stack([fu, fv, fw], axis=1))).to(dev)
@@ -194,8 +213,6 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
     # x_p 24 + host 4 + vertices 96 and orientation 4 + node ids 16 + four nodal values 96 + result 24
     b_i3 = n * (24 + 4 + 96 + 4 + 16 + 96 + 24)
     g_i3 = b_i3 / (i3_ms.mean() / 1e3) / 1e9
-    cnn3_flops = 2.0 * CNN3_MACS_PER_CELL * w.G ** 3
-    cnn3_tf = cnn3_flops / (p3_ms.mean() / 1e3) / 1e12
     log(f"3D plain SNS: {plain_ms.mean():.3f} ms, mean I_t {it_p.mean():.2f}; "
         f"3D lookup start: {asg_ms.mean():.3f} ms, mean I_t {it_a.mean():.2f}")
     # one 128-byte element record per iteration; per point x_p 24 B, the start (or lookup entry)
@@ -232,6 +249,13 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
                                      "traffic": traffic_for("cnn3_forward_f32", name),
                                      "algorithmic_per_launch": f"{cnn3_flops:.4e} FLOP (2 x 60480 MAC x G^3, "
                                                                f"G={w.G})"}},
+        "cnn_sns_bf16": {"predict_ms": round(float(pb_ms.mean()), 4), "locate_ms": round(float(lb_ms.mean()), 4),
+                         "step_ms": round(float((pb_ms + lb_ms).mean()), 4),
+                         "speedup_vs_plain_sns": round(float(plain_ms.mean() / (pb_ms + lb_ms).mean()), 4),
+                         "mean_path_length": round(float(it_b.mean()), 3),
+                         "cnn_roofline": {"achieved": round(cnn3_tf_b, 3), "peak": PEAK["bf16_TFLOPs"],
+                                          "unit": "TFLOP/s", "frac": round(cnn3_tf_b / PEAK["bf16_TFLOPs"], 4),
+                                          "traffic": traffic_for("cnn3_forward_bf16", name)}},
         "interp_leg": {"kernel": "k3_interp (P1 velocity at x_p in its host tetrahedron)",
                        "ms": round(float(i3_ms.mean()), 4), "points_per_s": round(n / (i3_ms.mean() / 1e3), 1),
                        "bound": "hbm", "achieved": round(g_i3, 1), "unit": "GB/s",

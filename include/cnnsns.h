@@ -227,12 +227,15 @@ int cnnsns_destroy_mesh3d(cnnsns_mesh3 m);
  *   w     weights as in cnnsns_predict, with 3 x 3 x 3 kernels: w[0] FP32
  *         [32][3][3][3][3], w[1], w[2] [32][32][3][3][3], w[3] [3][32][3][3][3]
  *         (OIDHW); b[0..2] [32], b[3] [3]; fp8_scale unused.
- *   precision  CNNSNS_F32 (the only one implemented in 3D).
+ *   precision  CNNSNS_F32, or CNNSNS_BF16: layers 2 and 3 with BF16 weights
+ *              and activations (rounded to nearest even) on the matrix cores,
+ *              FP32 accumulation; layer 1 writes BF16 activations and layer 4
+ *              reads them, both computing in FP32.  CNNSNS_FP8E4M3: EINVAL.
  *   disp  FP32 [3][G][G][G] out: the predicted displacement per cell.
  * Uses a workspace of the mesh (2 G^3 x 32 FP32 activations plus 216 KiB),
  * allocated on the first call; calls on one mesh must not overlap.
  * Asynchronous on `stream`.  Errors: EINVAL (null argument, precision not
- * CNNSNS_F32), ENOMEM (workspace), EHIP.
+ * CNNSNS_F32 or CNNSNS_BF16), ENOMEM (workspace), EHIP.
  */
 int cnnsns_predict3d(cnnsns_mesh3 m, const float* vel, const cnnsns_cnn* w, int32_t precision, float* disp,
                      void* stream);

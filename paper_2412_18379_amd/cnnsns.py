@@ -243,16 +243,17 @@ class Weights3D:
             self.struct.b[l] = self.b[l].data_ptr()
 
 
-def predict3d(mesh: Mesh3D, vel: torch.Tensor, weights: Weights3D, disp: torch.Tensor = None,
+def predict3d(mesh: Mesh3D, vel: torch.Tensor, weights: Weights3D, precision="f32", disp: torch.Tensor = None,
               stream=None) -> torch.Tensor:
-    """The 3D displacement CNN on the mesh's G^3 overlay (cnnsns_predict3d, FP32)."""
+    """The 3D displacement CNN on the mesh's G^3 overlay (cnnsns_predict3d, FP32 or BF16)."""
     G = mesh.G
     _need(vel, torch.float32, (3, G, G, G), "vel")
     if disp is None:
         disp = torch.empty((3, G, G, G), dtype=torch.float32, device=vel.device)
     _need(disp, torch.float32, (3, G, G, G), "disp")
-    _check(lib().cnnsns_predict3d(mesh.handle, _ptr(vel), ctypes.byref(weights.struct), PRECISIONS["f32"],
-                                  _ptr(disp), _stream(stream)))
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().cnnsns_predict3d(mesh.handle, _ptr(vel), ctypes.byref(weights.struct), p, _ptr(disp),
+                                  _stream(stream)))
     return disp
 
 

@@ -161,9 +161,10 @@ int cnnsns_predict3d(cnnsns_mesh3 m, const float* vel, const cnnsns_cnn* w, int3
         if (!m || !vel || !w || !disp) fail(CNNSNS_EINVAL, "predict3d: NULL argument");
         for (int l = 0; l < 4; ++l)
             if (!w->w[l] || !w->b[l]) fail(CNNSNS_EINVAL, "predict3d: NULL weight or bias pointer");
-        if (precision != CNNSNS_F32) fail(CNNSNS_EINVAL, "predict3d: only CNNSNS_F32 is implemented in 3D");
+        if (precision != CNNSNS_F32 && precision != CNNSNS_BF16)
+            fail(CNNSNS_EINVAL, "predict3d: CNNSNS_F32 and CNNSNS_BF16 are implemented in 3D");
         DeviceScope ds(m->device);
-        run_predict3(*m, vel, *w, disp, static_cast<hipStream_t>(stream));
+        run_predict3(*m, vel, *w, precision, disp, static_cast<hipStream_t>(stream));
     });
 }
 

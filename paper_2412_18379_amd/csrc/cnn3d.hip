@@ -29,11 +29,16 @@ namespace cnnsns {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v8f __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16;
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int C = 32;             // hidden channels
 constexpr int CIO = 3;            // velocity / displacement components
 constexpr int TAPS = 27;
 constexpr int NWT = TAPS * 4 * 64 * 4;  // operand-ordered weights of one 32 -> 32 layer (floats)
+constexpr int NWB = TAPS * 2 * 64;      // the same in BF16 (bf16x8 entries)
 constexpr int kBlock = 256;       // vector-ALU layers
 constexpr int kWaves32 = 8;       // matrix layers: waves per block (168 registers each)
 constexpr int kWaves4 = 16;       // layer 4: waves per block
@@ -49,10 +54,12 @@ __global__ void k3c_wprep(const float* __restrict__ w, float* __restrict__ wt)
     wt[k] = w[(o * C + ci) * TAPS + tap];
 }
 
-// Layer 1: 3 -> 32 with ReLU, one cell per lane; weights in LDS as [cin][tap][32].
+// Layer 1: 3 -> 32 with ReLU, one cell per lane; weights in LDS as [cin][tap][32].  The output
+// activations are FP32, or BF16 rounded to nearest even for the BF16 pass.
+template <class T>
 __global__ __launch_bounds__(kBlock) void k3c_conv1(int32_t G, const float* __restrict__ vel,
                                                      const float* __restrict__ w, const float* __restrict__ b,
-                                                     float* __restrict__ out)
+                                                     T* __restrict__ out)
 {
     __shared__ float s_w[CIO * TAPS * C];
     __shared__ float s_b[C];
@@ -86,11 +93,22 @@ __global__ __launch_bounds__(kBlock) void k3c_conv1(int32_t G, const float* __re
             }
         }
     }
-    v4f* dst = reinterpret_cast<v4f*>(out + v * C);
+    if constexpr (sizeof(T) == 4) {
+        v4f* dst = reinterpret_cast<v4f*>(out + v * C);
 #pragma unroll
-    for (int q = 0; q < C / 4; ++q)
-        dst[q] = v4f{ fmaxf(acc[4 * q], 0.f), fmaxf(acc[4 * q + 1], 0.f), fmaxf(acc[4 * q + 2], 0.f),
-                      fmaxf(acc[4 * q + 3], 0.f) };
+        for (int q = 0; q < C / 4; ++q)
+            dst[q] = v4f{ fmaxf(acc[4 * q], 0.f), fmaxf(acc[4 * q + 1], 0.f), fmaxf(acc[4 * q + 2], 0.f),
+                          fmaxf(acc[4 * q + 3], 0.f) };
+    } else {
+        bf16x8* dst = reinterpret_cast<bf16x8*>(out + v * C);
+#pragma unroll
+        for (int q = 0; q < C / 8; ++q) {
+            v8f r;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) r[j] = fmaxf(acc[8 * q + j], 0.f);
+            dst[q] = __builtin_convertvector(r, bf16x8);
+        }
+    }
 }
 
 // The work items (64 cells of an x row) of a persistent block: the blocks of one XCD (block id
@@ -195,7 +213,95 @@ __global__ __launch_bounds__(kWaves32 * 64) void k3c_conv32(int32_t G, const flo
     }
 }
 
-__device__ __forceinline__ void conv4_item(int32_t G, const float* __restrict__ in, const v4f* s_w, int segs,
+// BF16 operand-ordered weights: wb[(tap * 2 + nb) * 64 + l] holds, as 8 BF16 (rounded to
+// nearest even), W[16 nb + l%16][8 (l/16) + j][tap] for j = 0..7: the A operand of
+// v_mfma_f32_16x16x32_bf16 (row = output channel, k = input channel 8 (l/16) + j).
+__global__ void k3c_wprep_bf16(const float* __restrict__ w, bf16x8* __restrict__ wb)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NWB) return;
+    const int l = k & 63, nb = (k >> 6) & 1, tap = k >> 7;
+    const int o = 16 * nb + (l & 15), c0 = 8 * (l >> 4);
+    v8f v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = w[(o * C + c0 + j) * TAPS + tap];
+    wb[k] = __builtin_convertvector(v, bf16x8);
+}
+
+// Layers 2 and 3 in BF16 (BF16 activations and weights, FP32 accumulation): one
+// v_mfma_f32_16x16x32_bf16 per tap covers all 32 input channels of 16 cells x 16 output
+// channels.  Lane l's B operand is channels 8 (l/16) .. +7 of cell l%16 (one 16-byte load), and
+// it receives output channels 16 nb + 4 (l/16) + r of cell l%16, stored as four BF16 after ReLU.
+// Persistent blocks of 16 wavefronts, the next tap loaded while this tap's 8 instructions run.
+__global__ __launch_bounds__(16 * 64) void k3c_conv32_bf16(int32_t G, const bf16* __restrict__ in,
+                                                          const bf16x8* __restrict__ wb,
+                                                          const float* __restrict__ bias, bf16* __restrict__ out)
+{
+    __shared__ bf16x8 s_w[NWB];
+    for (int k = threadIdx.x; k < NWB; k += 16 * 64) s_w[k] = wb[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int segs = (G + kSeg - 1) / kSeg;
+    int64_t i0, i1;
+    item_range((int64_t)G * G * segs, i0, i1);
+    const v4f bv0 = *reinterpret_cast<const v4f*>(bias + 4 * grp);
+    const v4f bv1 = *reinterpret_cast<const v4f*>(bias + 16 + 4 * grp);
+    for (int64_t item = i0 + wave; item < i1; item += 16) {
+        const int seg = (int)(item % segs);
+        const int64_t row = item / segs;
+        const int y = (int)(row % G), z = (int)(row / G);
+        const int x0 = seg * kSeg;
+        v4f acc[4][2];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            acc[mb][0] = bv0;
+            acc[mb][1] = bv1;
+        }
+        auto load = [&](int t, bf16x8 (&bo)[4]) {
+            const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, dx = t % 3 - 1;
+            const bool ok = Z >= 0 && Z < G && Y >= 0 && Y < G;
+            const bf16* src = in + ((int64_t)(ok ? Z : 0) * G + (ok ? Y : 0)) * G * C + 8 * grp;
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) {
+                const int X = x0 + 16 * mb + col + dx;
+                if (ok && X >= 0 && X < G)
+                    bo[mb] = *reinterpret_cast<const bf16x8*>(src + (int64_t)X * C);
+                else
+                    bo[mb] = bf16x8{ 0, 0, 0, 0, 0, 0, 0, 0 };
+            }
+        };
+        bf16x8 bop[4], bnx[4];
+        load(0, bop);
+        for (int t = 0; t < TAPS; ++t) {
+            if (t + 1 < TAPS) load(t + 1, bnx);
+            const bf16x8 a0 = s_w[(t * 2) * 64 + lane], a1 = s_w[(t * 2 + 1) * 64 + lane];
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) {
+                acc[mb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bop[mb], acc[mb][0], 0, 0, 0);
+                acc[mb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bop[mb], acc[mb][1], 0, 0, 0);
+            }
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) bop[mb] = bnx[mb];
+        }
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            const int X = x0 + 16 * mb + col;
+            if (X >= G) continue;
+            bf16* dst = out + (row * G + X) * C + 4 * grp;
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const v4f a = acc[mb][nb];
+                const v4f r{ fmaxf(a.x, 0.f), fmaxf(a.y, 0.f), fmaxf(a.z, 0.f), fmaxf(a.w, 0.f) };
+                *reinterpret_cast<bf16x4*>(dst + 16 * nb) = __builtin_convertvector(r, bf16x4);
+            }
+        }
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void conv4_item(int32_t G, const T* __restrict__ in, const v4f* s_w, int segs,
                                            int64_t item, int col, int grp, int64_t n, float bias,
                                            float* __restrict__ disp)
 {
@@ -211,7 +317,7 @@ __device__ __forceinline__ void conv4_item(int32_t G, const float* __restrict__ 
     for (int t = 0; t < TAPS; ++t) {
         const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, dx = t % 3 - 1;
         if (Z < 0 || Z >= G || Y < 0 || Y >= G) continue;
-        const float* src = in + ((int64_t)Z * G + Y) * G * C + 8 * grp;
+        const T* src = in + ((int64_t)Z * G + Y) * G * C + 8 * grp;
         const v4f* wq = s_w + (t * 4 + grp) * 6;  // 24 floats: [channel][output]
         const v4f w0 = wq[0], w1 = wq[1], w2 = wq[2], w3 = wq[3], w4 = wq[4], w5 = wq[5];
         const float wv[24] = { w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w, w2.x, w2.y, w2.z, w2.w,
@@ -220,9 +326,17 @@ __device__ __forceinline__ void conv4_item(int32_t G, const float* __restrict__ 
         for (int mb = 0; mb < 4; ++mb) {
             const int X = x0 + 16 * mb + col + dx;
             if (X < 0 || X >= G) continue;
-            const v4f* p = reinterpret_cast<const v4f*>(src + (int64_t)X * C);
-            const v4f a0 = p[0], a1 = p[1];
-            const float av[8] = { a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w };
+            float av[8];
+            if constexpr (sizeof(T) == 4) {
+                const v4f* p = reinterpret_cast<const v4f*>(src + (int64_t)X * C);
+                const v4f a0 = p[0], a1 = p[1];
+                av[0] = a0.x; av[1] = a0.y; av[2] = a0.z; av[3] = a0.w;
+                av[4] = a1.x; av[5] = a1.y; av[6] = a1.z; av[7] = a1.w;
+            } else {
+                const v8f a = __builtin_convertvector(*reinterpret_cast<const bf16x8*>(src + (int64_t)X * C), v8f);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) av[j] = a[j];
+            }
 #pragma unroll
             for (int c = 0; c < 8; ++c)
 #pragma unroll
@@ -257,7 +371,8 @@ __device__ __forceinline__ void conv4_item(int32_t G, const float* __restrict__ 
 // cell l%16 of each 16-cell block (four lanes cover a cell's 128-byte line), forms the partial
 // sums of its 8 channels for the 3 outputs, and the four lane groups' sums are added across lanes.
 // Weights in LDS as [tap][lane group][8 channels][3].
-__global__ __launch_bounds__(kWaves4 * 64) void k3c_conv4(int32_t G, const float* __restrict__ in,
+template <class T>
+__global__ __launch_bounds__(kWaves4 * 64) void k3c_conv4(int32_t G, const T* __restrict__ in,
                                                            const float* __restrict__ w, const float* __restrict__ b,
                                                            float* __restrict__ disp)
 {
@@ -276,7 +391,7 @@ __global__ __launch_bounds__(kWaves4 * 64) void k3c_conv4(int32_t G, const float
     int64_t i0, i1;
     item_range((int64_t)G * G * segs, i0, i1);
     for (int64_t item = i0 + (threadIdx.x >> 6); item < i1; item += kWaves4)
-        conv4_item(G, in, s_w, segs, item, col, grp, n, bias, disp);
+        conv4_item<T>(G, in, s_w, segs, item, col, grp, n, bias, disp);
 }
 
 unsigned blocks_for(int64_t n)
@@ -292,7 +407,8 @@ size_t cnn3_workspace_bytes(int32_t G)
     return 2 * cells * C * sizeof(float) + 2 * (size_t)NWT * sizeof(float);
 }
 
-void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, float* disp, hipStream_t stream)
+void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
+                  hipStream_t stream)
 {
     const size_t need = cnn3_workspace_bytes(m.G);
     {
@@ -314,17 +430,30 @@ void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, floa
     }
     const int32_t G = m.G;
     const int64_t cells = (int64_t)G * G * G;
+    const unsigned grid = cnn_persistent_grid();
     float* act0 = static_cast<float*>(m.cnn_ws);
     float* act1 = act0 + cells * C;
     float* wt2 = act1 + cells * C;
     float* wt3 = wt2 + NWT;
-    k3c_wprep<<<(NWT + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[1], wt2);
-    k3c_wprep<<<(NWT + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[2], wt3);
-    k3c_conv1<<<blocks_for(cells), kBlock, 0, stream>>>(G, vel, w.w[0], w.b[0], act0);
-    const unsigned grid = cnn_persistent_grid();
-    k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act0, wt2, w.b[1], act1);
-    k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act1, wt3, w.b[2], act0);
-    k3c_conv4<<<grid, kWaves4 * 64, 0, stream>>>(G, act0, w.w[3], w.b[3], disp);
+    if (precision == CNNSNS_BF16) {
+        bf16* b0 = reinterpret_cast<bf16*>(act0);
+        bf16* b1 = reinterpret_cast<bf16*>(act1);
+        bf16x8* wb2 = reinterpret_cast<bf16x8*>(wt2);
+        bf16x8* wb3 = reinterpret_cast<bf16x8*>(wt3);
+        k3c_wprep_bf16<<<(NWB + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[1], wb2);
+        k3c_wprep_bf16<<<(NWB + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[2], wb3);
+        k3c_conv1<bf16><<<blocks_for(cells), kBlock, 0, stream>>>(G, vel, w.w[0], w.b[0], b0);
+        k3c_conv32_bf16<<<grid, 16 * 64, 0, stream>>>(G, b0, wb2, w.b[1], b1);
+        k3c_conv32_bf16<<<grid, 16 * 64, 0, stream>>>(G, b1, wb3, w.b[2], b0);
+        k3c_conv4<bf16><<<grid, kWaves4 * 64, 0, stream>>>(G, b0, w.w[3], w.b[3], disp);
+    } else {
+        k3c_wprep<<<(NWT + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[1], wt2);
+        k3c_wprep<<<(NWT + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[2], wt3);
+        k3c_conv1<float><<<blocks_for(cells), kBlock, 0, stream>>>(G, vel, w.w[0], w.b[0], act0);
+        k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act0, wt2, w.b[1], act1);
+        k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act1, wt3, w.b[2], act0);
+        k3c_conv4<float><<<grid, kWaves4 * 64, 0, stream>>>(G, act0, w.w[3], w.b[3], disp);
+    }
     hip_check(hipGetLastError(), "predict3d launch");
 }
 

@@ -91,7 +91,8 @@ void launch_interp3(const cnnsns_mesh3_s& m, int64_t n, const double* xp, const 
                     double* out, hipStream_t stream);
 // cnn3d.hip
 size_t cnn3_workspace_bytes(int32_t G);
-void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, float* disp, hipStream_t stream);
+void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
+                  hipStream_t stream);
 
 // mesh.hip
 cnnsns_mesh build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, int64_t n_tri, int32_t G,

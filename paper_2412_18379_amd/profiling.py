@@ -39,6 +39,7 @@ SOURCES = {
     "k3_locate_cnn": ("mesh3d.hip",),
     "k3_interp": ("mesh3d.hip",),
     "cnn3_forward_f32": ("cnn3d.hip",),
+    "cnn3_forward_bf16": ("cnn3d.hip",),
 }
 
 

@@ -4,8 +4,10 @@ the FP64 CPU oracle, through the C ABI.
 
 Bars: the FP32 forward pass within the FP32 tolerance per output channel c,
 |y - y_ref| <= 1e-5 |y_ref| + 1e-5 max_c |y_ref| (the 2D bar); a constructed
-pass-through net gives -dt u exactly (one rounding of one product); starts, hosts,
-path lengths and statuses of the walk bit for bit, given the same displacement grid.
+pass-through net gives -dt u exactly (one rounding of one product); the BF16 pass within
+the BF16 bar of the 2D path (every element within 3% of its channel's largest magnitude,
+the mean within 0.5%); starts, hosts, path lengths and statuses of the walk bit for bit,
+given the same displacement grid.
 """
 import numpy as np
 import pytest
@@ -136,7 +138,7 @@ def test_fallback_and_errors(C, oracle_mod, wl):
     W = C.Weights3D(ws, bs)
     vel = torch.zeros((3, G, G, G), dtype=torch.float32, device="cuda")
     disp = torch.empty_like(vel)
-    assert lib.cnnsns_predict3d(mesh.handle, vel.data_ptr(), W.struct, C.PRECISIONS["bf16"], disp.data_ptr(),
+    assert lib.cnnsns_predict3d(mesh.handle, vel.data_ptr(), W.struct, C.PRECISIONS["fp8"], disp.data_ptr(),
                                 None) == C.EINVAL
     assert lib.cnnsns_predict3d(None, vel.data_ptr(), W.struct, 0, disp.data_ptr(), None) == C.EINVAL
     assert lib.cnnsns_predict3d(mesh.handle, None, W.struct, 0, disp.data_ptr(), None) == C.EINVAL
@@ -146,3 +148,48 @@ def test_fallback_and_errors(C, oracle_mod, wl):
                                None, None, None) == C.EINVAL  # disp without origin
     with pytest.raises(ValueError):
         C.Weights3D([x[:, :, :, :, :2] for x in ws], bs)
+
+
+def _within_bf16_bar(got, ref):
+    """The BF16 bar (no tolerance is stated for the lower precision): per output channel, every
+    element within 3% of the channel's largest magnitude and the mean error within 0.5%."""
+    scale = np.abs(ref).reshape(ref.shape[0], -1).max(axis=1)
+    err = np.abs(got - ref).reshape(ref.shape[0], -1)
+    return float((err.max(axis=1) / scale).max()), float((err.mean(axis=1) / scale).max())
+
+
+@pytest.mark.parametrize("G", [5, 17, 33])
+def test_bf16_forward_full_grid(C, oracle_mod, G):
+    rng = np.random.default_rng(200 + G)
+    vel = rng.standard_normal((3, G, G, G)).astype(np.float32)
+    ws, bs = he_net(G + 1)
+    mesh = _cube_mesh(C, G)
+    got = C.predict3d(mesh, _dev(vel), C.Weights3D(ws, bs), "bf16").cpu().numpy().astype(np.float64)
+    worst, mean = _within_bf16_bar(got, oracle_mod.cnn3_forward(vel, ws, bs))
+    print(f"[cnn3d bf16] G={G}: worst {worst:.4f}, mean {mean:.5f} of the channel maximum", flush=True)
+    assert worst <= 0.03 and mean <= 0.005
+
+
+def test_bf16_forward_windows_and_walk(C, oracle_mod, wl):
+    """The 623K-tetrahedron mesh's overlay (G = 128): windows against the oracle, and the CNN-SNS
+    walk from the BF16 displacement bit for bit against the oracle's walk from the same grid."""
+    w = wl.build_3d("t2")
+    G = w.G
+    vel = wl.overlay_velocity_3d(w.flow, G)
+    ws, bs = he_net(11)
+    mesh = C.Mesh3D(w.xyz, w.tet, overlay_side=G)
+    got = C.predict3d(mesh, _dev(vel), C.Weights3D(ws, bs), "bf16").cpu().numpy().astype(np.float64)
+    for o, s in [((0, 0, 0), (1, G, G)), ((G // 2, 5, 0), (2, 3, G))]:
+        ref = oracle_mod.cnn3_window(vel, ws, bs, o, s)
+        worst, mean = _within_bf16_bar(got[:, o[0]:o[0] + s[0], o[1]:o[1] + s[1], o[2]:o[2] + s[2]], ref)
+        assert worst <= 0.03 and mean <= 0.005
+    wc, bc = constructed_net(w.dt)
+    disp = C.predict3d(mesh, _dev(vel), C.Weights3D(wc, bc), "bf16")
+    h, it, st = (t.cpu().numpy() for t in C.locate3d(mesh, _dev(w.xp), start=_dev(w.start), origin=_dev(w.xyz),
+                                                       disp=disp))
+    tp, nbr = oracle_mod.prepare_mesh3(w.xyz, w.tet)
+    lk = oracle_mod.lookup3(w.xyz, tp, G)
+    _, rh, rit, rst = oracle_mod.cnnsns3(w.xyz, tp, nbr, lk, w.xyz, w.xp, disp.cpu().numpy().astype(np.float64),
+                                         fallback=w.start)
+    assert np.array_equal(h, rh) and np.array_equal(it, rit) and np.array_equal(st, rst)
+    assert np.all(st == C.FOUND)
