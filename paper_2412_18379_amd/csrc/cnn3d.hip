@@ -14,9 +14,11 @@
 // x row (four 16-cell blocks) for all 32 output channels; the 27 taps' weights
 // sit in LDS in operand order (108 KiB, loaded once per block), the
 // activations come through the caches (a cell's 32 channels are one 128-byte
-// line).  Layers 1 and 4 (3 -> 32, 32 -> 3) are 9 % of the work and run on the
-// vector ALUs: layer 1 one cell per lane, layer 4 four lanes per cell (each with
-// 8 of the 32 input channels, read as the matrix layers read them).
+// line).  Layers 1 and 4 (3 -> 32, 32 -> 3) are 9 % of the work.  Layer 1 runs
+// on the vector ALUs, one cell per lane; layer 4 reads its input as the matrix
+// layers do and runs on the vector ALUs in FP32 (four lanes per cell, 8 of the
+// 32 input channels each) or, in the BF16 pass, on the matrix cores with its
+// 3 outputs padded to 16.
 //
 // Activations between layers: FP32 [G^3][32], cell-major (z, y, x; x fastest),
 // 32 channels per cell.  Input velocity and output displacement: FP32
@@ -274,6 +276,7 @@ __global__ __launch_bounds__(16 * 64) void k3c_conv32_bf16(int32_t G, const bf16
         };
         bf16x8 bop[4], bnx[4];
         load(0, bop);
+#pragma unroll 1
         for (int t = 0; t < TAPS; ++t) {
             if (t + 1 < TAPS) load(t + 1, bnx);
             const bf16x8 a0 = s_w[(t * 2) * 64 + lane], a1 = s_w[(t * 2 + 1) * 64 + lane];
@@ -300,8 +303,83 @@ __global__ __launch_bounds__(16 * 64) void k3c_conv32_bf16(int32_t G, const bf16
     }
 }
 
-template <class T>
-__device__ __forceinline__ void conv4_item(int32_t G, const T* __restrict__ in, const v4f* s_w, int segs,
+// Layer 4 in the BF16 pass on the matrix cores: the 3 output channels padded to one 16-row A
+// block, wb4[tap * 64 + l] = W4[l%16][8 (l/16) + j][tap] as BF16 (zero for rows >= 3), so a tap is
+// one v_mfma_f32_16x16x32_bf16 per 16 cells.  Lanes 0..15 receive output channels 0..3 of
+// their cell, the first three of which are written with the bias added.
+__global__ void k3c_wprep4_bf16(const float* __restrict__ w, bf16x8* __restrict__ wb)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= TAPS * 64) return;
+    const int l = k & 63, tap = k >> 6;
+    const int o = l & 15, c0 = 8 * (l >> 4);
+    v8f v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = o < CIO ? w[(o * C + c0 + j) * TAPS + tap] : 0.f;
+    wb[k] = __builtin_convertvector(v, bf16x8);
+}
+
+__global__ __launch_bounds__(16 * 64) void k3c_conv4_bf16(int32_t G, const bf16* __restrict__ in,
+                                                         const bf16x8* __restrict__ wb, const float* __restrict__ b,
+                                                         float* __restrict__ disp)
+{
+    __shared__ bf16x8 s_w[TAPS * 64];
+    for (int k = threadIdx.x; k < TAPS * 64; k += 16 * 64) s_w[k] = wb[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int segs = (G + kSeg - 1) / kSeg;
+    const int64_t n = (int64_t)G * G * G;
+    const float b0 = b[0], b1 = b[1], b2 = b[2];
+    int64_t i0, i1;
+    item_range((int64_t)G * G * segs, i0, i1);
+    for (int64_t item = i0 + wave; item < i1; item += 16) {
+        const int seg = (int)(item % segs);
+        const int64_t row = item / segs;
+        const int y = (int)(row % G), z = (int)(row / G);
+        const int x0 = seg * kSeg;
+        v4f acc[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) acc[mb] = v4f{ 0.f, 0.f, 0.f, 0.f };
+        auto load = [&](int t, bf16x8 (&bo)[4]) {
+            const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, dx = t % 3 - 1;
+            const bool ok = Z >= 0 && Z < G && Y >= 0 && Y < G;
+            const bf16* src = in + ((int64_t)(ok ? Z : 0) * G + (ok ? Y : 0)) * G * C + 8 * grp;
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) {
+                const int X = x0 + 16 * mb + col + dx;
+                if (ok && X >= 0 && X < G)
+                    bo[mb] = *reinterpret_cast<const bf16x8*>(src + (int64_t)X * C);
+                else
+                    bo[mb] = bf16x8{ 0, 0, 0, 0, 0, 0, 0, 0 };
+            }
+        };
+        bf16x8 bop[4], bnx[4];
+        load(0, bop);
+        for (int t = 0; t < TAPS; ++t) {
+            if (t + 1 < TAPS) load(t + 1, bnx);
+            const bf16x8 a = s_w[t * 64 + lane];
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bop[mb], acc[mb], 0, 0, 0);
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) bop[mb] = bnx[mb];
+        }
+        if (grp == 0) {
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) {
+                const int X = x0 + 16 * mb + col;
+                if (X >= G) continue;
+                const int64_t c = row * G + X;
+                disp[c] = acc[mb].x + b0;
+                disp[n + c] = acc[mb].y + b1;
+                disp[2 * n + c] = acc[mb].z + b2;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void conv4_item(int32_t G, const float* __restrict__ in, const v4f* s_w, int segs,
                                            int64_t item, int col, int grp, int64_t n, float bias,
                                            float* __restrict__ disp)
 {
@@ -317,7 +395,7 @@ __device__ __forceinline__ void conv4_item(int32_t G, const T* __restrict__ in, 
     for (int t = 0; t < TAPS; ++t) {
         const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, dx = t % 3 - 1;
         if (Z < 0 || Z >= G || Y < 0 || Y >= G) continue;
-        const T* src = in + ((int64_t)Z * G + Y) * G * C + 8 * grp;
+        const float* src = in + ((int64_t)Z * G + Y) * G * C + 8 * grp;
         const v4f* wq = s_w + (t * 4 + grp) * 6;  // 24 floats: [channel][output]
         const v4f w0 = wq[0], w1 = wq[1], w2 = wq[2], w3 = wq[3], w4 = wq[4], w5 = wq[5];
         const float wv[24] = { w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w, w2.x, w2.y, w2.z, w2.w,
@@ -326,17 +404,9 @@ __device__ __forceinline__ void conv4_item(int32_t G, const T* __restrict__ in, 
         for (int mb = 0; mb < 4; ++mb) {
             const int X = x0 + 16 * mb + col + dx;
             if (X < 0 || X >= G) continue;
-            float av[8];
-            if constexpr (sizeof(T) == 4) {
-                const v4f* p = reinterpret_cast<const v4f*>(src + (int64_t)X * C);
-                const v4f a0 = p[0], a1 = p[1];
-                av[0] = a0.x; av[1] = a0.y; av[2] = a0.z; av[3] = a0.w;
-                av[4] = a1.x; av[5] = a1.y; av[6] = a1.z; av[7] = a1.w;
-            } else {
-                const v8f a = __builtin_convertvector(*reinterpret_cast<const bf16x8*>(src + (int64_t)X * C), v8f);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) av[j] = a[j];
-            }
+            const v4f* p = reinterpret_cast<const v4f*>(src + (int64_t)X * C);
+            const v4f a0 = p[0], a1 = p[1];
+            const float av[8] = { a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w };
 #pragma unroll
             for (int c = 0; c < 8; ++c)
 #pragma unroll
@@ -371,8 +441,7 @@ __device__ __forceinline__ void conv4_item(int32_t G, const T* __restrict__ in, 
 // cell l%16 of each 16-cell block (four lanes cover a cell's 128-byte line), forms the partial
 // sums of its 8 channels for the 3 outputs, and the four lane groups' sums are added across lanes.
 // Weights in LDS as [tap][lane group][8 channels][3].
-template <class T>
-__global__ __launch_bounds__(kWaves4 * 64) void k3c_conv4(int32_t G, const T* __restrict__ in,
+__global__ __launch_bounds__(kWaves4 * 64) void k3c_conv4(int32_t G, const float* __restrict__ in,
                                                            const float* __restrict__ w, const float* __restrict__ b,
                                                            float* __restrict__ disp)
 {
@@ -391,7 +460,7 @@ __global__ __launch_bounds__(kWaves4 * 64) void k3c_conv4(int32_t G, const T* __
     int64_t i0, i1;
     item_range((int64_t)G * G * segs, i0, i1);
     for (int64_t item = i0 + (threadIdx.x >> 6); item < i1; item += kWaves4)
-        conv4_item<T>(G, in, s_w, segs, item, col, grp, n, bias, disp);
+        conv4_item(G, in, s_w, segs, item, col, grp, n, bias, disp);
 }
 
 unsigned blocks_for(int64_t n)
@@ -445,14 +514,16 @@ void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, int3
         k3c_conv1<bf16><<<blocks_for(cells), kBlock, 0, stream>>>(G, vel, w.w[0], w.b[0], b0);
         k3c_conv32_bf16<<<grid, 16 * 64, 0, stream>>>(G, b0, wb2, w.b[1], b1);
         k3c_conv32_bf16<<<grid, 16 * 64, 0, stream>>>(G, b1, wb3, w.b[2], b0);
-        k3c_conv4<bf16><<<grid, kWaves4 * 64, 0, stream>>>(G, b0, w.w[3], w.b[3], disp);
+        bf16x8* wb4 = wb3 + NWB;
+        k3c_wprep4_bf16<<<(TAPS * 64 + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[3], wb4);
+        k3c_conv4_bf16<<<grid, 16 * 64, 0, stream>>>(G, b0, wb4, w.b[3], disp);
     } else {
         k3c_wprep<<<(NWT + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[1], wt2);
         k3c_wprep<<<(NWT + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[2], wt3);
         k3c_conv1<float><<<blocks_for(cells), kBlock, 0, stream>>>(G, vel, w.w[0], w.b[0], act0);
         k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act0, wt2, w.b[1], act1);
         k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act1, wt3, w.b[2], act0);
-        k3c_conv4<float><<<grid, kWaves4 * 64, 0, stream>>>(G, act0, w.w[3], w.b[3], disp);
+        k3c_conv4<<<grid, kWaves4 * 64, 0, stream>>>(G, act0, w.w[3], w.b[3], disp);
     }
     hip_check(hipGetLastError(), "predict3d launch");
 }
