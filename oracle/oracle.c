@@ -694,32 +694,41 @@ int orc3_lookup(int64_t n_tet, const double* xyz, const int32_t* tet, int32_t G,
     if (G <= 0 || n_tet < 0) return ORC_EINVAL;
     const int64_t nc = (int64_t)G * G * G;
     for (int64_t c = 0; c < nc; ++c) lookup[c] = -1;
-    for (int64_t t = 0; t < n_tet; ++t) {
-        const double* v[4];
-        int32_t id[4];
-        tet_vertices(xyz, tet, t, v, id);
-        int lo[3], hi[3];
-        for (int d = 0; d < 3; ++d) {
-            double mn = v[0][d], mx = v[0][d];
-            for (int k = 1; k < 4; ++k) {
-                mn = v[k][d] < mn ? v[k][d] : mn;
-                mx = v[k][d] > mx ? v[k][d] : mx;
-            }
-            lo[d] = (int)floor(mn * G - 0.5) - 1;
-            hi[d] = (int)ceil(mx * G - 0.5) + 1;
-            if (lo[d] < 0) lo[d] = 0;
-            if (hi[d] > G - 1) hi[d] = G - 1;
-        }
-        for (int cz = lo[2]; cz <= hi[2]; ++cz)
-            for (int cy = lo[1]; cy <= hi[1]; ++cy)
-                for (int cx = lo[0]; cx <= hi[0]; ++cx) {
-                    int32_t* cell = lookup + ((int64_t)cz * G + cy) * G + cx;
-                    if (*cell != -1) continue;
-                    const double p[3] = { (cx + 0.5) / G, (cy + 0.5) / G, (cz + 0.5) / G };
-                    double s[4];
-                    bary3_numerators(v, id, p, s);
-                    if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0 && s[3] >= 0.0) *cell = (int32_t)t;
+    /* each thread owns a range of cell planes z and visits every tetrahedron in increasing id
+       for the cells of its planes, so the result is the serial one */
+#pragma omp parallel
+    {
+        const int tid = omp_get_thread_num(), nth = omp_get_num_threads();
+        const int z_lo = (int)((int64_t)G * tid / nth), z_hi = (int)((int64_t)G * (tid + 1) / nth) - 1;
+        for (int64_t t = 0; t < n_tet; ++t) {
+            const double* v[4];
+            int32_t id[4];
+            tet_vertices(xyz, tet, t, v, id);
+            int lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) {
+                double mn = v[0][d], mx = v[0][d];
+                for (int k = 1; k < 4; ++k) {
+                    mn = v[k][d] < mn ? v[k][d] : mn;
+                    mx = v[k][d] > mx ? v[k][d] : mx;
                 }
+                lo[d] = (int)floor(mn * G - 0.5) - 1;
+                hi[d] = (int)ceil(mx * G - 0.5) + 1;
+                if (lo[d] < 0) lo[d] = 0;
+                if (hi[d] > G - 1) hi[d] = G - 1;
+            }
+            if (lo[2] < z_lo) lo[2] = z_lo;
+            if (hi[2] > z_hi) hi[2] = z_hi;
+            for (int cz = lo[2]; cz <= hi[2]; ++cz)
+                for (int cy = lo[1]; cy <= hi[1]; ++cy)
+                    for (int cx = lo[0]; cx <= hi[0]; ++cx) {
+                        int32_t* cell = lookup + ((int64_t)cz * G + cy) * G + cx;
+                        if (*cell != -1) continue;
+                        const double p[3] = { (cx + 0.5) / G, (cy + 0.5) / G, (cz + 0.5) / G };
+                        double s[4];
+                        bary3_numerators(v, id, p, s);
+                        if (s[0] >= 0.0 && s[1] >= 0.0 && s[2] >= 0.0 && s[3] >= 0.0) *cell = (int32_t)t;
+                    }
+        }
     }
     return ORC_OK;
 }
