@@ -114,7 +114,51 @@ def pct(a, q):
     return float(np.percentile(a, q))
 
 
-def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
+def cpu_baseline_3d(w, ws, bs, vel, d32, slab: int = 8):
+    """The FP64 oracle beside the 3D legs on a bounded sample of the same workload (host cores):
+    the plain walk of all points, and the 3D CNN on `slab` overlay planes plus the CNN-SNS start
+    and walk of the points whose origin lies in them.  Also the timed FP32 3D CNN output on that
+    slab against the oracle (the 1e-5 bar per channel)."""
+    import oracle as O
+
+    threads = O.set_threads(0)
+    G = w.G
+    t = time.perf_counter()
+    tp, nbr = O.prepare_mesh3(w.xyz, w.tet)
+    lk = O.lookup3(w.xyz, tp, G)
+    setup_s = time.perf_counter() - t
+    z0 = max(0, G // 2 - slab // 2)
+    z1 = min(G, z0 + slab)
+    cz = np.clip(np.floor(w.xyz[:, 2] * G), 0, G - 1).astype(np.int64)
+    sel = np.nonzero((cz >= z0) & (cz < z1))[0]
+    t = time.perf_counter()
+    ref = O.cnn3_window(vel, ws, bs, (z0, 0, 0), (z1 - z0, G, G))
+    t_cnn = time.perf_counter() - t
+    disp = np.zeros((3, G, G, G))
+    disp[:, z0:z1] = ref
+    t = time.perf_counter()
+    s0 = O.cnnsns3_start(w.xyz[sel], disp, lk, w.start[sel])
+    _, it, _ = O.sns3(w.xyz, tp, nbr, w.xp[sel], s0)
+    t_walk = time.perf_counter() - t
+    t = time.perf_counter()
+    _, pit, _ = O.sns3(w.xyz, tp, nbr, w.xp, w.start)
+    t_plain = time.perf_counter() - t
+    got = d32[:, z0:z1].astype(np.float64)
+    scale = np.abs(ref).reshape(3, -1).max(axis=1)[:, None, None, None]
+    ratio = float((np.abs(got - ref) / (1e-5 * np.abs(ref) + 1e-5 * scale + 1e-30)).max())
+    n = len(sel)
+    return {
+        "value": n / (t_cnn + t_walk), "unit": "points/s", "cores": threads, "kind": "oracle",
+        "sample": (f"overlay planes z in [{z0},{z1}) of {G}: FP64 3D CNN on them ({t_cnn:.2f}s) + CNN-SNS start and "
+                   f"walk of the {n} points whose origin lies in them ({t_walk:.2f}s); mesh prep and lookup untimed "
+                   f"({setup_s:.1f}s)"),
+        "plain_sns_value": w.n_points / t_plain, "plain_sns_s": t_plain, "plain_sns_sample": "all points",
+        "mean_path_cnn_sns": float(it.mean()), "mean_path_plain": float(pit.mean()),
+        "f32_parity_on_slab": {"worst_error_over_tolerance": round(ratio, 4), "pass": ratio <= 1.0},
+    }
+
+
+def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float, with_cpu: bool = True):
     """Alg. 1 on a tetrahedral mesh (the walk of Sec. 2.2 with four faces per element): the
     departure points of a jittered Kuhn mesh advected in the ABC flow, walked from the element
     before movement and from the overlay lookup, on the same GPU."""
@@ -179,6 +223,7 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
     log(f"3D CNN-SNS: predict {p3_ms.mean():.3f} ms, locate {l3_ms.mean():.3f} ms, mean I_t {it_c.mean():.2f}")
     cnn3_flops = 2.0 * CNN3_MACS_PER_CELL * w.G ** 3
     cnn3_tf = cnn3_flops / (p3_ms.mean() / 1e3) / 1e12
+    d32 = disp.cpu().numpy()
     # the same step with the BF16 3D CNN (precision variant)
     for _ in range(warmup):
         C.predict3d(mesh, vel, wts, "bf16", disp=disp)
@@ -269,6 +314,11 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float):
                      "lookup_start_leg": {"achieved": round(g_asg, 1), "frac": round(g_asg / PEAK["hbm_GBps"], 4),
                                           "traffic": traffic_for("k3_locate_lookup", name)}},
     }
+    if with_cpu:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline_3d(w, ws, bs, W.overlay_velocity_3d(w.flow, w.G), d32)
+        log(f"3D cpu baseline: {out['cpu_baseline']['value']:.0f} points/s CNN-SNS, "
+            f"{out['cpu_baseline']['plain_sns_value']:.0f} points/s plain ({time.perf_counter() - t0:.1f}s)")
     mesh.close()
     return out
 
@@ -699,7 +749,7 @@ def main():
         res["precision_report"] = {"mean_path_f32_cnn": round(float(it32.mean()), 4),
                                    "mean_path_change": round(float(it_c.mean() - it32.mean()), 4)}
     if args.walk3d != "none":
-        res["walk3d_leg"] = walk3d_leg(args.walk3d, K, args.warmup, copy_gbps)
+        res["walk3d_leg"] = walk3d_leg(args.walk3d, K, args.warmup, copy_gbps, with_cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         band = args.cpu_band_rows or {"c2": 1024, "c3": 1536, "c4": 1024}[args.workload]
         t0 = time.perf_counter()
