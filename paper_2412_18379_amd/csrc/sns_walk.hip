@@ -2,15 +2,16 @@
 // CNN-SNS start element of Alg. 2 selected in the same kernel.
 //
 // One lane walks one point.  With looked-up starts (short walks, a few long
-// ones) a wavefront owns a chunk of 512 points and keeps all 64 lanes busy:
-// whenever lanes finish their walks, the wave hands them the chunk's next
-// unstarted points (ballot + lane prefix count), so a long walk does not leave
-// the rest of its wave idle.  From given starts (long walks of similar length
-// for neighbouring points) a wavefront takes 64 points, one per lane: on 8M
-// points in 16M triangles that is 20 % faster than chunks of 512 and 7 %
-// faster than 128, the wider grid hiding more of each hop's latency.  Each hop is one
-// 64-byte gather of the current element's record; the geometry is FP64 with
-// no fused multiply-add, exactly as written.
+// ones) a wavefront owns 128 points and keeps all 64 lanes busy: whenever
+// lanes finish their walks, the wave hands them its next unstarted points
+// (ballot + lane prefix count), so a long walk does not leave the rest of its
+// wave idle (on 8M points in 16M triangles, 128 points per wavefront walk 7 %
+// faster than 512 and 3.5 % faster than 256).  From given starts (long walks
+// of similar length for neighbouring points) a wavefront takes 64 points, one
+// per lane: 20 % faster than chunks of 512 and 7 % faster than 128, the wider
+// grid hiding more of each hop's latency.  Each hop is one 64-byte gather of
+// the current element's record; the geometry is FP64 with no fused
+// multiply-add, exactly as written.
 #pragma clang fp contract(off)
 
 #include "common.h"
@@ -20,7 +21,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
-constexpr int64_t kChunk = 512;      // points per wavefront, looked-up starts
+constexpr int64_t kChunk = 128;      // points per wavefront, looked-up starts (two per lane at least)
 constexpr int64_t kChunkGiven = 64;  // points per wavefront, given starts
 
 __device__ __forceinline__ int32_t cell_of(double x, int32_t G)
@@ -49,15 +50,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     // From the element before movement (long paths, where neighbouring points share elements)
     // a wave owns kChunkGiven slots: slot v is point wave kChunkGiven + v, a contiguous chunk.
     // From a looked-up start (short paths, whose rare long ones cluster at the two ends of the
-    // point order, the domain boundary) a wave owns kChunk slots, 8 runs of 64 consecutive
-    // points strided across all points, so the long walks of one region spread over many waves: run u is
-    // 64-point block b + u n_waves with b = wave for even u and n_waves - 1 - wave for odd u,
-    // so both ends of the point order fall to the first waves, which walk them first (runs in
-    // the order 0, 7, 1, 6, 2, 5, 3, 4).
+    // point order, the domain boundary) a wave owns kChunk slots, R = kChunk / 64 runs of 64
+    // consecutive points strided across all points, so the long walks of one region spread over
+    // many waves: run u is 64-point block b + u n_waves with b = wave for even u and
+    // n_waves - 1 - wave for odd u, so both ends of the point order fall to the first waves,
+    // which walk them first (runs in the order 0, R - 1, 1, R - 2, ...).
     auto point_of = [&](int64_t v) -> int64_t {
         if (MODE == START_GIVEN) return wave * kChunkGiven + v;
         const int k = (int)(v >> 6);
-        const int u = (k & 1) ? 7 - (k >> 1) : (k >> 1);
+        const int u = (k & 1) ? (int)(kChunk / 64) - 1 - (k >> 1) : (k >> 1);
         const int64_t b = (u & 1) ? n_waves - 1 - wave : wave;
         return ((b + u * n_waves) << 6) + (v & (kWave - 1));
     };
@@ -75,6 +76,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         // in two halves of four points per lane, staged so that the four chains' loads of each
         // level issue together (eight at once would cost occupancy)
         constexpr int PER_LANE = (int)(kChunk / kWave), H = PER_LANE / 2;
+        static_assert(H >= 1 && PER_LANE == 2 * H, "looked-up starts need an even number (>= 2) of points per lane");
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             int64_t pt[H];
