@@ -106,7 +106,7 @@ typedef struct {
  *
  * The inputs are copied; the caller keeps its arrays.  Errors: EINVAL (null
  * pointer, n_nodes < 3, n_tri < 1, overlay_side < 0 or > 65536), EMESH (a
- * node index out of range, a zero-area triangle, an edge in more than two
+ * node index out of range, a triangle of zero or non-finite area, an edge in more than two
  * triangles, or two triangles that overlap across an edge), ENOMEM, EHIP.
  */
 int cnnsns_build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, int64_t n_tri,

@@ -38,7 +38,7 @@ __global__ void k_canonicalise(int64_t n_tri, int64_t n_nodes, const double2* __
     }
     double2 A = xy[a], B = xy[b], C = xy[c];
     double d = (B.x - A.x) * (C.y - A.y) - (B.y - A.y) * (C.x - A.x);
-    if (d == 0.0) atomicOr(err, ERR_AREA);
+    if (!(d > 0.0 || d < 0.0) || !isfinite(d)) atomicOr(err, ERR_AREA);  // zero, NaN or infinite
     tri[3 * t] = a;
     tri[3 * t + 1] = d < 0.0 ? c : b;
     tri[3 * t + 2] = d < 0.0 ? b : c;
@@ -127,13 +127,14 @@ __device__ __forceinline__ CellBox cell_box(const ElemRec& r, int32_t G)
     const double g = (double)G;
     double xmin = fmin(r.ax, fmin(r.bx, r.cx)), xmax = fmax(r.ax, fmax(r.bx, r.cx));
     double ymin = fmin(r.ay, fmin(r.by, r.cy)), ymax = fmax(r.ay, fmax(r.by, r.cy));
-    double fx0 = floor(xmin * g - 0.5) - 1.0, fx1 = ceil(xmax * g - 0.5) + 1.0;
-    double fy0 = floor(ymin * g - 0.5) - 1.0, fy1 = ceil(ymax * g - 0.5) + 1.0;
+    // clamped before conversion (fmax and fmin return the number when the other is NaN)
+    const double fx0 = fmax(floor(xmin * g - 0.5) - 1.0, 0.0), fx1 = fmin(ceil(xmax * g - 0.5) + 1.0, g - 1.0);
+    const double fy0 = fmax(floor(ymin * g - 0.5) - 1.0, 0.0), fy1 = fmin(ceil(ymax * g - 0.5) + 1.0, g - 1.0);
     CellBox b;
-    b.cx0 = fx0 < 0.0 ? 0 : (fx0 > g - 1.0 ? G : (int32_t)fx0);
-    b.cy0 = fy0 < 0.0 ? 0 : (fy0 > g - 1.0 ? G : (int32_t)fy0);
-    b.cx1 = fx1 > g - 1.0 ? G - 1 : (fx1 < 0.0 ? -1 : (int32_t)fx1);
-    b.cy1 = fy1 > g - 1.0 ? G - 1 : (fy1 < 0.0 ? -1 : (int32_t)fy1);
+    b.cx0 = fx0 > g - 1.0 ? G : (int32_t)fx0;
+    b.cy0 = fy0 > g - 1.0 ? G : (int32_t)fy0;
+    b.cx1 = fx1 < 0.0 ? -1 : (int32_t)fx1;
+    b.cy1 = fy1 < 0.0 ? -1 : (int32_t)fy1;
     return b;
 }
 
@@ -294,7 +295,7 @@ cnnsns_mesh build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, in
         hip_check(hipMemcpyAsync(&err, d_err.p, sizeof(int), hipMemcpyDeviceToHost, stream), "copy err");
         hip_check(hipStreamSynchronize(stream), "mesh build");
         if (err & ERR_INDEX) fail(CNNSNS_EMESH, "build_mesh: node index out of range");
-        if (err & ERR_AREA) fail(CNNSNS_EMESH, "build_mesh: zero-area triangle");
+        if (err & ERR_AREA) fail(CNNSNS_EMESH, "build_mesh: a triangle of zero or non-finite area");
         if (err & ERR_EDGE3) fail(CNNSNS_EMESH, "build_mesh: an edge is shared by more than two triangles");
         if (err & ERR_OVERLAP) fail(CNNSNS_EMESH, "build_mesh: two triangles overlap across an edge");
     }

@@ -184,6 +184,9 @@ def test_mesh_errors_on_device(C):
     with pytest.raises(C.CnnsnsError) as e:
         C.Mesh(xy3, np.array([[0, 1, 2], [0, 1, 3]], np.int32))
     assert e.value.code == C.EMESH
+    with pytest.raises(C.CnnsnsError) as e:  # a non-finite node
+        C.Mesh(np.array([[0, 0], [1, 0], [np.nan, 1]], dtype=np.float64), np.array([[0, 1, 2]], np.int32))
+    assert e.value.code == C.EMESH
 
 
 def test_ragged_counts_lookup_modes(C, oracle_mod, wl):
