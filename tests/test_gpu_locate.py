@@ -147,7 +147,7 @@ def test_statuses_and_edge_cases(C, oracle_mod, wl):
     assert np.array_equal(s.cpu().numpy(), os_)
     assert np.all(os_[:4] == C.BADSTART) and np.all(os_[10:14] == C.OUTSIDE)
     # optional outputs omitted; n = 0; ragged counts around the wave chunk size
-    for n in [0, 1, 63, 64, 65, 511, 512, 513, 1000]:
+    for n in [0, 1, 63, 64, 65, 255, 256, 257, 511, 512, 513, 1000]:
         hh, _, _ = C.locate(mesh, _dev(w.xp[:n]), start=_dev(w.start[:n]), want_iters=False, want_status=False)
         torch.cuda.synchronize()
         if n:
@@ -201,7 +201,7 @@ def test_ragged_counts_lookup_modes(C, oracle_mod, wl):
     lk = oracle_mod.lookup(w.xy, tc, G)
     zero = np.zeros((2, G, G))
     d_disp = _dev(disp)
-    for n in [1, 63, 64, 65, 511, 512, 513, 1000, 2049, 4097, 70001]:
+    for n in [1, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1000, 2049, 4097, 70001]:
         print(f"[ragged lookup modes] n={n}", flush=True)
         xp, org = w.xp[:n], w.origins[:n]
         _, oh, oi, _ = oracle_mod.cnnsns(w.xy, tc, nbr, lk, org, xp, disp.astype(np.float64))
