@@ -189,3 +189,39 @@ def test_coarse_mesh_under_a_fine_overlay(C, oracle_mod, wl):
     lk = oracle_mod.lookup3(xyz, tp, G)
     h, it, st = _np(*C.locate3d(mesh, _dev(_centres(G)), max_iter=1))
     assert np.array_equal(h, lk.ravel()) and np.all(st == C.FOUND)
+
+
+def test_unstructured_delaunay_mesh(C, oracle_mod, wl):
+    """Qhull's Delaunay tetrahedralisation of 20,000 random points (irregular topology and node
+    order, a ragged hull): given, lookup and CNN-SNS starts bit for bit against the oracle,
+    including the points outside the hull."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(22)
+    pts = rng.uniform(0.0, 1.0, size=(20000, 3))
+    tet = Delaunay(pts).simplices.astype(np.int32)
+    G = 24
+    mesh = C.Mesh3D(pts, tet, overlay_side=G)
+    tp, nbr = oracle_mod.prepare_mesh3(pts, tet)
+    lk = oracle_mod.lookup3(pts, tp, G)
+    n = 50000
+    q = rng.uniform(0.0, 1.0, size=(n, 3))
+    start = rng.integers(0, tet.shape[0], size=n).astype(np.int32)
+    h, it, st = _np(*C.locate3d(mesh, _dev(q), start=_dev(start)))
+    rh, rit, rst = oracle_mod.sns3(pts, tp, nbr, q, start)
+    assert np.array_equal(h, rh) and np.array_equal(it, rit) and np.array_equal(st, rst)
+    assert set(np.unique(st)) == {C.FOUND, C.OUTSIDE}
+    h, it, st = _np(*C.locate3d(mesh, _dev(q)))
+    rh, rit, rst = oracle_mod.sns3(pts, tp, nbr, q, _lookup_starts(lk, q, G))
+    assert np.array_equal(h, rh) and np.array_equal(it, rit) and np.array_equal(st, rst)
+    origin = np.clip(q + rng.normal(0.0, 0.05, size=q.shape), 0.0, 1.0)
+    # a displacement grid: the mean step of the points whose origin is in the cell, else 0
+    c = np.clip(np.floor(origin * G), 0, G - 1).astype(np.int64)
+    flat = (c[:, 2] * G + c[:, 1]) * G + c[:, 0]
+    grid = np.zeros((3, G ** 3))
+    cnt = np.bincount(flat, minlength=G ** 3)
+    for a in range(3):
+        grid[a] = np.bincount(flat, weights=q[:, a] - origin[:, a], minlength=G ** 3) / np.maximum(cnt, 1)
+    grid = grid.reshape(3, G, G, G).astype(np.float32)
+    h, it, st = _np(*C.locate3d(mesh, _dev(q), start=_dev(start), origin=_dev(origin), disp=_dev(grid)))
+    _, rh, rit, rst = oracle_mod.cnnsns3(pts, tp, nbr, lk, origin, q, grid.astype(np.float64), fallback=start)
+    assert np.array_equal(h, rh) and np.array_equal(it, rit) and np.array_equal(st, rst)

@@ -130,3 +130,22 @@ def test_ties_go_to_the_lowest_index(oracle_mod, wl):
     for t, p, want in cases:
         h, it, st = oracle_mod.sns3(xyz, tp, nbr, np.array([p]), np.array([t], np.int32), max_iter=1)
         assert st[0] == 2 and it[0] == 1 and h[0] == want, (t, p, h[0], want)
+
+
+def test_unstructured_delaunay_mesh_against_qhull(oracle_mod):
+    """An unstructured mesh (Qhull's Delaunay tetrahedralisation of 3000 random points): every
+    point inside the hull is found in the simplex Qhull's own point location returns, every point
+    outside ends OUTSIDE at a boundary face, whatever the start."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(21)
+    pts = rng.uniform(0.0, 1.0, size=(3000, 3))
+    d = Delaunay(pts)
+    tet = d.simplices.astype(np.int32)
+    tp, nbr = oracle_mod.prepare_mesh3(pts, tet)
+    q = rng.uniform(0.0, 1.0, size=(20000, 3))
+    start = rng.integers(0, tet.shape[0], size=20000).astype(np.int32)
+    h, it, st = oracle_mod.sns3(pts, tp, nbr, q, start)
+    fs = d.find_simplex(q)
+    inside = fs >= 0
+    assert np.all(st[inside] == 0) and np.array_equal(h[inside], fs[inside])
+    assert np.all(st[~inside] == 1) and np.all(np.any(nbr[h[~inside]] == -1, axis=1))
