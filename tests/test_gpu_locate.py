@@ -211,3 +211,34 @@ def test_ragged_counts_lookup_modes(C, oracle_mod, wl):
         ah, ai, _ = oracle_mod.sns(w.xy, tc, nbr, xp, st)
         h, it, _ = C.locate(mesh, _dev(xp))
         assert np.array_equal(h.cpu().numpy(), ah) and np.array_equal(it.cpu().numpy(), ai)
+
+
+def test_unstructured_delaunay_mesh(C, oracle_mod):
+    """Qhull's Delaunay triangulation of 50,000 random points (irregular topology and node order,
+    a ragged hull): given, ASG and CNN-SNS starts bit for bit against the oracle, including the
+    points outside the hull."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(23)
+    pts = rng.uniform(0.0, 1.0, size=(50000, 2))
+    tri = Delaunay(pts).simplices.astype(np.int32)
+    G = 128
+    mesh = C.Mesh(pts, tri, overlay_side=G)
+    tc, nbr = oracle_mod.prepare_mesh(pts, tri)
+    lk = oracle_mod.lookup(pts, tc, G)
+    n = 60000
+    q = rng.uniform(0.0, 1.0, size=(n, 2))
+    start = rng.integers(0, tri.shape[0], size=n).astype(np.int32)
+    h, it, st = C.locate(mesh, _dev(q), start=_dev(start))
+    rh, rit, rst = oracle_mod.sns(pts, tc, nbr, q, start)
+    assert np.array_equal(h.cpu().numpy(), rh) and np.array_equal(it.cpu().numpy(), rit)
+    assert np.array_equal(st.cpu().numpy(), rst) and set(np.unique(rst)) == {C.FOUND, C.OUTSIDE}
+    h, it, st = C.locate(mesh, _dev(q))
+    a_st = oracle_mod.cnnsns_start(q, np.zeros((2, G, G)), lk)
+    rh, rit, rst = oracle_mod.sns(pts, tc, nbr, q, a_st)
+    assert np.array_equal(h.cpu().numpy(), rh) and np.array_equal(it.cpu().numpy(), rit)
+    origin = np.clip(q + rng.normal(0.0, 0.02, size=q.shape), 0.0, 1.0)
+    disp = rng.normal(0.0, 0.01, size=(2, G, G)).astype(np.float32)
+    h, it, st = C.locate(mesh, _dev(q), start=_dev(start), origin=_dev(origin), disp=_dev(disp))
+    _, rh, rit, rst = oracle_mod.cnnsns(pts, tc, nbr, lk, origin, q, disp.astype(np.float64), fallback=start)
+    assert np.array_equal(h.cpu().numpy(), rh) and np.array_equal(it.cpu().numpy(), rit)
+    assert np.array_equal(st.cpu().numpy(), rst)
