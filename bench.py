@@ -500,7 +500,7 @@ def main():
                     help="only run a device copy of BYTES (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(points are independent; see the sharding note in the design document).", file=sys.stderr)
         sys.exit(2)
 

@@ -297,7 +297,7 @@ int cnnsns_interpolate3d(cnnsns_mesh3 m, int64_t n, const double* xp, const int3
  *   max_inflight      jobs on the device at once (>= 1).
  *   queue_depth       jobs waiting for admission at most (>= 1).
  *   w                 CNN weights (device pointers; copied at creation).
- * Switched off in this build: returns EINVAL unless the environment variable
+ * Switched off: returns EINVAL unless the environment variable
  * CNNSNS_ENABLE_SERVING is "1", because runs of the serving loop on the GPU
  * have occasionally ended in a host-side segmentation fault whose cause has
  * not been found.

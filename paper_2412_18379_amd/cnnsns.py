@@ -47,7 +47,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2412_18379_amd.build first")
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         sig = {

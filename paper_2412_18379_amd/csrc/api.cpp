@@ -219,7 +219,7 @@ int cnnsns_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int32_t
         // then, in a host-side segmentation fault whose cause has not been found.
         const char* on = std::getenv("CNNSNS_ENABLE_SERVING");
         if (!on || std::strcmp(on, "1") != 0)
-            fail(CNNSNS_EINVAL, "server_create: the serving loop is switched off in this build (an intermittent host "
+            fail(CNNSNS_EINVAL, "server_create: the serving loop is switched off (an intermittent host "
                                 "crash in it is unexplained); set CNNSNS_ENABLE_SERVING=1 to enable it");
         *out = server_create(hbm_budget_bytes, max_inflight, queue_depth, precision, w);
     });

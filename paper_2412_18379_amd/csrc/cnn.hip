@@ -701,7 +701,7 @@ void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision
         cnn_bf16_forward(G, vel, ws, w, disp, persistent_grid(1 << 30), stream);
         return;
     }
-    if (precision != CNNSNS_F32) fail(CNNSNS_EINVAL, "predict: FP8 is not available in this build");
+    if (precision != CNNSNS_F32) fail(CNNSNS_EINVAL, "predict: FP8 is not implemented");
     float* u2 = static_cast<float*>(ws);
     float* u3 = u2 + NU;
     float* act2 = u3 + NU;
