@@ -9,7 +9,7 @@
   KiB; each is scaled by the factor (bytes the copy must move) / (bytes the
   counter reports for it), so a kernel's figure is in the copy's units.
 
-    python -m paper_2412_18379_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
+    python -m paper_2412_18379_amd.profiling stats <kernel_stats.csv> <out.md> "<command>" [+names|-names]
     python -m paper_2412_18379_amd.profiling traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
         <copy_write.csv> <copy_bytes> <workload> <traffic.json> "<command>" name=kernel[*k][+kernel[*k]] ...
 
@@ -67,9 +67,15 @@ def _short(name: str, width: int = 90) -> str:
     return short if len(short) <= width else short[:width - 3] + "..."
 
 
-def stats(csv_path: str, out_path: str, command: str, top: int = 20) -> str:
+def stats(csv_path: str, out_path: str, command: str, top: int = 20, select: str = "") -> str:
+    """Markdown table of the kernel statistics; `select` "+a,b" keeps only the kernels whose name
+    contains one of a, b, "-a,b" drops them (the percentages stay those of the whole run)."""
     with open(csv_path) as f:
         rows = list(csv.DictReader(f))
+    if select:
+        keys = select[1:].split(",")
+        keep = select[0] == "+"
+        rows = [r for r in rows if any(k in r["Name"] for k in keys) == keep]
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     lines = [f"Command: `{command}`", "",
              "| kernel | calls | mean (us) | min (us) | max (us) | total (ms) | % |",
@@ -144,7 +150,7 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, wo
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
-        print(stats(sys.argv[2], sys.argv[3], sys.argv[4]))
+        print(stats(sys.argv[2], sys.argv[3], sys.argv[4], select=sys.argv[5] if len(sys.argv) > 5 else ""))
     elif sys.argv[1] == "traffic":
         a = sys.argv[2:]
         groups = {}
