@@ -42,7 +42,7 @@ constexpr int TAPS = 27;
 constexpr int NWT = TAPS * 4 * 64 * 4;  // operand-ordered weights of one 32 -> 32 layer (floats)
 constexpr int NWB = TAPS * 2 * 64;      // the same in BF16 (bf16x8 entries)
 constexpr int kBlock = 256;       // vector-ALU layers
-constexpr int kWaves32 = 8;       // matrix layers: waves per block (168 registers each)
+constexpr int kWaves32 = 12;      // matrix layers: waves per block (three per SIMD, at most 170 registers)
 constexpr int kWaves4 = 16;       // layer 4: waves per block
 constexpr int kSeg = 64;          // cells per wavefront work item (four 16-cell blocks)
 
@@ -143,10 +143,11 @@ __device__ __forceinline__ void item_range(int64_t n_items, int64_t& i0, int64_t
     i1 = i0 + per < n_items ? i0 + per : n_items;
 }
 
-// Layers 2 and 3: 32 -> 32 with ReLU on the matrix cores, persistent blocks of 8 wavefronts (two
-// per SIMD).  The next tap's activations are loaded while this tap's 64 matrix instructions run:
-// that needs 168 registers, so two wavefronts per SIMD instead of four without the prefetch
-// (3.43 -> 3.25 ms for the whole pass at G = 128; four wavefronts with the prefetch spill).
+// Layers 2 and 3: 32 -> 32 with ReLU on the matrix cores, persistent blocks of 12 wavefronts
+// (three per SIMD).  The next tap's activations are loaded while this tap's 64 matrix
+// instructions run: that needs 160 registers, so three wavefronts per SIMD instead of four
+// without the prefetch (whole pass at G = 128: 3.43 ms without it, 3.25 ms with it at two
+// wavefronts per SIMD, 3.12 ms at three; four wavefronts with the prefetch spill).
 __global__ __launch_bounds__(kWaves32 * 64) void k3c_conv32(int32_t G, const float* __restrict__ in,
                                                             const float* __restrict__ wt,
                                                             const float* __restrict__ bias,
