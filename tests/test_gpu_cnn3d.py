@@ -193,3 +193,26 @@ def test_bf16_forward_windows_and_walk(C, oracle_mod, wl):
                                          fallback=w.start)
     assert np.array_equal(h, rh) and np.array_equal(it, rit) and np.array_equal(st, rst)
     assert np.all(st == C.FOUND)
+
+
+def test_deterministic_and_on_a_side_stream(C, wl):
+    """The 3D CNN (both precisions) and the CNN-SNS walk give the same bits on a second stream and
+    when repeated (no atomics or order-dependent reductions in their results)."""
+    w = wl.build_3d("t1")
+    mesh = C.Mesh3D(w.xyz, w.tet, overlay_side=w.G)
+    vel = _dev(wl.overlay_velocity_3d(w.flow, w.G))
+    net = C.Weights3D(*he_net(4))
+    xp, st, org = _dev(w.xp), _dev(w.start), _dev(w.xyz)
+    for prec in ("f32", "bf16"):
+        d0 = C.predict3d(mesh, vel, net, prec)
+        h0, i0, s0 = C.locate3d(mesh, xp, start=st, origin=org, disp=d0)
+        torch.cuda.synchronize()  # calls on one mesh share its CNN workspace and must not overlap
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            d1 = C.predict3d(mesh, vel, net, prec, stream=side)
+            h1, i1, s1 = C.locate3d(mesh, xp, start=st, origin=org, disp=d1, stream=side)
+        side.synchronize()
+        torch.cuda.synchronize()
+        assert torch.equal(d0, d1) and torch.equal(h0, h1) and torch.equal(i0, i1) and torch.equal(s0, s1)
+        d2 = C.predict3d(mesh, vel, net, prec)
+        assert torch.equal(d0, d2)
