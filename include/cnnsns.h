@@ -48,7 +48,7 @@ enum {
     CNNSNS_ENOMEM = -2, /* device or host allocation failed, or a memory budget is exceeded */
     CNNSNS_EHIP = -3,   /* a HIP runtime call failed */
     CNNSNS_EMESH = -4,  /* the mesh is invalid (see cnnsns_build_mesh) */
-    CNNSNS_EBUSY = -5,  /* the serving queue is full; retry later */
+    CNNSNS_EBUSY = -5,  /* the serving queue is full (retry later), or a mesh still has jobs in flight */
 };
 
 /* Per-point outcome of a walk (not an error). */
@@ -120,7 +120,8 @@ int cnnsns_build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, int
 int cnnsns_mesh_info(cnnsns_mesh m, int64_t* n_tri, int32_t* overlay_side, int64_t* device_bytes,
                      double* mean_diam);
 
-/* Free a mesh and its device memory (synchronises the device first). NULL is a no-op. */
+/* Free a mesh and its device memory (synchronises the device first). NULL is a
+ * no-op.  EBUSY while serving jobs submitted on the mesh are not complete. */
 int cnnsns_destroy_mesh(cnnsns_mesh m);
 
 /*
@@ -133,8 +134,11 @@ int cnnsns_destroy_mesh(cnnsns_mesh m);
  * The mesh keeps a workspace for the forward pass, allocated on first use and
  * grown when needed (FP32: one 32-channel FP32 activation of 128 G^2 bytes
  * plus 128 KiB of transformed weights; BF16: 40 KiB of packed weights) until
- * it is destroyed; concurrent predicts on one mesh must use one stream.
- * Asynchronous on `stream`.  Errors: EINVAL, ENOMEM, EHIP.
+ * it is destroyed.  Passes on one mesh share it: a pass is ordered on the
+ * device after the previous pass on that mesh, also across streams and
+ * threads (growing it synchronises the device).  Asynchronous on `stream`.
+ * Errors: EINVAL (also for CNNSNS_FP8E4M3, before any allocation), ENOMEM,
+ * EHIP.
  */
 int cnnsns_predict(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t precision, float* disp,
                    void* stream);
@@ -233,7 +237,8 @@ int cnnsns_destroy_mesh3d(cnnsns_mesh3 m);
  *              reads them, both computing in FP32.  CNNSNS_FP8E4M3: EINVAL.
  *   disp  FP32 [3][G][G][G] out: the predicted displacement per cell.
  * Uses a workspace of the mesh (2 G^3 x 32 FP32 activations plus 216 KiB),
- * allocated on the first call; calls on one mesh must not overlap.
+ * allocated on the first call; a pass is ordered on the device after the
+ * previous pass on that mesh, also across streams.
  * Asynchronous on `stream`.  Errors: EINVAL (null argument, precision not
  * CNNSNS_F32 or CNNSNS_BF16), ENOMEM (workspace), EHIP.
  */
@@ -311,12 +316,19 @@ int cnnsns_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int32_t
  * before movement origin (DEVICE FP64 [n][2]); results go to host / iters
  * (DEVICE int32 [n], iters may be NULL).  start (DEVICE int32 [n]) may be
  * NULL; it is only the fallback for uncovered overlay cells.  With n == 0
- * the point buffers may be NULL (the job is the forward pass alone).  Buffers
- * must stay valid until the job completes.  Returns at once with *job_id.
- * Errors: EINVAL, EBUSY (queue full), ENOMEM (the job alone exceeds the budget).
+ * the point buffers may be NULL (the job is the forward pass alone).
+ *   stream  the caller's stream (NULL = the null stream): the job runs after
+ *           the work enqueued on it before this call (an event is recorded
+ *           on it here), so inputs and output buffers written there are
+ *           ready; to consume the results, wait for completion (poll/wait).
+ * Buffers and the mesh must stay valid until the job completes; while a
+ * mesh has jobs that are not complete, cnnsns_destroy_mesh refuses it
+ * (EBUSY).  Returns at once with *job_id.  Errors: EINVAL, EBUSY (queue
+ * full), ENOMEM (the job alone exceeds the budget), EHIP.
  */
 int cnnsns_submit(cnnsns_server s, cnnsns_mesh m, const float* vel, int64_t n, const double* xp,
-                  const double* origin, const int32_t* start, int32_t* host, int32_t* iters, uint64_t* job_id);
+                  const double* origin, const int32_t* start, int32_t* host, int32_t* iters, void* stream,
+                  uint64_t* job_id);
 
 /*
  * Completion of a job: *done = 1 when its results are in device memory.

@@ -65,7 +65,7 @@ def lib():
             "cnnsns_locate3d": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp],
             "cnnsns_interpolate3d": [vp, i64, vp, vp, vp, vp, vp],
             "cnnsns_server_create": [i64, i32, i32, i32, ctypes.POINTER(_Cnn), ctypes.POINTER(vp)],
-            "cnnsns_submit": [vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)],
+            "cnnsns_submit": [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)],
             "cnnsns_poll": [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
             "cnnsns_wait": [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)],
             "cnnsns_server_destroy": [vp],
@@ -323,11 +323,21 @@ class Server:
         self.handle = h
         self._keep = {}
 
-    def submit(self, mesh: Mesh, vel, xp, origin, host, iters=None, start=None) -> int:
+    def submit(self, mesh: Mesh, vel, xp, origin, host, iters=None, start=None, stream=None) -> int:
+        """Queue a CNN-SNS job; it runs after the work enqueued on `stream` (default: the current
+        stream) before this call.  The mesh and the buffers are kept alive until it completes."""
+        n = xp.shape[0]
+        G = mesh.G
+        _need(vel, torch.float32, (2, G, G), "vel")
+        _need(xp, torch.float64, (n, 2), "xp")
+        _need(origin, torch.float64, (n, 2), "origin")
+        _need(host, torch.int32, (n,), "host")
+        _need(iters, torch.int32, (n,), "iters")
+        _need(start, torch.int32, (n,), "start")
         jid = ctypes.c_uint64()
-        _check(lib().cnnsns_submit(self.handle, mesh.handle, _ptr(vel), xp.shape[0], _ptr(xp), _ptr(origin),
-                                   _ptr(start), _ptr(host), _ptr(iters), ctypes.byref(jid)))
-        self._keep[jid.value] = (vel, xp, origin, host, iters, start)
+        _check(lib().cnnsns_submit(self.handle, mesh.handle, _ptr(vel), n, _ptr(xp), _ptr(origin),
+                                   _ptr(start), _ptr(host), _ptr(iters), _stream(stream), ctypes.byref(jid)))
+        self._keep[jid.value] = (mesh, vel, xp, origin, host, iters, start)
         return jid.value
 
     def poll(self, job_id: int):

@@ -29,6 +29,42 @@ void hip_check(hipError_t e, const char* what)
     }
 }
 
+void workspace_acquire(Workspace& ws, size_t need, hipStream_t stream, const char* what)
+{
+    if (ws.bytes < need) {
+        if (ws.ptr) {
+            // every pass enqueued with the old buffer must finish before it is freed
+            hip_check(hipDeviceSynchronize(), what);
+            hip_check(hipFree(ws.ptr), what);
+            ws.ptr = nullptr;
+            ws.bytes = 0;
+        }
+        if (hipMalloc(&ws.ptr, need) != hipSuccess) {
+            ws.ptr = nullptr;
+            (void)hipGetLastError();
+            fail(CNNSNS_ENOMEM, std::string(what) + ": workspace of " + std::to_string(need) + " bytes");
+        }
+        ws.bytes = need;
+    }
+    // (also on the same stream handle: a destroyed stream's handle may be reused by a new one)
+    if (ws.last_use) hip_check(hipStreamWaitEvent(stream, ws.last_use, 0), what);
+}
+
+void workspace_used(Workspace& ws, hipStream_t stream)
+{
+    if (!ws.last_use) hip_check(hipEventCreateWithFlags(&ws.last_use, hipEventDisableTiming), "workspace event");
+    hip_check(hipEventRecord(ws.last_use, stream), "workspace event");
+}
+
+void workspace_release(Workspace& ws)
+{
+    if (ws.ptr) (void)hipFree(ws.ptr);
+    if (ws.last_use) (void)hipEventDestroy(ws.last_use);
+    ws.ptr = nullptr;
+    ws.bytes = 0;
+    ws.last_use = nullptr;
+}
+
 template <class F>
 static int guarded(F&& f)
 {
@@ -104,8 +140,8 @@ int cnnsns_predict(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t
         if (!m || !vel || !w || !disp) fail(CNNSNS_EINVAL, "predict: NULL argument");
         for (int l = 0; l < 4; ++l)
             if (!w->w[l] || !w->b[l]) fail(CNNSNS_EINVAL, "predict: NULL weight or bias pointer");
-        if (precision != CNNSNS_F32 && precision != CNNSNS_BF16 && precision != CNNSNS_FP8E4M3)
-            fail(CNNSNS_EINVAL, "predict: unknown precision");
+        if (precision == CNNSNS_FP8E4M3) fail(CNNSNS_EINVAL, "predict: FP8 is not implemented");
+        if (precision != CNNSNS_F32 && precision != CNNSNS_BF16) fail(CNNSNS_EINVAL, "predict: unknown precision");
         DeviceScope ds(m->device);
         run_predict(*m, vel, *w, precision, disp, static_cast<hipStream_t>(stream));
     });
@@ -226,13 +262,13 @@ int cnnsns_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int32_t
 }
 
 int cnnsns_submit(cnnsns_server s, cnnsns_mesh m, const float* vel, int64_t n, const double* xp, const double* origin,
-                  const int32_t* start, int32_t* host, int32_t* iters, uint64_t* job_id)
+                  const int32_t* start, int32_t* host, int32_t* iters, void* stream, uint64_t* job_id)
 {
     return guarded([&] {
         if (!s || !m || !vel || !job_id) fail(CNNSNS_EINVAL, "submit: NULL argument");
         if (n < 0) fail(CNNSNS_EINVAL, "submit: n must be >= 0");
         if (n > 0 && (!xp || !origin || !host)) fail(CNNSNS_EINVAL, "submit: NULL point buffer");
-        *job_id = server_submit(s, m, vel, n, xp, origin, start, host, iters);
+        *job_id = server_submit(s, m, vel, n, xp, origin, start, host, iters, static_cast<hipStream_t>(stream));
     });
 }
 

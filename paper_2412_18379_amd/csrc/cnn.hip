@@ -718,21 +718,11 @@ void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision
 void run_predict(cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
                  hipStream_t stream)
 {
-    const size_t need = cnn_workspace_bytes(m.G, precision);
-    {
-        std::lock_guard<std::mutex> lock(m.ws_mutex);
-        if (m.cnn_ws_bytes < need) {
-            if (m.cnn_ws) {
-                hip_check(hipDeviceSynchronize(), "predict workspace");
-                hip_check(hipFree(m.cnn_ws), "predict workspace free");
-                m.cnn_ws = nullptr;
-                m.cnn_ws_bytes = 0;
-            }
-            hip_check(hipMalloc(&m.cnn_ws, need), "predict workspace allocation");
-            m.cnn_ws_bytes = need;
-        }
-    }
-    run_cnn(m.G, vel, w, precision, disp, m.cnn_ws, stream);
+    if (precision != CNNSNS_F32 && precision != CNNSNS_BF16) fail(CNNSNS_EINVAL, "predict: unsupported precision");
+    std::lock_guard<std::mutex> lock(m.ws.mu);
+    workspace_acquire(m.ws, cnn_workspace_bytes(m.G, precision), stream, "predict");
+    run_cnn(m.G, vel, w, precision, disp, m.ws.ptr, stream);
+    workspace_used(m.ws, stream);
 }
 
 }  // namespace cnnsns

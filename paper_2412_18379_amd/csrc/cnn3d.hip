@@ -492,31 +492,16 @@ size_t cnn3_workspace_bytes(int32_t G)
 void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
                   hipStream_t stream)
 {
-    const size_t need = cnn3_workspace_bytes(m.G);
-    {
-        std::lock_guard<std::mutex> lock(m.ws_mutex);
-        if (m.cnn_ws_bytes < need) {
-            if (m.cnn_ws) {
-                hip_check(hipDeviceSynchronize(), "predict3d workspace");
-                hip_check(hipFree(m.cnn_ws), "predict3d workspace free");
-                m.cnn_ws = nullptr;
-                m.cnn_ws_bytes = 0;
-            }
-            if (hipMalloc(&m.cnn_ws, need) != hipSuccess) {
-                m.cnn_ws = nullptr;
-                (void)hipGetLastError();
-                fail(CNNSNS_ENOMEM, "predict3d: workspace of " + std::to_string(need) + " bytes");
-            }
-            m.cnn_ws_bytes = need;
-        }
-    }
+    if (precision != CNNSNS_F32 && precision != CNNSNS_BF16) fail(CNNSNS_EINVAL, "predict3d: unsupported precision");
+    std::lock_guard<std::mutex> lock(m.ws.mu);
+    workspace_acquire(m.ws, cnn3_workspace_bytes(m.G), stream, "predict3d");
     const int32_t G = m.G;
     const int64_t cells = (int64_t)G * G * G;
     const unsigned grid = cnn_persistent_grid();
     const int64_t c1blocks = (int64_t)G * ((G + kC1R - 1) / kC1R) * ((G + kC1W - 1) / kC1W);
     if (c1blocks > (int64_t)UINT32_MAX) fail(CNNSNS_EINVAL, "predict3d: overlay too large");
     const unsigned c1grid = (unsigned)c1blocks;
-    float* act0 = static_cast<float*>(m.cnn_ws);
+    float* act0 = static_cast<float*>(m.ws.ptr);
     float* act1 = act0 + cells * C;
     float* wt2 = act1 + cells * C;
     float* wt3 = wt2 + NWT;
@@ -542,6 +527,7 @@ void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, int3
         k3c_conv4<<<grid, kWaves4 * 64, 0, stream>>>(G, act0, w.w[3], w.b[3], disp);
     }
     hip_check(hipGetLastError(), "predict3d launch");
+    workspace_used(m.ws, stream);
 }
 
 }  // namespace cnnsns

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -45,6 +46,26 @@ struct Error {
 [[noreturn]] void fail(int code, const std::string& msg);
 void hip_check(hipError_t e, const char* what);
 
+// Device workspace a mesh keeps for its CNN forward passes, allocated on the
+// first pass and grown when a larger one is needed.  Passes on one mesh share
+// it, so each pass is ordered on the device after the previous one (an event
+// recorded after the last pass, waited on by the next pass's stream);
+// growing frees the old buffer only after the device has drained.
+struct Workspace {
+    std::mutex mu;
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipEvent_t last_use = nullptr;  // recorded after the last pass that used ptr
+};
+
+// Makes ws.ptr at least `need` bytes and orders `stream` after the previous
+// pass that used it.  Call with ws.mu held; after enqueueing the pass, call
+// workspace_used with the lock still held.
+void workspace_acquire(Workspace& ws, size_t need, hipStream_t stream, const char* what);
+void workspace_used(Workspace& ws, hipStream_t stream);
+// Frees the buffer and the event (the caller has synchronised the device).
+void workspace_release(Workspace& ws);
+
 }  // namespace cnnsns
 
 struct cnnsns_mesh_s {
@@ -58,9 +79,9 @@ struct cnnsns_mesh_s {
     int32_t* lookup = nullptr;       // device [G][G]
     int64_t device_bytes = 0;
     // CNN workspace, allocated on the first cnnsns_predict of this mesh
-    std::mutex ws_mutex;
-    void* cnn_ws = nullptr;
-    size_t cnn_ws_bytes = 0;
+    cnnsns::Workspace ws;
+    // serving jobs submitted on this mesh and not yet complete (destroy refuses while > 0)
+    std::atomic<int64_t> pending_jobs{ 0 };
 };
 
 struct cnnsns_mesh3_s {
@@ -73,9 +94,7 @@ struct cnnsns_mesh3_s {
     int32_t* lookup = nullptr;      // device [G][G][G]
     int64_t device_bytes = 0;
     // 3D CNN workspace, allocated on the first cnnsns_predict3d of this mesh
-    std::mutex ws_mutex;
-    void* cnn_ws = nullptr;
-    size_t cnn_ws_bytes = 0;
+    cnnsns::Workspace ws;
 };
 
 namespace cnnsns {

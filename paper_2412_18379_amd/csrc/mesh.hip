@@ -317,6 +317,8 @@ cnnsns_mesh build_mesh(const double* xy, int64_t n_nodes, const int32_t* tri, in
 void destroy_mesh(cnnsns_mesh m)
 {
     if (!m) return;
+    if (m->pending_jobs.load() > 0)
+        fail(CNNSNS_EBUSY, "destroy_mesh: serving jobs on this mesh are not complete");
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(m->device);
@@ -324,7 +326,7 @@ void destroy_mesh(cnnsns_mesh m)
     (void)hipFree(m->rec);
     (void)hipFree(m->tri);
     (void)hipFree(m->lookup);
-    if (m->cnn_ws) (void)hipFree(m->cnn_ws);
+    workspace_release(m->ws);
     (void)hipSetDevice(cur);
     delete m;
 }

@@ -530,7 +530,7 @@ void destroy_mesh3(cnnsns_mesh3 m)
     (void)hipFree(m->rec);
     (void)hipFree(m->ids);
     (void)hipFree(m->lookup);
-    if (m->cnn_ws) (void)hipFree(m->cnn_ws);
+    workspace_release(m->ws);
     (void)hipSetDevice(cur);
     delete m;
 }

@@ -90,6 +90,7 @@ struct Job {
     const int32_t* start = nullptr;
     int32_t* host = nullptr;
     int32_t* iters = nullptr;
+    hipEvent_t ready = nullptr;  // recorded on the submitter's stream: the job's inputs are written
     size_t footprint = 0;
     int64_t arena_off = -1;
     Clock::time_point t_submit, t_done;
@@ -199,6 +200,8 @@ void launch_batch(cnnsns_server_s& s, const std::vector<uint64_t>& ids)
     hip_check(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "graph instantiate");
     hip_check(hipEventCreateWithFlags(&b.done, hipEventDisableTiming), "event");
     hipStream_t st = s.streams[s.next_stream++ % s.streams.size()];
+    // the batch starts once every job's inputs, written on its submitter's stream, are ready
+    for (uint64_t id : ids) hip_check(hipStreamWaitEvent(st, s.jobs.at(id).ready, 0), "wait for job inputs");
     hip_check(hipGraphLaunch(b.exec, st), "graph launch");
     if (hipEventRecord(b.done, st) != hipSuccess) {
         // the graph is running: its jobs' memory may only be released once it has finished
@@ -214,6 +217,9 @@ void release_batch(cnnsns_server_s& s, Batch& b, Clock::time_point now, int err)
     for (uint64_t id : b.jobs) {
         Job& j = s.jobs.at(id);
         s.arena->release((size_t)j.arena_off, j.footprint);
+        if (j.ready) (void)hipEventDestroy(j.ready);
+        j.ready = nullptr;
+        j.mesh->pending_jobs.fetch_sub(1);
         j.done = true;
         j.error = err;
         j.t_done = now;
@@ -356,7 +362,8 @@ cnnsns_server server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int3
 }
 
 uint64_t server_submit(cnnsns_server s, cnnsns_mesh m, const float* vel, int64_t n, const double* xp,
-                       const double* origin, const int32_t* start, int32_t* host, int32_t* iters)
+                       const double* origin, const int32_t* start, int32_t* host, int32_t* iters,
+                       hipStream_t stream)
 {
     if (m->device != s->device) fail(CNNSNS_EINVAL, "submit: mesh and server are on different devices");
     Job j;
@@ -372,9 +379,19 @@ uint64_t server_submit(cnnsns_server s, cnnsns_mesh m, const float* vel, int64_t
     if ((int64_t)j.footprint > s->budget)
         fail(CNNSNS_ENOMEM, "submit: the job's device footprint (" + std::to_string(j.footprint) +
                                 " bytes) exceeds the server budget");
+    // order the job after the caller's work on its stream (inputs written, outputs initialised)
+    struct EventGuard {
+        hipEvent_t e = nullptr;
+        ~EventGuard() { if (e) (void)hipEventDestroy(e); }
+    } ready;
+    hip_check(hipEventCreateWithFlags(&ready.e, hipEventDisableTiming), "submit event");
+    hip_check(hipEventRecord(ready.e, stream), "submit: event on the caller's stream");
     std::lock_guard<std::mutex> lock(s->mu);
     if (s->stop) fail(CNNSNS_EINVAL, "submit: server is shutting down");
     if ((int32_t)s->queue.size() >= s->queue_depth) fail(CNNSNS_EBUSY, "submit: queue full");
+    j.ready = ready.e;
+    ready.e = nullptr;
+    m->pending_jobs.fetch_add(1);
     j.id = s->next_id++;
     j.t_submit = Clock::now();
     s->jobs.emplace(j.id, j);

@@ -97,7 +97,7 @@ int main(int argc, char** argv)
         const bool empty = d.n == 0;  // an empty job may pass NULL point buffers
         const int rc = cnnsns_submit(s, d.m, d.vel.data(), d.n, empty ? nullptr : d.xp.data(),
                                      empty ? nullptr : d.origin.data(), nullptr, empty ? nullptr : o.host.data(),
-                                     empty ? nullptr : o.iters.data(), &o.id);
+                                     empty ? nullptr : o.iters.data(), nullptr, &o.id);
         expect(rc == CNNSNS_OK, "submit");
         return o;
     };

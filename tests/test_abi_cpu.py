@@ -43,7 +43,7 @@ def test_argument_errors_without_gpu(L):
     assert L.cnnsns_mesh_info(None, None, None, None, None) == C.EINVAL
     assert L.cnnsns_destroy_mesh(None) == C.OK
     assert L.cnnsns_last_error() == b""
-    assert L.cnnsns_submit(None, None, None, 0, None, None, None, None, None, None) == C.EINVAL
+    assert L.cnnsns_submit(None, None, None, 0, None, None, None, None, None, None, None) == C.EINVAL
     assert L.cnnsns_server_destroy(None) == C.OK
 
 
