@@ -242,3 +242,45 @@ def test_unstructured_delaunay_mesh(C, oracle_mod):
     _, rh, rit, rst = oracle_mod.cnnsns(pts, tc, nbr, lk, origin, q, disp.astype(np.float64), fallback=start)
     assert np.array_equal(h.cpu().numpy(), rh) and np.array_equal(it.cpu().numpy(), rit)
     assert np.array_equal(st.cpu().numpy(), rst)
+
+
+def test_full_size_16m_triangles(C, oracle_mod, wl):
+    """The headline configuration: 16M triangles (graded), all 8,003,241 node points, in the launch
+    configuration the benchmark times.  Plain SNS from the elements before movement (Alg. 1), CNN-SNS
+    (Alg. 2) from one fixed displacement grid, the one-step displacement -dt u at the 4096^2 cell
+    centres (an input from the generator, not from the GPU), and the ASG start at x_p: host, I_t and
+    status of every point equal the oracle's bit for bit."""
+    import time
+    t0 = time.perf_counter()
+    w = wl.build("c3")
+    print(f"[c3] {w.n_tri} triangles, {w.n_points} points, G={w.G} ({time.perf_counter() - t0:.1f}s)", flush=True)
+    mesh = C.Mesh(w.xy, w.tri, overlay_side=w.G)
+    tc, nbr = oracle_mod.prepare_mesh(w.xy, w.tri)
+    xp, start = _dev(w.xp), _dev(w.start)
+    h, it, st = C.locate(mesh, xp, start=start)
+    torch.cuda.synchronize()
+    oh, oi, os_ = oracle_mod.sns(w.xy, tc, nbr, w.xp, w.start)
+    print(f"[c3] plain: oracle mean I_t {oi.mean():.2f} ({time.perf_counter() - t0:.1f}s)", flush=True)
+    assert np.array_equal(h.cpu().numpy(), oh)
+    assert np.array_equal(it.cpu().numpy(), oi)
+    assert np.array_equal(st.cpu().numpy(), os_)
+    assert np.all(os_ == C.FOUND)
+
+    disp = (-w.dt * w.vel.astype(np.float64)).astype(np.float32)
+    lk = oracle_mod.lookup(w.xy, tc, w.G)
+    h2, it2, st2 = C.locate(mesh, xp, start=start, origin=_dev(w.origins), disp=_dev(disp))
+    torch.cuda.synchronize()
+    _, oh2, oi2, os2 = oracle_mod.cnnsns(w.xy, tc, nbr, lk, w.origins, w.xp, disp, fallback=w.start)
+    print(f"[c3] CNN-SNS: oracle mean I_t {oi2.mean():.2f} ({time.perf_counter() - t0:.1f}s)", flush=True)
+    assert np.array_equal(h2.cpu().numpy(), oh2)
+    assert np.array_equal(it2.cpu().numpy(), oi2)
+    assert np.array_equal(st2.cpu().numpy(), os2)
+    assert np.array_equal(oh2, oh)  # the start never changes the host here
+
+    h3, it3, st3 = C.locate(mesh, xp)
+    torch.cuda.synchronize()
+    _, oh3, oi3, os3 = oracle_mod.cnnsns(w.xy, tc, nbr, lk, w.xp, w.xp, np.zeros_like(disp))
+    assert np.array_equal(h3.cpu().numpy(), oh3)
+    assert np.array_equal(it3.cpu().numpy(), oi3)
+    assert np.array_equal(st3.cpu().numpy(), os3)
+    mesh.close()
