@@ -144,6 +144,24 @@ int cnnsns_predict(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t
                    void* stream);
 
 /*
+ * cnnsns_predict for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same forward pass, same kernels and same results, with its workspace
+ * in a preallocated array of 32 MiB + 128 KiB per GPU that the library holds until the
+ * process ends, instead of the mesh's workspace.  Makes no hipMalloc,
+ * hipFree or other allocating call.  Every call on one GPU uses that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race
+ * and give wrong results; a call may follow another on the same stream.
+ *   precision  CNNSNS_F32 (workspace 128 G^2 bytes + 128 KiB: G <= 512) or
+ *              CNNSNS_BF16 (40 KiB: any G).
+ * Other arguments as in cnnsns_predict.  Asynchronous on `stream`.  Errors:
+ * EINVAL (null argument, precision, or a workspace beyond the array's
+ * size), EHIP.
+ */
+int cnnsns_predict_noalloc(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t precision, float* disp,
+                           void* stream);
+
+/*
  * Locate n points (Alg. 1 for every point; Alg. 2 when a displacement grid is
  * given).  All arrays are DEVICE memory:
  *   xp      FP64 [n][2] query points x_p (departure points).

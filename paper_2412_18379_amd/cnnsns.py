@@ -22,7 +22,8 @@ F32, BF16, FP8E4M3 = 0, 1, 2
 PRECISIONS = {"f32": F32, "bf16": BF16, "fp8": FP8E4M3}
 
 EXPORTS = (
-    "cnnsns_build_mesh", "cnnsns_mesh_info", "cnnsns_destroy_mesh", "cnnsns_predict", "cnnsns_locate",
+    "cnnsns_build_mesh", "cnnsns_mesh_info", "cnnsns_destroy_mesh", "cnnsns_predict", "cnnsns_predict_noalloc",
+    "cnnsns_locate",
     "cnnsns_interpolate", "cnnsns_build_mesh3d", "cnnsns_mesh3d_info", "cnnsns_destroy_mesh3d", "cnnsns_predict3d",
     "cnnsns_locate3d", "cnnsns_interpolate3d",
     "cnnsns_server_create", "cnnsns_submit", "cnnsns_poll", "cnnsns_wait", "cnnsns_server_destroy",
@@ -56,6 +57,7 @@ def lib():
                                  ctypes.POINTER(ctypes.c_double)],
             "cnnsns_destroy_mesh": [vp],
             "cnnsns_predict": [vp, vp, ctypes.POINTER(_Cnn), i32, vp, vp],
+            "cnnsns_predict_noalloc": [vp, vp, ctypes.POINTER(_Cnn), i32, vp, vp],
             "cnnsns_locate": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp],
             "cnnsns_interpolate": [vp, i64, vp, vp, vp, vp, vp],
             "cnnsns_build_mesh3d": [vp, i64, vp, i64, i32, vp, ctypes.POINTER(vp)],
@@ -168,6 +170,19 @@ def predict(mesh: Mesh, vel: torch.Tensor, weights: Weights, precision="f32", di
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     _check(lib().cnnsns_predict(mesh.handle, _ptr(vel), ctypes.byref(weights.struct), p, _ptr(disp),
                                 _stream(stream)))
+    return disp
+
+
+def predict_noalloc(mesh: Mesh, vel: torch.Tensor, weights: Weights, disp: torch.Tensor, precision="bf16",
+                    stream=None) -> torch.Tensor:
+    """The forward pass with the library's preallocated per-GPU workspace (cnnsns_predict_noalloc):
+    no device allocation; calls overlapping on one GPU race.  `disp` is caller-allocated."""
+    G = mesh.G
+    _need(vel, torch.float32, (2, G, G), "vel")
+    _need(disp, torch.float32, (2, G, G), "disp")
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().cnnsns_predict_noalloc(mesh.handle, _ptr(vel), ctypes.byref(weights.struct), p, _ptr(disp),
+                                        _stream(stream)))
     return disp
 
 

@@ -147,6 +147,18 @@ int cnnsns_predict(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t
     });
 }
 
+int cnnsns_predict_noalloc(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t precision, float* disp,
+                           void* stream)
+{
+    return guarded([&] {
+        if (!m || !vel || !w || !disp) fail(CNNSNS_EINVAL, "predict_noalloc: NULL argument");
+        for (int l = 0; l < 4; ++l)
+            if (!w->w[l] || !w->b[l]) fail(CNNSNS_EINVAL, "predict_noalloc: NULL weight or bias pointer");
+        DeviceScope ds(m->device);
+        run_predict_noalloc(*m, vel, *w, precision, disp, static_cast<hipStream_t>(stream));
+    });
+}
+
 int cnnsns_locate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* start, const double* origin,
                   const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status, void* stream)
 {

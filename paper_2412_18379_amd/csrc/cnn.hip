@@ -715,6 +715,54 @@ void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision
     hip_check(hipGetLastError(), "predict launch");
 }
 
+// Workspace of the forward passes that may not allocate (cnnsns_predict_noalloc): one
+// array per GPU, held until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device, never by its name.
+constexpr size_t kScratchBytes = ((size_t)32 << 20) + ((size_t)128 << 10);  // the FP32 pass at G = 512
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The calling thread's current device's copy of `scratch`, looked up once per device.
+void* scratch_for_current_device()
+{
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) fail(CNNSNS_EINVAL, "predict_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "predict_noalloc: scratch address");
+        if (!p) fail(CNNSNS_EHIP, "predict_noalloc: scratch address is NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+size_t cnn_scratch_bytes()
+{
+    return kScratchBytes;
+}
+
+void run_predict_noalloc(const cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision,
+                         float* disp, hipStream_t stream)
+{
+    if (precision != CNNSNS_F32 && precision != CNNSNS_BF16)
+        fail(CNNSNS_EINVAL, "predict_noalloc: precision must be CNNSNS_F32 or CNNSNS_BF16");
+    const size_t need = cnn_workspace_bytes(m.G, precision);
+    if (need > kScratchBytes)
+        fail(CNNSNS_EINVAL, "predict_noalloc: this overlay needs a workspace of " + std::to_string(need) +
+                                " bytes, more than the " + std::to_string(kScratchBytes) +
+                                " bytes of the preallocated one (FP32 takes G <= 512; BF16 any G)");
+    run_cnn(m.G, vel, w, precision, disp, scratch_for_current_device(), stream);
+}
+
 void run_predict(cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
                  hipStream_t stream)
 {

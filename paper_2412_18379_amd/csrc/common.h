@@ -138,5 +138,9 @@ void cnn_bf16_forward(int32_t G, const float* vel, const void* packed, const cnn
                       unsigned grid, hipStream_t stream);
 void run_predict(cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
                  hipStream_t stream);
+// the same pass with the preallocated per-device workspace (no allocation)
+size_t cnn_scratch_bytes();
+void run_predict_noalloc(const cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision,
+                         float* disp, hipStream_t stream);
 
 }  // namespace cnnsns

@@ -38,6 +38,7 @@ extern "C" int mock_failures();
 extern "C" long mock_live_device_bytes();
 extern "C" long mock_live_handles();
 extern "C" long mock_launches();
+extern "C" long mock_mallocs();
 
 namespace {
 
@@ -416,6 +417,31 @@ void scenario_mesh3d()
     for (void* p : { (void*)vel, (void*)disp, (void*)xp, (void*)host, (void*)nodal, (void*)out }) (void)hipFree(p);
 }
 
+// the no-allocation forward pass: no hipMalloc from its first call on, two meshes
+// (the second with a smaller overlay), both precisions, FP32 refused beyond its size
+void scenario_noalloc()
+{
+    Weights W(2);
+    Job a = make_job(grid_mesh(60), 512, nullptr), b = make_job(grid_mesh(20), 64, nullptr),
+        c = make_job(grid_mesh(20), 1024, nullptr);
+    float* disp = dev_alloc<float>(2 * 1024 * 1024);
+    const long before = mock_mallocs();
+    for (int rep = 0; rep < 3; ++rep)
+        for (Job* j : { &a, &b })
+            for (int prec : { CNNSNS_BF16, CNNSNS_F32 })
+                EXPECT(cnnsns_predict_noalloc(j->m, j->vel, &W.w, prec, disp, nullptr) == CNNSNS_OK, "noalloc");
+    EXPECT(cnnsns_predict_noalloc(c.m, c.vel, &W.w, CNNSNS_BF16, disp, nullptr) == CNNSNS_OK, "noalloc bf16 G=1024");
+    EXPECT(cnnsns_predict_noalloc(c.m, c.vel, &W.w, CNNSNS_F32, disp, nullptr) == CNNSNS_EINVAL,
+           "noalloc f32 beyond the scratch size");
+    EXPECT(cnnsns_predict_noalloc(c.m, c.vel, &W.w, CNNSNS_FP8E4M3, disp, nullptr) == CNNSNS_EINVAL, "noalloc fp8");
+    EXPECT(mock_mallocs() == before, "no device allocation");
+    (void)hipDeviceSynchronize();
+    (void)hipFree(disp);
+    free_job(a);
+    free_job(b);
+    free_job(c);
+}
+
 }  // namespace
 
 int main(int argc, char** argv)
@@ -434,6 +460,8 @@ int main(int argc, char** argv)
         scenario_predict_mt((int)arg(2, 200));
     else if (sc == "mesh3d")
         scenario_mesh3d();
+    else if (sc == "noalloc")
+        scenario_noalloc();
     else {
         std::fprintf(stderr, "unknown scenario %s\n", sc.c_str());
         return 2;

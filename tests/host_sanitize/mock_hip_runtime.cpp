@@ -115,6 +115,10 @@ struct State {
     std::set<Capture*> captures;     // open captures
     MStream null_stream;             // the legacy null stream
     std::map<const void*, std::string> kernels;  // host stub -> kernel name
+    std::map<const void*, size_t> vars;          // device variable shadow -> size
+    std::map<const void*, char*> var_copies;     // its device copy (looked up once)
+    long static_bytes = 0;                       // held by device variables until exit
+    long mallocs = 0;                            // hipMalloc calls
     bool stop = false;
     std::thread device;
     State();
@@ -305,13 +309,19 @@ extern "C" long mock_live_device_bytes()
     std::lock_guard<std::mutex> lk(g_mu);
     long b = 0;
     for (auto& a : g_allocs) b += (long)a.second;
-    return b;
+    return b - mock_state().static_bytes;
 }
 
 extern "C" long mock_live_handles()
 {
     std::lock_guard<std::mutex> lk(g_mu);
     return (long)(g_streams.size() + g_events.size() + g_graphs.size());
+}
+
+extern "C" long mock_mallocs()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return mock_state().mallocs;
 }
 
 extern "C" long mock_launches()
@@ -336,7 +346,30 @@ extern "C" void __hipRegisterFunction(void**, const void* hostFunction, char*, c
 
 extern "C" void __hipUnregisterFatBinary(void**) {}
 
-extern "C" void __hipRegisterVar(void**, void*, char*, char*, int, size_t, int, int) {}
+// device variables: host shadow address -> size; their device copies, made on first lookup
+extern "C" void __hipRegisterVar(void**, void* var, char*, char*, int, size_t size, int, int)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    mock_state().vars[var] = size;
+}
+
+hipError_t hipGetSymbolAddress(void** p, const void* symbol)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = mock_state().vars.find(symbol);
+    if (it == mock_state().vars.end()) {
+        failure("hipGetSymbolAddress of an unregistered symbol");
+        return set_err(hipErrorInvalidSymbol);
+    }
+    auto& copy = mock_state().var_copies[symbol];
+    if (!copy) {
+        copy = static_cast<char*>(std::aligned_alloc(256, (it->second + 255) / 256 * 256));
+        g_allocs[copy] = it->second;
+        mock_state().static_bytes += (long)it->second;
+    }
+    *p = copy;
+    return hipSuccess;
+}
 
 hipError_t __hipPushCallConfiguration(dim3 gridDim, dim3 blockDim, size_t sharedMem, hipStream_t stream)
 {
@@ -465,6 +498,7 @@ hipError_t hipMalloc(void** p, size_t n)
     if (!q) return set_err(hipErrorOutOfMemory);
     std::lock_guard<std::mutex> lk(g_mu);
     g_allocs[q] = std::max<size_t>(n, 1);
+    ++mock_state().mallocs;
     *p = q;
     return hipSuccess;
 }

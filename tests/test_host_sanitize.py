@@ -75,6 +75,7 @@ SCENARIOS = [
     ("serve", "2"),
     ("predict_mt", "150"),
     ("mesh3d",),
+    ("noalloc",),
 ]
 
 
