@@ -32,10 +32,29 @@ if ROOT not in sys.path:
 
 PEAK = {"hbm_GBps": 8000.0, "f32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0, "fp8_TFLOPs": 5000.0}
 CNN_MACS_PER_PIXEL = 2 * 32 * 9 + 32 * 32 * 9 * 2 + 32 * 2 * 9  # 19,584
-# matrix-core MACs per overlay cell of the FP32 path: conv1 (K 20 x N 32, on the 18 x 34 input tile of a
-# 16 x 32 region: x 612/512), conv2 and conv3 (16 x 32 x 32 per 2 x 2 block; conv3 on the 16 x 32 region of a
-# 14 x 30 output tile: x 512/420), conv4 (K 32 x N 32 per region pixel: x 512/420)
-EXEC_MACS_PER_PIXEL_F32 = round(20 * 32 * 612 / 512 + 4096 + 4096 * 512 / 420 + 32 * 32 * 512 / 420)
+# Winograd F(2x2,3x3) multiplies per output pixel and channel pair: 16 per 2 x 2 block; the MACs it
+# saves are not counted as useful work
+WINO_USEFUL_MACS_PER_PIXEL = 2 * 32 * 9 + 2 * 32 * 32 * 4 + 32 * 2 * 9  # 9,344
+
+
+def cnn_issued_macs(G: int, precision: str) -> float:
+    """Matrix-core MACs one forward pass issues over a G x G overlay, padding and recomputed halos
+    included (per tile, as the kernels are written)."""
+    def cdiv(a, b):
+        return -(-a // b)
+    if precision == "f32":
+        regions12 = cdiv(G, 32) * cdiv(G, 16)  # 16 x 32 regions: conv1 (K 18 -> 20) on the 39 M-blocks of
+        tiles34 = cdiv(G, 30) * cdiv(G, 14)    # the 18 x 34 input tile, then conv2 as Winograd F(2x2,3x3);
+        # 14 x 30 output tiles: conv3 as Winograd on their 16 x 32 region, conv4 as 16 matrix columns
+        return (regions12 * (624 * 20 * 32 + 128 * 16 * 32 * 32) +
+                tiles34 * (128 * 16 * 32 * 32 + 512 * 32 * 16))
+    if precision == "bf16":
+        tiles = cdiv(G, 30) * cdiv(G, 14)  # fused 14 x 30 output tiles: conv1 (K 32) on 20 x 36 pixels,
+        # conv2 on 40 M-blocks (18 x 34 pixels), conv3 on 32 (16 x 32), conv4 as 32 columns of K 32
+        return tiles * (720 * 32 * 32 + 640 * 288 * 32 + 512 * 288 * 32 + 512 * 32 * 32)
+    raise ValueError(precision)
+
+
 REC_BYTES = 60  # algorithmic bytes of one element record: 6 FP64 coordinates + 3 int32 neighbours
 # one tetrahedron record: 12 FP64 coordinates, 4 int32 neighbours and the 4 int32 node ids that put
 # each face's nodes in a fixed order
@@ -632,22 +651,27 @@ def main():
     bytes_plain = REC_BYTES * float(it_p.sum()) + n * (16 + 4 + out_b)
     gbps_cnn_walk = bytes_cnn_walk / (loc_ms.mean() / 1e3) / 1e9
     gbps_plain = bytes_plain / (plain_ms.mean() / 1e3) / 1e9
+    issued_tf = 2.0 * cnn_issued_macs(G, precision) / (pred_ms.mean() / 1e3) / 1e12
+    useful_macs = (WINO_USEFUL_MACS_PER_PIXEL if precision == "f32" else CNN_MACS_PER_PIXEL) * G * G
     roofline = {
         "kernel": {"f32": "cnn forward (k_conv12_f32 + k_conv34_f32, one cnnsns_predict)",
                    "bf16": "cnn forward (k_cnn_bf16, one cnnsns_predict)"}.get(precision, "cnn forward"),
-        "bound": "mfma", "achieved": round(cnn_tf, 3), "peak": cnn_peak, "unit": "TFLOP/s",
-        "frac": round(cnn_tf / cnn_peak, 4),
+        "bound": "mfma", "achieved": round(issued_tf, 3), "peak": cnn_peak, "unit": "TFLOP/s",
+        "frac": round(issued_tf / cnn_peak, 4),
         "traffic": traffic_for(f"cnn_forward_{precision}", args.workload),
-        "algorithmic_per_launch": f"{cnn_flops:.4e} FLOP (2 x 19584 MAC x G^2, G={G}, direct convolution)",
+        "algorithmic_per_launch": (f"{2 * cnn_issued_macs(G, precision):.4e} FLOP issued on the matrix cores "
+                                   f"(G={G}: {cnn_issued_macs(G, precision) / (G * G):.0f} MAC per cell with "
+                                   f"padding, recomputed halos and, in FP32, the Winograd form)"),
+        "useful_work": {"macs_per_cell": useful_macs // (G * G),
+                        "achieved": round(2.0 * useful_macs / (pred_ms.mean() / 1e3) / 1e12, 3),
+                        "frac": round(2.0 * useful_macs / (pred_ms.mean() / 1e3) / 1e12 / cnn_peak, 4),
+                        "note": "the products the method needs: " + (
+                            "Winograd F(2x2,3x3) for conv2/conv3, direct for conv1/conv4" if precision == "f32"
+                            else "direct convolution")},
+        "direct_conv_equivalent": {"macs_per_cell": CNN_MACS_PER_PIXEL, "achieved": round(cnn_tf, 3),
+                                   "note": "2 x 19584 MAC x G^2 over the pass time; exceeds the matrix "
+                                           "cores' work when conv2/conv3 run as Winograd"},
     }
-    if precision == "f32":
-        # the 32 -> 32 layers run as Winograd F(2x2,3x3): 16 products per 2x2 block and channel pair
-        executed = 2.0 * EXEC_MACS_PER_PIXEL_F32 * G * G / (pred_ms.mean() / 1e3) / 1e12
-        roofline["executed_matrix_work"] = {
-            "macs_per_cell": EXEC_MACS_PER_PIXEL_F32, "achieved": round(executed, 3),
-            "frac": round(executed / cnn_peak, 4),
-            "note": "matrix-core MACs actually issued (conv1 K padded to 20, conv2/conv3 in the Winograd "
-                    "domain, conv4 as 32 columns); 'achieved' above counts the direct-convolution FLOPs"}
     # interpolation: x_p 16 + host 4 + element coordinates 48 and node ids 12 + three nodal values 48
     # + the result 16 bytes per point
     bytes_interp = n * (16 + 4 + 48 + 12 + 48 + 16)
@@ -734,9 +758,16 @@ def main():
             "mean_path_length": round(float(it_b.mean()), 3),
             "mean_path_change_vs_f32": round(float(it_b.mean() - it_c.mean()), 4),
             "host_agreement_with_f32_path": float(np.mean(host_b.cpu().numpy() == host_c)),
-            "cnn_roofline": {"achieved": round(cnn_flops / (pb.mean() / 1e3) / 1e12, 3),
+            "cnn_roofline": {"achieved": round(2.0 * cnn_issued_macs(G, "bf16") / (pb.mean() / 1e3) / 1e12, 3),
                              "peak": PEAK["bf16_TFLOPs"], "unit": "TFLOP/s",
-                             "frac": round(cnn_flops / (pb.mean() / 1e3) / 1e12 / PEAK["bf16_TFLOPs"], 4),
+                             "frac": round(2.0 * cnn_issued_macs(G, "bf16") / (pb.mean() / 1e3) / 1e12 /
+                                           PEAK["bf16_TFLOPs"], 4),
+                             "algorithmic_per_launch": (f"{2 * cnn_issued_macs(G, 'bf16'):.4e} FLOP issued "
+                                                        f"({cnn_issued_macs(G, 'bf16') / (G * G):.0f} MAC per "
+                                                        f"cell with padding and recomputed halos)"),
+                             "useful_work": {"macs_per_cell": CNN_MACS_PER_PIXEL,
+                                             "frac": round(cnn_flops / (pb.mean() / 1e3) / 1e12 /
+                                                           PEAK["bf16_TFLOPs"], 4)},
                              "traffic": traffic_for("cnn_forward_bf16", args.workload)},
         }
         log(f"BF16 CNN-SNS: {res['bf16_variant']['ms_per_step']:.3f} ms/step (predict {pb.mean():.3f} ms), "

@@ -12,6 +12,16 @@
     python -m paper_2412_18379_amd.profiling stats <kernel_stats.csv> <out.md> "<command>" [+names|-names]
     python -m paper_2412_18379_amd.profiling traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
         <copy_write.csv> <copy_bytes> <workload> <traffic.json> "<command>" name=kernel[*k][+kernel[*k]] ...
+    python -m paper_2412_18379_amd.profiling counters <out.md> <kernel_stats.csv> "<commands>" \
+        <counter_collection.csv> [more counter csvs] -- substring[,substring ...]
+
+* ``counters``: per kernel (name containing one of the substrings), the mean
+  per dispatch of every counter in the given --pmc runs, the mean duration
+  from a --kernel-trace --stats run, and what follows from them: the
+  matrix-core busy fraction (MfmaUtil), the matrix FLOPs per dispatch
+  (MfmaFlopsF32 / MfmaFlopsBF16, 512 per MOP) and their rate against the
+  duration, and HBM-side read bytes from the TCC/EA read requests counted
+  by size (TCC_EA0_RDREQ_32B / _64B / _128B), with the share sent to DRAM.
 
   (a kernel is named by substrings of its full name joined with "&"; "*k"
   counts it k times per launch of the group)
@@ -148,6 +158,63 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, wo
     return db
 
 
+def _counter_table(csv_paths):
+    """{kernel: {counter: mean per dispatch}} over one or more --pmc CSVs."""
+    tot, cnt = defaultdict(lambda: defaultdict(float)), defaultdict(lambda: defaultdict(int))
+    for path in csv_paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                k, c = r["Kernel_Name"], r["Counter_Name"]
+                tot[k][c] += float(r["Counter_Value"])
+                cnt[k][c] += 1
+    return {k: {c: tot[k][c] / cnt[k][c] for c in tot[k]} for k in tot}
+
+
+def counters(out_path, stats_csv, command, csv_paths, select):
+    table = _counter_table(csv_paths)
+    durations = {}
+    with open(stats_csv) as f:
+        for r in csv.DictReader(f):
+            durations[r["Name"]] = float(r["AverageNs"])
+    keys = select.split(",")
+    names = sorted((k for k in table if any(s in k for s in keys)), key=lambda k: _short(k))
+    lines = [f"Commands: `{command}`", "",
+             "| kernel | mean (us) | MFMA busy | MFMA TFLOP/dispatch (F32 / BF16) | MFMA TFLOP/s | "
+             "VALU instr / dispatch | HBM-side read bytes / dispatch | to DRAM |",
+             "|---|---|---|---|---|---|---|---|"]
+    out = {}
+    for k in names:
+        c = table[k]
+        dur = durations.get(k)
+        f32, b16 = c.get("MfmaFlopsF32"), c.get("MfmaFlopsBF16")
+        flops = (f32 or 0.0) + (b16 or 0.0)
+        rate = flops / (dur * 1e-9) / 1e12 if dur and flops else None
+        rd = None
+        if "TCC_EA0_RDREQ_128B_sum" in c and "TCC_EA0_RDREQ_64B_sum" in c:
+            rd = (128 * c["TCC_EA0_RDREQ_128B_sum"] + 64 * c["TCC_EA0_RDREQ_64B_sum"] +
+                  32 * c.get("TCC_EA0_RDREQ_32B_sum", 0.0))
+        dram = (c["TCC_EA0_RDREQ_DRAM_sum"] / c["TCC_EA0_RDREQ_sum"]
+                if c.get("TCC_EA0_RDREQ_sum") and "TCC_EA0_RDREQ_DRAM_sum" in c else None)
+        row = {"mean_us": dur / 1e3 if dur else None, "mfma_util": c.get("MfmaUtil"),
+               "mfma_flops_f32": f32, "mfma_flops_bf16": b16, "mfma_tflops": rate,
+               "valu_insts": c.get("SQ_INSTS_VALU"), "read_bytes": rd, "dram_share": dram,
+               "counters": {n: round(v, 3) for n, v in sorted(c.items())}}
+        out[_short(k)] = row
+
+        def fmt(v, spec):
+            return "—" if v is None else format(v, spec)
+        lines.append(f"| `{_short(k)}` | {fmt(row['mean_us'], '.1f')} | "
+                     f"{fmt(row['mfma_util'] and row['mfma_util'] / 100, '.3f')} | "
+                     f"{fmt(f32 and f32 / 1e12, '.4f')} / {fmt(b16 and b16 / 1e12, '.4f')} | {fmt(rate, '.1f')} | "
+                     f"{fmt(row['valu_insts'], '.4g')} | {fmt(rd, '.4g')} | {fmt(dram, '.3f')} |")
+    text = "\n".join(lines) + "\n"
+    with open(out_path, "w") as f:
+        f.write(text)
+    with open(os.path.splitext(out_path)[0] + ".json", "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    return text
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats(sys.argv[2], sys.argv[3], sys.argv[4], select=sys.argv[5] if len(sys.argv) > 5 else ""))
@@ -158,5 +225,9 @@ if __name__ == "__main__":
             k, v = g.split("=", 1)
             groups[k] = v.split("+")
         print(json.dumps(traffic(a[0], a[1], a[2], a[3], int(a[4]), a[5], a[6], a[7], groups), indent=1))
+    elif sys.argv[1] == "counters":
+        a = sys.argv[2:]
+        sep = a.index("--")
+        print(counters(a[0], a[1], a[2], a[3:sep], a[sep + 1]))
     else:
         raise SystemExit(__doc__)
