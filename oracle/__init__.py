@@ -32,6 +32,16 @@ Parity status of each function (what pins it, see ``tests/test_oracle_*.py``):
   cnnsns3_start             - zero displacement at cell centres gives the
                               lookup; clamping; x = 1 maps to cell G-1;
                               fallback of empty cells
+  cls_pool                  - exact-rational means of the centroids per cell;
+                              empty cells give their centre; independent of
+                              the node order within a triangle
+  cls_features              - closed forms on a structured grid (features of
+                              a point at a pooled centroid, one-cell shifts,
+                              the window replicated at the boundary)
+  cls_forward               - the same network in torch float64 (conv2d,
+                              avg_pool2d, linear, softmax); hand-built nets
+                              with closed-form classes (ties to the lowest)
+  cls_start, cls_label      - closed-form cells on hand-made cases
 """
 from __future__ import annotations
 
@@ -92,6 +102,11 @@ def _L():
             "orc3_cnn_window": [i32, vp, vp, vp, vp, vp, vp, vp],
             "orc3_interp": [i64, vp, vp, vp, i64, vp, vp, vp],
             "orc3_cnnsns_start": [i64, vp, i32, vp, vp, vp, vp],
+            "orc_cls_pool": [i64, vp, i64, vp, i32, vp],
+            "orc_cls_features": [i64, vp, i32, vp, vp, vp],
+            "orc_cls_forward": [i64, vp, vp, vp, vp, vp, vp, vp],
+            "orc_cls_start": [i64, vp, i32, vp, vp, vp, vp],
+            "orc_cls_label": [i64, vp, i32, vp, i64, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -351,3 +366,79 @@ def interpolate3(xyz, tet_pos, nodal, xp, host):
     _check(_L().orc3_interp(tet_pos.shape[0], _p(xyz), _p(tet_pos), _p(nodal), xp.shape[0], _p(xp), _p(host),
                             _p(out)), "interpolate3")
     return out
+
+
+# ---------------------------------------------------------------------------- the classifier CNN (Sec. 2.3)
+
+CLS_W, CLS_NA = 9, 81
+CLS_SHAPES = [(16, 2, 3, 3), (16, 16, 3, 3), (256, 2), (256, 256), (512, 512), (81, 512)]
+
+
+def cls_pool(xy, tri, G: int):
+    """Average-pooled ASG grid [G][G][2]: per overlay cell the mean centroid of the elements whose centroid
+    lies in it (ascending element id), or the cell centre."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    out = np.empty((G, G, 2), np.float64)
+    _check(_L().orc_cls_pool(xy.shape[0], _p(xy), tri.shape[0], _p(tri), int(G), _p(out)), "cls_pool")
+    return out
+
+
+def cls_features(xp, pool):
+    """Network inputs: feat FP32 [n][2][9][9] (G (pooled centroid - x_p) over the 9 x 9 window) and xoff FP32
+    [n][2] (x_p's offset in its cell)."""
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    pool = np.ascontiguousarray(pool, dtype=np.float64)
+    n, G = xp.shape[0], pool.shape[0]
+    feat = np.empty((n, 2, CLS_W, CLS_W), np.float32)
+    xoff = np.empty((n, 2), np.float32)
+    _check(_L().orc_cls_features(n, _p(xp), int(G), _p(pool), _p(feat), _p(xoff)), "cls_features")
+    return feat, xoff
+
+
+def cls_forward(feat, xoff, ws, bs):
+    """(logits FP64 [n][81], probabilities FP64 [n][81], class int32 [n])."""
+    feat = np.ascontiguousarray(feat, dtype=np.float32)
+    xoff = np.ascontiguousarray(xoff, dtype=np.float32)
+    ws = [np.ascontiguousarray(x, dtype=np.float32) for x in ws]
+    bs = [np.ascontiguousarray(x, dtype=np.float32) for x in bs]
+    if [tuple(w.shape) for w in ws] != CLS_SHAPES or [b.shape[0] for b in bs] != [s[0] for s in CLS_SHAPES]:
+        raise ValueError("cls_forward: weights of the 2-16-16 conv / 2-256-256 / 512-512-81 net expected")
+    n = feat.shape[0]
+    wp = (ctypes.c_void_p * 6)(*[x.ctypes.data for x in ws])
+    bp = (ctypes.c_void_p * 6)(*[x.ctypes.data for x in bs])
+    logits = np.empty((n, CLS_NA), np.float64)
+    prob = np.empty((n, CLS_NA), np.float64)
+    cls = np.empty(n, np.int32)
+    _check(_L().orc_cls_forward(n, _p(feat), _p(xoff), wp, bp, _p(logits), _p(prob), _p(cls)), "cls_forward")
+    return logits, prob, cls
+
+
+def cls_start(xp, lookup_grid, cls, fallback=None):
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    lk = np.ascontiguousarray(lookup_grid, dtype=np.int32)
+    cls = np.ascontiguousarray(cls, dtype=np.int32)
+    fb = None if fallback is None else np.ascontiguousarray(fallback, dtype=np.int32)
+    out = np.empty(xp.shape[0], np.int32)
+    _check(_L().orc_cls_start(xp.shape[0], _p(xp), lk.shape[0], _p(lk), _p(cls), _p(fb), _p(out)), "cls_start")
+    return out
+
+
+def cls_label(xp, G: int, xy, tri, host):
+    """Training labels from SNS hosts: the window class of the cell holding the host's centroid."""
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    host = np.ascontiguousarray(host, dtype=np.int32)
+    out = np.empty(xp.shape[0], np.int32)
+    _check(_L().orc_cls_label(xp.shape[0], _p(xp), int(G), _p(xy), tri.shape[0], _p(tri), _p(host), _p(out)),
+           "cls_label")
+    return out
+
+
+def cls_classify(xy, tri, lookup_grid, xp, ws, bs, fallback=None):
+    """The classifier's prediction step of Alg. 2 end to end: (class, K_p, logits)."""
+    G = lookup_grid.shape[0]
+    feat, xoff = cls_features(xp, cls_pool(xy, tri, G))
+    logits, _, cls = cls_forward(feat, xoff, ws, bs)
+    return cls, cls_start(xp, lookup_grid, cls, fallback), logits

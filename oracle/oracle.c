@@ -882,3 +882,250 @@ int orc3_cnnsns_start(int64_t n, const double* origin, int32_t G, const double* 
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The paper's classifier CNN (Sec. 2.3, eq. 7-8, Alg. 2's prediction step), */
+/* in 2D on the overlay grid.                                                */
+/*
+ * Input preparation (Sec. 2.3):
+ *  - each element is represented by its centroid (the paper's "barycentric
+ *    coordinates" x_l^*): the mean of its vertices, summed with the vertices
+ *    in ascending node id, ((x_a + x_b) + x_c) / 3;
+ *  - the ASG filter assigns each element to the overlay cell holding its
+ *    centroid, and average pooling gives each cell one value: the mean of the
+ *    centroids assigned to it (summed in ascending element id, divided by
+ *    their count), or the cell centre when none is;
+ *  - the filtered region around x_p is the W x W block of cells centred on
+ *    the cell of x_p (W = 9, N_a = 81 classes); the padding layer extends the
+ *    grid at its boundary (a cell index outside [0, G) takes the nearest
+ *    cell's value);
+ *  - network input: per window cell, G (pooled centroid - x_p), both
+ *    components, rounded to FP32 (channel 0 x, channel 1 y, [2][9][9]); and
+ *    x_p's offset in its own cell, x_p G - (cell + 1/2) per axis, rounded to
+ *    FP32.
+ * Network (Fig. 2's sizes are missing; chosen here): module 1: conv 3x3
+ * 2 -> 16, ReLU, conv 3x3 16 -> 16, ReLU (zero "same" padding), 2 x 2 average
+ * pooling (stride 2, the last row and column dropped: 4 x 4), flattened in
+ * [channel][row][col] order (256); module 2: FC 2 -> h1 = 256, ReLU, FC
+ * 256 -> 256, ReLU; concatenation [module 1, module 2] (512); FC 512 -> h2 =
+ * 512, ReLU; FC 512 -> N_a = 81: the logits H_l; B_l = softmax(H)_l; the class
+ * is the l of the largest B_l, the lowest l on ties (eq. 8's "max" read as
+ * argmax).  Class l = (dy + 4) 9 + (dx + 4) is the window cell at offset
+ * (dx, dy) from the cell of x_p, and K_p is the overlay lookup element of that
+ * cell (clamped to the grid), or the fallback start (else element 0) where the
+ * cell has none.
+ * Weights are FP32 in PyTorch layouts (conv [out][in][3][3], FC [out][in]),
+ * widened exactly to FP64.
+ */
+#define CLS_W 9
+#define CLS_R 4
+#define CLS_NA (CLS_W * CLS_W)
+#define CLS_C 16
+#define CLS_P 4
+#define CLS_H1 256
+#define CLS_H2 512
+#define CLS_F (CLS_C * CLS_P * CLS_P)
+
+static int64_t clamp_cell(int64_t c, int32_t G)
+{
+    return c < 0 ? 0 : (c >= G ? G - 1 : c);
+}
+
+/* centroid of triangle t, vertices summed in ascending node id */
+static void centroid_by_id(const double* xy, const int32_t* tri, int64_t t, double c[2])
+{
+    int32_t v[3] = { tri[3 * t], tri[3 * t + 1], tri[3 * t + 2] };
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2 - i; ++j)
+            if (v[j] > v[j + 1]) {
+                int32_t s = v[j];
+                v[j] = v[j + 1];
+                v[j + 1] = s;
+            }
+    for (int k = 0; k < 2; ++k)
+        c[k] = ((xy[2 * (int64_t)v[0] + k] + xy[2 * (int64_t)v[1] + k]) + xy[2 * (int64_t)v[2] + k]) / 3.0;
+}
+
+/* The average-pooled ASG grid: pool [G][G][2] (x, y), as described above. */
+int orc_cls_pool(int64_t n_nodes, const double* xy, int64_t n_tri, const int32_t* tri, int32_t G, double* pool)
+{
+    if (n_tri < 0 || G <= 0 || n_nodes < 0) return ORC_EINVAL;
+    const int64_t GG = (int64_t)G * G;
+    int64_t* count = (int64_t*)calloc((size_t)GG, sizeof(int64_t));
+    if (!count) return ORC_ENOMEM;
+    for (int64_t k = 0; k < 2 * GG; ++k) pool[k] = 0.0;
+    for (int64_t t = 0; t < n_tri; ++t) { /* ascending element id */
+        double c[2];
+        centroid_by_id(xy, tri, t, c);
+        const int64_t cell = cell_of(c[1], G) * G + cell_of(c[0], G);
+        pool[2 * cell] += c[0];
+        pool[2 * cell + 1] += c[1];
+        ++count[cell];
+    }
+    for (int64_t cy = 0; cy < G; ++cy)
+        for (int64_t cx = 0; cx < G; ++cx) {
+            const int64_t cell = cy * G + cx;
+            if (count[cell] > 0) {
+                pool[2 * cell] /= (double)count[cell];
+                pool[2 * cell + 1] /= (double)count[cell];
+            } else {
+                pool[2 * cell] = ((double)cx + 0.5) / (double)G;
+                pool[2 * cell + 1] = ((double)cy + 0.5) / (double)G;
+            }
+        }
+    free(count);
+    return ORC_OK;
+}
+
+/* Network inputs of n points: feat [n][2][9][9] and xoff [n][2], FP32. */
+int orc_cls_features(int64_t n, const double* xp, int32_t G, const double* pool, float* feat, float* xoff)
+{
+    if (n < 0 || G <= 0) return ORC_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        const double px = xp[2 * i], py = xp[2 * i + 1];
+        const int64_t cx = cell_of(px, G), cy = cell_of(py, G);
+        for (int dy = -CLS_R; dy <= CLS_R; ++dy)
+            for (int dx = -CLS_R; dx <= CLS_R; ++dx) {
+                const int64_t cell = clamp_cell(cy + dy, G) * G + clamp_cell(cx + dx, G);
+                const int64_t o = (dy + CLS_R) * CLS_W + (dx + CLS_R);
+                feat[(i * 2 + 0) * CLS_NA + o] = (float)((pool[2 * cell] - px) * (double)G);
+                feat[(i * 2 + 1) * CLS_NA + o] = (float)((pool[2 * cell + 1] - py) * (double)G);
+            }
+        xoff[2 * i] = (float)(px * (double)G - ((double)cx + 0.5));
+        xoff[2 * i + 1] = (float)(py * (double)G - ((double)cy + 0.5));
+    }
+    return ORC_OK;
+}
+
+/* one 3x3 "same" convolution on a 9 x 9 image, FP64, optional ReLU */
+static void cls_conv(const double* x, int cin, const float* w, const float* b, int cout, double* y)
+{
+    for (int o = 0; o < cout; ++o)
+        for (int r = 0; r < CLS_W; ++r)
+            for (int c = 0; c < CLS_W; ++c) {
+                double s = (double)b[o];
+                for (int i = 0; i < cin; ++i)
+                    for (int u = 0; u < 3; ++u)
+                        for (int v = 0; v < 3; ++v) {
+                            const int rr = r + u - 1, cc = c + v - 1;
+                            if (rr < 0 || rr >= CLS_W || cc < 0 || cc >= CLS_W) continue;
+                            s += (double)w[((o * cin + i) * 3 + u) * 3 + v] * x[(i * CLS_W + rr) * CLS_W + cc];
+                        }
+                y[(o * CLS_W + r) * CLS_W + c] = s > 0.0 ? s : 0.0;
+            }
+}
+
+/* a fully connected layer y = W x + b ([out][in] weights), FP64, optional ReLU */
+static void cls_fc(const double* x, int nin, const float* w, const float* b, int nout, int relu, double* y)
+{
+    for (int o = 0; o < nout; ++o) {
+        double s = (double)b[o];
+        for (int k = 0; k < nin; ++k) s += (double)w[(int64_t)o * nin + k] * x[k];
+        y[o] = relu && !(s > 0.0) ? 0.0 : s;
+    }
+}
+
+/*
+ * The classifier on n prepared inputs.  w[0..5] / b[0..5]: conv1, conv2,
+ * module-2 FC1, module-2 FC2, FC h2, FC N_a.  Outputs (each may be NULL):
+ * logits [n][81] (FP64), prob [n][81] (the softmax, FP64), cls [n].
+ */
+int orc_cls_forward(int64_t n, const float* feat, const float* xoff, const float* const* w, const float* const* b,
+                    double* logits, double* prob, int32_t* cls)
+{
+    if (n < 0) return ORC_EINVAL;
+    int rc = ORC_OK;
+#pragma omp parallel
+    {
+        double* x0 = (double*)malloc(sizeof(double) * 2 * CLS_NA);
+        double* y1 = (double*)malloc(sizeof(double) * CLS_C * CLS_NA);
+        double* y2 = (double*)malloc(sizeof(double) * CLS_C * CLS_NA);
+        double* z = (double*)malloc(sizeof(double) * (CLS_F + CLS_H1));
+        double* m1 = (double*)malloc(sizeof(double) * CLS_H1);
+        double* h = (double*)malloc(sizeof(double) * CLS_H2);
+        double H[CLS_NA], B[CLS_NA];
+        if (!x0 || !y1 || !y2 || !z || !m1 || !h) {
+#pragma omp atomic write
+            rc = ORC_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t i = 0; i < n; ++i) {
+                for (int k = 0; k < 2 * CLS_NA; ++k) x0[k] = (double)feat[i * 2 * CLS_NA + k];
+                /* module 1: two convolutions with ReLU, 2 x 2 average pooling, flattened */
+                cls_conv(x0, 2, w[0], b[0], CLS_C, y1);
+                cls_conv(y1, CLS_C, w[1], b[1], CLS_C, y2);
+                for (int o = 0; o < CLS_C; ++o)
+                    for (int r = 0; r < CLS_P; ++r)
+                        for (int c = 0; c < CLS_P; ++c) {
+                            const double* q = y2 + (o * CLS_W + 2 * r) * CLS_W + 2 * c;
+                            z[(o * CLS_P + r) * CLS_P + c] = (((q[0] + q[1]) + q[CLS_W]) + q[CLS_W + 1]) / 4.0;
+                        }
+                /* module 2: two fully connected layers on x_p's offset */
+                const double xo[2] = { (double)xoff[2 * i], (double)xoff[2 * i + 1] };
+                cls_fc(xo, 2, w[2], b[2], CLS_H1, 1, m1);
+                cls_fc(m1, CLS_H1, w[3], b[3], CLS_H1, 1, z + CLS_F);
+                /* fusion: two fully connected layers to the logits */
+                cls_fc(z, CLS_F + CLS_H1, w[4], b[4], CLS_H2, 1, h);
+                cls_fc(h, CLS_H2, w[5], b[5], CLS_NA, 0, H);
+                /* softmax and its argmax (lowest index on ties) */
+                double mx = H[0];
+                for (int l = 1; l < CLS_NA; ++l)
+                    if (H[l] > mx) mx = H[l];
+                double sum = 0.0;
+                for (int l = 0; l < CLS_NA; ++l) sum += (B[l] = exp(H[l] - mx));
+                int best = 0;
+                for (int l = 0; l < CLS_NA; ++l) {
+                    B[l] /= sum;
+                    if (B[l] > B[best]) best = l;
+                }
+                if (logits) memcpy(logits + i * CLS_NA, H, sizeof(H));
+                if (prob) memcpy(prob + i * CLS_NA, B, sizeof(B));
+                if (cls) cls[i] = best;
+            }
+        }
+        free(x0); free(y1); free(y2); free(z); free(m1); free(h);
+    }
+    return rc;
+}
+
+/* K_p of each point: the lookup element of its class's window cell (clamped to the grid), else the fallback
+ * start (else element 0). */
+int orc_cls_start(int64_t n, const double* xp, int32_t G, const int32_t* lookup, const int32_t* cls,
+                  const int32_t* fallback, int32_t* start)
+{
+    if (n < 0 || G <= 0) return ORC_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        if (cls[i] < 0 || cls[i] >= CLS_NA) return ORC_EINVAL;
+        const int64_t dy = cls[i] / CLS_W - CLS_R, dx = cls[i] % CLS_W - CLS_R;
+        const int64_t cell = clamp_cell(cell_of(xp[2 * i + 1], G) + dy, G) * G + clamp_cell(cell_of(xp[2 * i], G) + dx, G);
+        int32_t k = lookup[cell];
+        if (k < 0) k = fallback ? fallback[i] : 0;
+        start[i] = k;
+    }
+    return ORC_OK;
+}
+
+/*
+ * Training label of each point (Sec. 2.3: B'_l = 1 for the class of the host
+ * K_t found by SNS): the window cell holding the centroid of the host
+ * element, its offset from the cell of x_p clamped to the window; -1 where
+ * the host is not an element.
+ */
+int orc_cls_label(int64_t n, const double* xp, int32_t G, const double* xy, int64_t n_tri, const int32_t* tri,
+                  const int32_t* host, int32_t* label)
+{
+    if (n < 0 || G <= 0) return ORC_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        if (host[i] < 0 || host[i] >= n_tri) {
+            label[i] = -1;
+            continue;
+        }
+        double c[2];
+        centroid_by_id(xy, tri, host[i], c);
+        int64_t dx = cell_of(c[0], G) - cell_of(xp[2 * i], G), dy = cell_of(c[1], G) - cell_of(xp[2 * i + 1], G);
+        dx = dx < -CLS_R ? -CLS_R : (dx > CLS_R ? CLS_R : dx);
+        dy = dy < -CLS_R ? -CLS_R : (dy > CLS_R ? CLS_R : dy);
+        label[i] = (int32_t)((dy + CLS_R) * CLS_W + (dx + CLS_R));
+    }
+    return ORC_OK;
+}
