@@ -55,6 +55,11 @@ def cnn_issued_macs(G: int, precision: str) -> float:
     raise ValueError(precision)
 
 
+# the classifier CNN (Sec. 2.3) per point: matrix-core MACs issued (conv2 on 96 rows of 16 x 144, the FC
+# layers 256 x 256, 512 x 512 and 512 x 128 with the 81 logits padded to two 64-column tiles) and the
+# products the network needs (conv1 and module 2's first layer run on the vector ALUs)
+CLS_ISSUED_MACS = 96 * 144 * 16 + 256 * 256 + 512 * 512 + 512 * 128  # 614,400
+CLS_USEFUL_MACS = 81 * 18 * 16 + 81 * 144 * 16 + 2 * 256 + 256 * 256 + 512 * 512 + 512 * 81  # 579,616
 REC_BYTES = 60  # algorithmic bytes of one element record: 6 FP64 coordinates + 3 int32 neighbours
 # one tetrahedron record: 12 FP64 coordinates, 4 int32 neighbours and the 4 int32 node ids that put
 # each face's nodes in a fixed order
@@ -500,6 +505,55 @@ def bench_served(args):
     print(json.dumps(res), flush=True)
 
 
+def classifier_leg(C, T, w, mesh, xp, start, K: int, warmup: int, plain_ms: float):
+    """The paper's own prediction step (the classifier CNN of Sec. 2.3, one inference per point) followed by
+    the walk from its start, on the same points: the cost beside the displacement form."""
+    import torch
+
+    from paper_2412_18379_amd import workload as W
+
+    tr = T.load_classifier(w.name) if hasattr(T, "load_classifier") else None
+    ws, bs = tr if tr is not None else W.classifier_he_weights(300)
+    Wc = C.ClsWeights(ws, bs)
+    n = xp.shape[0]
+    st = torch.empty(n, dtype=torch.int32, device=xp.device)
+    host = torch.empty(n, dtype=torch.int32, device=xp.device)
+    iters = torch.empty(n, dtype=torch.int32, device=xp.device)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        C.classify(mesh, xp, Wc, fallback=start, start=st, want_class=False)
+        C.locate(mesh, xp, start=st, host=host, iters=iters, want_status=False)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    for k in range(K):
+        ev[k][0].record(stream)
+        C.classify(mesh, xp, Wc, fallback=start, start=st, want_class=False)
+        ev[k][1].record(stream)
+        C.locate(mesh, xp, start=st, host=host, iters=iters, want_status=False)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    cls_ms = np.array([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)])
+    loc_ms = np.array([ev[k][1].elapsed_time(ev[k][2]) for k in range(K)])
+    it = iters.cpu().numpy()
+    issued = 2.0 * CLS_ISSUED_MACS * n / (cls_ms.mean() / 1e3) / 1e12
+    log(f"classifier CNN-SNS: classify {cls_ms.mean():.3f} ms, locate {loc_ms.mean():.3f} ms, mean I_t {it.mean():.2f}")
+    return {
+        "form": "the paper's classifier CNN, one inference per point (9 x 9 pooled ASG window, 81 classes)",
+        "weights": "trained on SNS labels" if tr is not None else "he-init (seed 300)",
+        "classify_ms": round(float(cls_ms.mean()), 4), "locate_ms": round(float(loc_ms.mean()), 4),
+        "step_ms": round(float((cls_ms + loc_ms).mean()), 4),
+        "points_per_s": round(n / ((cls_ms + loc_ms).mean() / 1e3), 1),
+        "speedup_vs_plain_sns": round(float(plain_ms / (cls_ms + loc_ms).mean()), 4),
+        "mean_path_length": round(float(it.mean()), 3),
+        "path_length_p50_p99_max": [pct(it, 50), pct(it, 99), int(it.max())],
+        "roofline": {"kernel": "cnnsns_classify (k_cls_module1 + 3 x k_dense_f32 + k_cls_argmax)", "bound": "mfma",
+                     "achieved": round(issued, 3), "peak": PEAK["f32_TFLOPs"], "unit": "TFLOP/s",
+                     "frac": round(issued / PEAK["f32_TFLOPs"], 4),
+                     "algorithmic_per_launch": f"{2.0 * CLS_ISSUED_MACS * n:.4e} FLOP issued ({CLS_ISSUED_MACS} MAC "
+                                               f"per point on the matrix cores; {CLS_USEFUL_MACS} needed)"},
+    }
+
+
 def main():
     faulthandler.enable()
     ap = argparse.ArgumentParser()
@@ -512,6 +566,8 @@ def main():
     ap.add_argument("--weights", default="trained", choices=["trained", "he"])
     ap.add_argument("--cpu-band-rows", type=int, default=0, help="oracle sample band (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--classifier", default="on", choices=["on", "off"],
+                    help="the paper's per-point classifier CNN leg (on: time it beside the displacement form)")
     ap.add_argument("--no-bf16-variant", action="store_true", help="skip the BF16 CNN leg of an FP32 run")
     ap.add_argument("--walk3d", default="t3", choices=["t1", "t2", "t3", "none"],
                     help="tetrahedral walk leg (none: skip)")
@@ -779,6 +835,8 @@ def main():
         it32 = it32.cpu().numpy()
         res["precision_report"] = {"mean_path_f32_cnn": round(float(it32.mean()), 4),
                                    "mean_path_change": round(float(it_c.mean() - it32.mean()), 4)}
+    if args.classifier == "on":
+        res["classifier_leg"] = classifier_leg(C, T, w, mesh, xp, start, K, args.warmup, float(plain_ms.mean()))
     if args.walk3d != "none":
         res["walk3d_leg"] = walk3d_leg(args.walk3d, K, args.warmup, copy_gbps, with_cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:

@@ -162,6 +162,55 @@ int cnnsns_predict_noalloc(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w,
                            void* stream);
 
 /*
+ * Weights of the paper's classifier CNN (Sec. 2.3, Fig. 2), as DEVICE FP32
+ * arrays in PyTorch layouts:
+ *   w[0] conv1 [16][2][3][3],   b[0] [16]   module 1: 3x3, zero padding, ReLU
+ *   w[1] conv2 [16][16][3][3],  b[1] [16]   then ReLU and 2 x 2 average pooling
+ *   w[2] fc    [256][2],        b[2] [256]  module 2 (x_p): FC, ReLU (h1 = 256)
+ *   w[3] fc    [256][256],      b[3] [256]  FC, ReLU
+ *   w[4] fc    [512][512],      b[4] [512]  [module 1 (256), module 2 (256)]: FC, ReLU (h2 = 512)
+ *   w[5] fc    [81][512],       b[5] [81]   the logits of the N_a = 81 classes
+ */
+typedef struct {
+    const float* w[6];
+    const float* b[6];
+} cnnsns_cls;
+
+/*
+ * The prediction step of Alg. 2 with the paper's classifier CNN (Sec. 2.3,
+ * eq. 7-8), per point, in 2D on the mesh's G x G overlay.  The element data
+ * fed to the network are the elements' centroids (vertices summed in
+ * ascending node id, divided by 3); each overlay cell holds the mean of the
+ * centroids lying in it (average pooling, summed in ascending element id), or
+ * its centre when none does, built once per mesh on the first call (16 G^2
+ * bytes, counted in the mesh's device bytes).  For a point x_p the network
+ * sees the 9 x 9 cells centred on the cell of x_p (cells outside the grid
+ * take the nearest cell's value: the padding layer), as G (cell value - x_p)
+ * in two channels, and x_p's offset in its own cell, x_p G - (cell + 1/2),
+ * both formed in FP64 and rounded to FP32; the network itself runs in FP32
+ * (convolutions and the fully connected layers on the matrix cores).  The
+ * class is the argmax of the 81 logits (the softmax of eq. 7 does not change
+ * it; ties go to the lowest class); class (dy + 4) 9 + (dx + 4) is the window
+ * cell at offset (dx, dy) from the cell of x_p, clamped to the grid, and the
+ * start element K_p is that cell's overlay lookup element.  The walk is then
+ * cnnsns_locate with these starts (Alg. 2's SNS from K_p).  DEVICE arrays:
+ *   xp        FP64 [n][2] the points x_p.
+ *   w         the weights (device pointers).
+ *   fallback  int32 [n] start where the chosen cell has no element, or NULL
+ *             (then element 0).
+ *   start     int32 [n] output K_p.
+ *   cls       int32 [n] output class, or NULL.
+ *   logits    FP32 [n][81] output logits, or NULL.
+ * Uses a workspace of the mesh (at most 4.4 KB per point, for up to 65,536
+ * points at a time), ordered after the previous classification on the mesh
+ * like cnnsns_predict.  Asynchronous on `stream` (the first call on a mesh
+ * synchronises it once, to build the pooled grid).  n == 0 is a no-op.
+ * Errors: EINVAL (null mesh, weights, xp or start, n < 0), ENOMEM, EHIP.
+ */
+int cnnsns_classify(cnnsns_mesh m, int64_t n, const double* xp, const cnnsns_cls* w, const int32_t* fallback,
+                    int32_t* start, int32_t* cls, float* logits, void* stream);
+
+/*
  * Locate n points (Alg. 1 for every point; Alg. 2 when a displacement grid is
  * given).  All arrays are DEVICE memory:
  *   xp      FP64 [n][2] query points x_p (departure points).

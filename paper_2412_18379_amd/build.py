@@ -28,6 +28,7 @@ SOURCES = {
     "cnn.hip": [],
     "cnn_bf16.hip": [],
     "cnn3d.hip": [],
+    "classifier.hip": [],
     "api.cpp": [],
     "serve.cpp": [],
 }

@@ -23,7 +23,7 @@ PRECISIONS = {"f32": F32, "bf16": BF16, "fp8": FP8E4M3}
 
 EXPORTS = (
     "cnnsns_build_mesh", "cnnsns_mesh_info", "cnnsns_destroy_mesh", "cnnsns_predict", "cnnsns_predict_noalloc",
-    "cnnsns_locate",
+    "cnnsns_locate", "cnnsns_classify",
     "cnnsns_interpolate", "cnnsns_build_mesh3d", "cnnsns_mesh3d_info", "cnnsns_destroy_mesh3d", "cnnsns_predict3d",
     "cnnsns_locate3d", "cnnsns_interpolate3d",
     "cnnsns_server_create", "cnnsns_submit", "cnnsns_poll", "cnnsns_wait", "cnnsns_server_destroy",
@@ -43,6 +43,10 @@ class _Cnn(ctypes.Structure):
     _fields_ = [("w", ctypes.c_void_p * 4), ("b", ctypes.c_void_p * 4)]
 
 
+class _Cls(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p * 6), ("b", ctypes.c_void_p * 6)]
+
+
 def lib():
     """Load libcnnsns.so (raises if it is not built)."""
     global _lib
@@ -59,6 +63,7 @@ def lib():
             "cnnsns_predict": [vp, vp, ctypes.POINTER(_Cnn), i32, vp, vp],
             "cnnsns_predict_noalloc": [vp, vp, ctypes.POINTER(_Cnn), i32, vp, vp],
             "cnnsns_locate": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp],
+            "cnnsns_classify": [vp, i64, vp, ctypes.POINTER(_Cls), vp, vp, vp, vp, vp],
             "cnnsns_interpolate": [vp, i64, vp, vp, vp, vp, vp],
             "cnnsns_build_mesh3d": [vp, i64, vp, i64, i32, vp, ctypes.POINTER(vp)],
             "cnnsns_mesh3d_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64)],
@@ -207,6 +212,40 @@ def locate(mesh: Mesh, xp: torch.Tensor, start: torch.Tensor = None, origin: tor
     _check(lib().cnnsns_locate(mesh.handle, n, _ptr(xp), _ptr(start), _ptr(origin), _ptr(disp), int(max_iter),
                                _ptr(host), _ptr(iters), _ptr(status), _stream(stream)))
     return host, iters, status
+
+
+CLS_SHAPES = [(16, 2, 3, 3), (16, 16, 3, 3), (256, 2), (256, 256), (512, 512), (81, 512)]
+
+
+class ClsWeights:
+    """Weights of the classifier CNN as device tensors (FP32, PyTorch layouts), kept alive with the struct."""
+
+    def __init__(self, ws: Sequence, bs: Sequence, device="cuda"):
+        self.w = [torch.as_tensor(w, dtype=torch.float32).to(device).contiguous() for w in ws]
+        self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in bs]
+        if [tuple(w.shape) for w in self.w] != CLS_SHAPES or [tuple(b.shape) for b in self.b] != \
+                [(s[0],) for s in CLS_SHAPES]:
+            raise ValueError(f"classifier weights of shapes {CLS_SHAPES} expected")
+        self.struct = _Cls()
+        for l in range(6):
+            self.struct.w[l] = self.w[l].data_ptr()
+            self.struct.b[l] = self.b[l].data_ptr()
+
+
+def classify(mesh: Mesh, xp: torch.Tensor, weights: ClsWeights, fallback: torch.Tensor = None,
+             start: torch.Tensor = None, want_class=True, want_logits=False, stream=None):
+    """The classifier's prediction step of Alg. 2 (cnnsns_classify): (start K_p, class, logits)."""
+    n = xp.shape[0]
+    _need(xp, torch.float64, (n, 2), "xp")
+    _need(fallback, torch.int32, (n,), "fallback")
+    if start is None:
+        start = torch.empty(n, dtype=torch.int32, device=xp.device)
+    _need(start, torch.int32, (n,), "start")
+    cls = torch.empty(n, dtype=torch.int32, device=xp.device) if want_class else None
+    logits = torch.empty((n, 81), dtype=torch.float32, device=xp.device) if want_logits else None
+    _check(lib().cnnsns_classify(mesh.handle, n, _ptr(xp), ctypes.byref(weights.struct), _ptr(fallback),
+                                 _ptr(start), _ptr(cls), _ptr(logits), _stream(stream)))
+    return start, cls, logits
 
 
 class Mesh3D:

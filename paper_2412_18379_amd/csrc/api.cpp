@@ -159,6 +159,21 @@ int cnnsns_predict_noalloc(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w,
     });
 }
 
+int cnnsns_classify(cnnsns_mesh m, int64_t n, const double* xp, const cnnsns_cls* w, const int32_t* fallback,
+                    int32_t* start, int32_t* cls, float* logits, void* stream)
+{
+    return guarded([&] {
+        if (!m || !w) fail(CNNSNS_EINVAL, "classify: NULL mesh or weights");
+        if (n < 0) fail(CNNSNS_EINVAL, "classify: n must be >= 0");
+        if (n == 0) return;
+        if (!xp || !start) fail(CNNSNS_EINVAL, "classify: xp and start must not be NULL");
+        for (int l = 0; l < 6; ++l)
+            if (!w->w[l] || !w->b[l]) fail(CNNSNS_EINVAL, "classify: NULL weight or bias pointer");
+        DeviceScope ds(m->device);
+        run_classify(*m, n, xp, *w, fallback, start, cls, logits, static_cast<hipStream_t>(stream));
+    });
+}
+
 int cnnsns_locate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* start, const double* origin,
                   const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status, void* stream)
 {

@@ -82,6 +82,10 @@ struct cnnsns_mesh_s {
     cnnsns::Workspace ws;
     // serving jobs submitted on this mesh and not yet complete (destroy refuses while > 0)
     std::atomic<int64_t> pending_jobs{ 0 };
+    // classifier CNN: the average-pooled overlay of element centroids (FP64 [G][G][2], built on the first
+    // cnnsns_classify) and the workspace of its layers
+    void* cls_pool = nullptr;
+    cnnsns::Workspace cls_ws;
 };
 
 struct cnnsns_mesh3_s {
@@ -125,6 +129,11 @@ void launch_interp(const cnnsns_mesh_s& m, int64_t n, const double* xp, const in
 void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t* start,
                    const double* origin, const float* disp, int32_t max_iter, int32_t* host, int32_t* iters,
                    uint8_t* status, hipStream_t stream);
+
+// classifier.hip
+size_t cls_workspace_bytes(int64_t n);
+void run_classify(cnnsns_mesh_s& m, int64_t n, const double* xp, const cnnsns_cls& w, const int32_t* fallback,
+                  int32_t* start, int32_t* cls, float* logits, hipStream_t stream);
 
 // cnn.hip
 unsigned cnn_persistent_grid();  // one block per compute unit

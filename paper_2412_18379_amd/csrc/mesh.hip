@@ -327,6 +327,8 @@ void destroy_mesh(cnnsns_mesh m)
     (void)hipFree(m->tri);
     (void)hipFree(m->lookup);
     workspace_release(m->ws);
+    workspace_release(m->cls_ws);
+    if (m->cls_pool) (void)hipFree(m->cls_pool);
     (void)hipSetDevice(cur);
     delete m;
 }

@@ -356,6 +356,15 @@ def he_weights(seed: int = 200, channels=(2, 32, 32, 32, 2)):
     return ws, bs
 
 
+def classifier_he_weights(seed: int = 300):
+    """He-normal weights of the classifier CNN (Sec. 2.3; PyTorch layouts, FP32), bias 0."""
+    shapes = [(16, 2, 3, 3), (16, 16, 3, 3), (256, 2), (256, 256), (512, 512), (81, 512)]
+    rng = np.random.default_rng(seed)
+    ws = [(rng.standard_normal(s) * math.sqrt(2.0 / float(np.prod(s[1:])))).astype(np.float32) for s in shapes]
+    bs = [np.zeros(s[0], np.float32) for s in shapes]
+    return ws, bs
+
+
 def random_weights(seed: int, channels=(2, 32, 32, 32, 2), bias_scale: float = 0.1):
     """He-normal weights with non-zero random biases (exercises the bias path)."""
     ws, _ = he_weights(seed, channels)

@@ -442,6 +442,40 @@ void scenario_noalloc()
     free_job(c);
 }
 
+// the classifier's prediction step: the pooled grid on the first call, two chunks of points
+void scenario_classify()
+{
+    const HostMesh hm = grid_mesh(200);
+    Job j = make_job(hm, 256, nullptr);
+    const size_t shapes[6][2] = { { 16, 18 }, { 16, 144 }, { 256, 2 }, { 256, 256 }, { 512, 512 }, { 81, 512 } };
+    std::vector<void*> bufs;
+    cnnsns_cls w{};
+    for (int l = 0; l < 6; ++l) {
+        float* wl = dev_copy(std::vector<float>(shapes[l][0] * shapes[l][1], 0.01f));
+        float* bl = dev_copy(std::vector<float>(shapes[l][0], 0.0f));
+        w.w[l] = wl;
+        w.b[l] = bl;
+        bufs.push_back(wl);
+        bufs.push_back(bl);
+    }
+    const int64_t n = 70001;  // two passes of the fully connected layers
+    int32_t* start = dev_alloc<int32_t>(n);
+    int32_t* cls = dev_alloc<int32_t>(n);
+    float* logits = dev_alloc<float>(81 * n);
+    for (int rep = 0; rep < 2; ++rep) {
+        EXPECT(cnnsns_classify(j.m, n, j.xp, &w, j.start, start, cls, logits, nullptr) == CNNSNS_OK, "classify");
+        EXPECT(cnnsns_classify(j.m, n, j.xp, &w, nullptr, start, nullptr, nullptr, nullptr) == CNNSNS_OK,
+               "classify without optional outputs");
+    }
+    EXPECT(cnnsns_classify(j.m, 0, nullptr, &w, nullptr, nullptr, nullptr, nullptr, nullptr) == CNNSNS_OK, "n = 0");
+    EXPECT(cnnsns_classify(j.m, n, j.xp, nullptr, nullptr, start, nullptr, nullptr, nullptr) == CNNSNS_EINVAL,
+           "no weights");
+    (void)hipDeviceSynchronize();
+    for (void* p : { (void*)start, (void*)cls, (void*)logits }) (void)hipFree(p);
+    for (void* p : bufs) (void)hipFree(p);
+    free_job(j);
+}
+
 }  // namespace
 
 int main(int argc, char** argv)
@@ -462,6 +496,8 @@ int main(int argc, char** argv)
         scenario_mesh3d();
     else if (sc == "noalloc")
         scenario_noalloc();
+    else if (sc == "classify")
+        scenario_classify();
     else {
         std::fprintf(stderr, "unknown scenario %s\n", sc.c_str());
         return 2;

@@ -71,6 +71,22 @@ void launch_interp(const cnnsns_mesh_s&, int64_t, const double*, const int32_t*,
 {
 }
 
+size_t cnn_scratch_bytes()
+{
+    return 0;
+}
+
+void run_predict_noalloc(const cnnsns_mesh_s&, const float*, const cnnsns_cnn&, int32_t, float*, hipStream_t)
+{
+    fail(CNNSNS_EINVAL, "the mock runtime has no preallocated workspace");
+}
+
+void run_classify(cnnsns_mesh_s&, int64_t, const double*, const cnnsns_cls&, const int32_t*, int32_t*, int32_t*,
+                  float*, hipStream_t)
+{
+    fail(CNNSNS_EINVAL, "the mock runtime has no classifier");
+}
+
 cnnsns_mesh3 build_mesh3(const double*, int64_t, const int32_t*, int64_t, int32_t, hipStream_t)
 {
     fail(CNNSNS_EINVAL, "the mock runtime has no 3D meshes");

@@ -26,7 +26,8 @@ HERE = os.path.join(ROOT, "tests", "host_sanitize")
 CSRC = os.path.join(ROOT, "paper_2412_18379_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CLANGXX = "/opt/rocm/llvm/bin/clang++"
-PRODUCT = ["mesh.hip", "sns_walk.hip", "cnn.hip", "cnn_bf16.hip", "mesh3d.hip", "cnn3d.hip", "api.cpp", "serve.cpp"]
+PRODUCT = ["mesh.hip", "sns_walk.hip", "cnn.hip", "cnn_bf16.hip", "mesh3d.hip", "cnn3d.hip", "classifier.hip",
+           "api.cpp", "serve.cpp"]
 SANITIZERS = {"asan": ["address", "undefined"], "tsan": ["thread"]}
 
 
@@ -76,6 +77,7 @@ SCENARIOS = [
     ("predict_mt", "150"),
     ("mesh3d",),
     ("noalloc",),
+    ("classify",),
 ]
 
 
