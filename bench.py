@@ -566,6 +566,9 @@ def main():
     ap.add_argument("--weights", default="trained", choices=["trained", "he"])
     ap.add_argument("--cpu-band-rows", type=int, default=0, help="oracle sample band (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--online", default="on", choices=["on", "off"],
+                    help="in-loop training of both predictors from the walks of the first 3 steps of an "
+                         "unsteady flow, then CNN-SNS in the later steps")
     ap.add_argument("--classifier", default="on", choices=["on", "off"],
                     help="the paper's per-point classifier CNN leg (on: time it beside the displacement form)")
     ap.add_argument("--no-bf16-variant", action="store_true", help="skip the BF16 CNN leg of an FP32 run")
@@ -835,6 +838,21 @@ def main():
         it32 = it32.cpu().numpy()
         res["precision_report"] = {"mean_path_f32_cnn": round(float(it32.mean()), 4),
                                    "mean_path_change": round(float(it_c.mean() - it32.mean()), 4)}
+    if args.online == "on":
+        from paper_2412_18379_amd import online as O
+        t0 = time.perf_counter()
+        rep = O.run(C, n_side=708, seed=2, field_seed=21, k=20.0, G=1024, n_steps=8, n_t=3, log=log)
+        rep.pop("weights")
+        later = [s for s in rep["steps"] if s["step"] >= rep["n_t"]]
+        rep["summary"] = {
+            "mean_path_plain": round(float(np.mean([s["plain_mean_path"] for s in later])), 3),
+            "mean_path_cnn_sns": round(float(np.mean([s["cnn_sns_mean_path"] for s in later])), 3),
+            "mean_path_classifier": round(float(np.mean([s["classifier_mean_path"] for s in later])), 3),
+            "wall_s": round(time.perf_counter() - t0, 2)}
+        rep["workload"] = ("1M-triangle jittered Delaunay (708 x 708 nodes), unsteady Fourier vortices (phases "
+                           "drifting 0.15 rad per step), ~20 diameters per step, G=1024, 8 steps, trained on the "
+                           "first 3 from plain SNS hosts")
+        res["online_training_leg"] = rep
     if args.classifier == "on":
         res["classifier_leg"] = classifier_leg(C, T, w, mesh, xp, start, K, args.warmup, float(plain_ms.mean()))
     if args.walk3d != "none":

@@ -214,6 +214,26 @@ class FourierVortices:
         return u * self.scale, v * self.scale
 
 
+class UnsteadyFourier:
+    """A time-dependent flow: the Fourier vortices of FourierVortices(seed) whose phases drift by
+    omega_k * drift radians per time step (omega_k ~ U[0.5, 1.5], drawn from seed + 1), with the
+    normalisation of step 0 kept (so the speed scale stays near U)."""
+
+    def __init__(self, seed: int, U: float = 1.0, norm_G: int = 1024, drift: float = 0.15):
+        self.base = FourierVortices(seed, U=U, norm_G=norm_G)
+        rng = np.random.default_rng(seed + 1)
+        n = len(self.base.a)
+        self.w_phi = rng.uniform(0.5, 1.5, size=n) * drift
+        self.w_theta = rng.uniform(0.5, 1.5, size=n) * drift
+
+    def at(self, step: int) -> "FourierVortices":
+        f = FourierVortices.__new__(FourierVortices)
+        f.a, f.m, f.n, f.scale = self.base.a, self.base.m, self.base.n, self.base.scale
+        f.phi = self.base.phi + self.w_phi * step
+        f.theta = self.base.theta + self.w_theta * step
+        return f
+
+
 def overlay_velocity(field, G: int) -> np.ndarray:
     """(u, v) at the cell centres ((cx+1/2)/G, (cy+1/2)/G), float32 [2][G][G] (channel, y, x)."""
     u, v = field.grid(G)
