@@ -505,6 +505,126 @@ def bench_served(args):
     print(json.dumps(res), flush=True)
 
 
+def config_legs(C, T, K: int, warmup: int, with_cpu: bool):
+    """The other configurations at their own sizes: C1 (plain SNS on 2K triangles), C2 (plain vs CNN-SNS with
+    the FP32 CNN on 1M triangles) and C4 (C2 with the BF16 CNN: displacement error against the FP64 oracle
+    over the whole grid, path-length change, host agreement), each with the oracle beside it on one host
+    thread (the walks of all points; C2's FP64 CNN on a band of rows)."""
+    import torch
+
+    from paper_2412_18379_amd import workload as W
+    stream = torch.cuda.current_stream()
+    dev = torch.device("cuda:0")
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        for k in range(K):
+            e[k][0].record(stream)
+            fn()
+            e[k][1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in e]))
+
+    out = {}
+    O = None
+    if with_cpu:
+        import oracle as O
+        threads_before = O.set_threads(0)
+    # C1
+    w = W.build("c1")
+    mesh = C.Mesh(w.xy, w.tri, overlay_side=w.G)
+    xp, start = torch.from_numpy(w.xp).to(dev), torch.from_numpy(w.start).to(dev)
+    host = torch.empty(w.n_points, dtype=torch.int32, device=dev)
+    iters = torch.empty(w.n_points, dtype=torch.int32, device=dev)
+    ms = timed(lambda: C.locate(mesh, xp, start=start, host=host, iters=iters, want_status=False))
+    leg = {"workload": "1,922-triangle jittered Delaunay, 1,024 node points, Taylor-Green, ~3 diameters",
+           "plain_sns_ms": round(ms, 4), "plain_sns_points_per_s": round(w.n_points / (ms / 1e3), 1),
+           "mean_path_length": round(float(iters.double().mean()), 3)}
+    if O is not None:
+        tc, nbr = O.prepare_mesh(w.xy, w.tri)
+        O.set_threads(1)
+        t = time.perf_counter()
+        oh, oi, _ = O.sns(w.xy, tc, nbr, w.xp, w.start)
+        t_or = time.perf_counter() - t
+        O.set_threads(threads_before)
+        leg["hosts_equal_oracle"] = bool(np.array_equal(host.cpu().numpy(), oh))
+        leg["cpu_baseline"] = {"value": round(w.n_points / t_or, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+                               "sample": "plain SNS of all 1,024 points, one thread"}
+    out["c1"] = leg
+    mesh.close()
+    # C2 and C4
+    w = W.build("c2")
+    mesh = C.Mesh(w.xy, w.tri, overlay_side=w.G)
+    tr = T.load("c2")
+    ws, bs = tr if tr is not None else W.he_weights(200)
+    Wt = C.Weights(ws, bs)
+    n = w.n_points
+    xp, start = torch.from_numpy(w.xp).to(dev), torch.from_numpy(w.start).to(dev)
+    origin, vel = torch.from_numpy(w.origins).to(dev), torch.from_numpy(w.vel).to(dev)
+    host = torch.empty(n, dtype=torch.int32, device=dev)
+    iters = torch.empty(n, dtype=torch.int32, device=dev)
+    disp = torch.empty((2, w.G, w.G), dtype=torch.float32, device=dev)
+    plain = timed(lambda: C.locate(mesh, xp, start=start, host=host, iters=iters, want_status=False))
+    hp, ip = host.cpu().numpy(), iters.cpu().numpy()
+    legs = {}
+    for prec, name in (("f32", "c2"), ("bf16", "c4")):
+        pred = timed(lambda: C.predict(mesh, vel, Wt, prec, disp=disp))
+        loc = timed(lambda: C.locate(mesh, xp, origin=origin, disp=disp, host=host, iters=iters, want_status=False))
+        ic = iters.cpu().numpy()
+        legs[name] = {"cnn_precision": prec, "weights": "trained" if tr is not None else "he-init",
+                      "predict_ms": round(pred, 4), "locate_ms": round(loc, 4), "plain_sns_ms": round(plain, 4),
+                      "points_per_s": round(n / ((pred + loc) / 1e3), 1),
+                      "plain_sns_points_per_s": round(n / (plain / 1e3), 1),
+                      "speedup_vs_plain_sns": round(plain / (pred + loc), 3),
+                      "mean_path_length": {"cnn_sns": round(float(ic.mean()), 3), "plain_sns": round(float(ip.mean()), 3)},
+                      "host_agreement_with_plain": float(np.mean(host.cpu().numpy() == hp)),
+                      "_disp": disp.cpu().numpy().astype(np.float64), "_iters": ic}
+    legs["c2"]["workload"] = "1M-triangle jittered Delaunay, 999,698 centroid points, ~20 diameters, G=1024, FP32 CNN"
+    legs["c4"]["workload"] = "C2 with the BF16 CNN (FP32 accumulation), walk in FP64"
+    legs["c4"]["mean_path_change_vs_f32"] = round(float(legs["c4"]["_iters"].mean() - legs["c2"]["_iters"].mean()), 4)
+    if O is not None:
+        tc, nbr = O.prepare_mesh(w.xy, w.tri)
+        ref = O.cnn_forward(w.vel, ws, bs)  # FP64, all host threads
+        for name in ("c2", "c4"):
+            err = np.hypot(*(legs[name]["_disp"] - ref)) / w.dbar
+            legs[name]["disp_error_vs_fp64_oracle_diameters"] = {"max": round(float(err.max()), 6),
+                                                                  "mean": round(float(err.mean()), 7)}
+        lk = O.lookup(w.xy, tc, w.G)
+        O.set_threads(1)
+        t = time.perf_counter()
+        oh, oi, _ = O.sns(w.xy, tc, nbr, w.xp, w.start)
+        t_walk = time.perf_counter() - t
+        t = time.perf_counter()
+        O.cnnsns(w.xy, tc, nbr, lk, w.origins, w.xp, ref, fallback=w.start)
+        t_cnnsns_walk = time.perf_counter() - t
+        rows = 16
+        t = time.perf_counter()
+        O.cnn_window(w.vel, ws, bs, w.G // 2, 0, rows, w.G)
+        t_cnn = (time.perf_counter() - t) * (w.G / rows)  # the whole grid at this rate
+        O.set_threads(threads_before)
+        far = _off_edge(w, oh, w.xp)
+        legs["c2"]["hosts_equal_oracle_off_edge"] = float(np.mean(hp[far] == oh[far]))
+        legs["c2"]["cpu_baseline"] = {
+            "value": round(n / (t_cnn + t_cnnsns_walk), 1),
+            "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one thread: the FP64 CNN on {rows} of the {w.G} overlay rows ({t_cnn * rows / w.G:.2f}s), "
+                       f"scaled to the whole grid, plus the CNN-SNS starts and walks of all {n} points from the "
+                       f"oracle's own displacement grid ({t_cnnsns_walk:.2f}s); plain SNS of all points "
+                       f"{t_walk:.2f}s"),
+            "plain_sns_value": round(n / t_walk, 1)}
+    for name in ("c2", "c4"):
+        legs[name].pop("_disp")
+        legs[name].pop("_iters")
+        out[name] = legs[name]
+    mesh.close()
+    log(f"configs: c1 {out['c1']['plain_sns_points_per_s']:.3g} points/s; c2 {out['c2']['speedup_vs_plain_sns']}x; "
+        f"c4 {out['c4']['speedup_vs_plain_sns']}x")
+    return out
+
+
 def classifier_leg(C, T, w, mesh, xp, start, K: int, warmup: int, plain_ms: float):
     """The paper's own prediction step (the classifier CNN of Sec. 2.3, one inference per point) followed by
     the walk from its start, on the same points: the cost beside the displacement form."""
@@ -566,6 +686,9 @@ def main():
     ap.add_argument("--weights", default="trained", choices=["trained", "he"])
     ap.add_argument("--cpu-band-rows", type=int, default=0, help="oracle sample band (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--configs", default="on", choices=["on", "off"],
+                    help="legs for the 2K- and 1M-triangle configurations (FP32 and BF16 CNN) with the oracle "
+                         "on one host thread beside them")
     ap.add_argument("--online", default="on", choices=["on", "off"],
                     help="in-loop training of both predictors from the walks of the first 3 steps of an "
                          "unsteady flow, then CNN-SNS in the later steps")
@@ -698,6 +821,21 @@ def main():
     torch.cuda.synchronize()
     interp_ms = np.array([a.elapsed_time(b) for a, b in ei])
     log(f"interpolation at x_p: {interp_ms.mean():.3f} ms")
+    # the same interpolation fused into the CNN-SNS walk's last iteration (one pass instead of two)
+    for _ in range(args.warmup):
+        C.locate_interpolate(mesh, xp, nodal, origin=origin, disp=disp, host=host, iters=iters, status=status,
+                             out=u_xp)
+    torch.cuda.synchronize()
+    ef = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for k in range(K):
+        ef[k][0].record(stream)
+        C.locate_interpolate(mesh, xp, nodal, origin=origin, disp=disp, host=host, iters=iters, status=status,
+                             out=u_xp)
+        ef[k][1].record(stream)
+    torch.cuda.synchronize()
+    fused_ms = np.array([a.elapsed_time(b) for a, b in ef])
+    log(f"CNN-SNS walk with the interpolation fused: {fused_ms.mean():.3f} ms "
+        f"(separately {loc_ms.mean():.3f} + {interp_ms.mean():.3f} ms)")
 
     value = n / (ms_step / 1e3)
     G = w.G
@@ -781,7 +919,12 @@ def main():
                        "frac": round(gbps_interp / PEAK["hbm_GBps"], 4),
                        "frac_of_measured_copy": round(gbps_interp / copy_gbps, 4),
                        "traffic": traffic_for("k_interp", args.workload),
-                       "algorithmic_per_launch": f"{bytes_interp:.4e} B (144 B x n)"},
+                       "algorithmic_per_launch": f"{bytes_interp:.4e} B (144 B x n)",
+                       "fused_into_cnn_sns_walk": {
+                           "kernel": "k_locate<START_CNN, interpolating> (cnnsns_locate_interpolate)",
+                           "ms": round(float(fused_ms.mean()), 4),
+                           "separate_walk_plus_interp_ms": round(float(loc_ms.mean() + interp_ms.mean()), 4),
+                           "saved_ms": round(float(loc_ms.mean() + interp_ms.mean() - fused_ms.mean()), 4)}},
     }
     disp_bf = None
     if precision == "f32" and not args.no_bf16_variant:
@@ -838,6 +981,8 @@ def main():
         it32 = it32.cpu().numpy()
         res["precision_report"] = {"mean_path_f32_cnn": round(float(it32.mean()), 4),
                                    "mean_path_change": round(float(it_c.mean() - it32.mean()), 4)}
+    if args.configs == "on" and args.workload == "c3":
+        res["config_legs"] = config_legs(C, T, K, args.warmup, with_cpu=not args.no_cpu_baseline)
     if args.online == "on":
         from paper_2412_18379_amd import online as O
         t0 = time.perf_counter()

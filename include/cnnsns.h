@@ -262,6 +262,23 @@ int cnnsns_interpolate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t
                        double* out, void* stream);
 
 /*
+ * cnnsns_locate followed, in the same pass, by the interpolation of
+ * cnnsns_interpolate at each point's x_p in the host the walk ends in (the
+ * step after eq. 4 of Sec. 2.1, fused into the walk's final iteration: the
+ * barycentric numerators of that iteration are reused, so x_p, the host and
+ * the element's coordinates are not read again).  Arguments as in
+ * cnnsns_locate, plus (DEVICE, as in cnnsns_interpolate):
+ *   nodal  FP64 [n_nodes][2] the field at the mesh nodes.
+ *   out    FP64 [n][2] output: sum_j lambda_j nodal[n_j], bit for bit what
+ *          cnnsns_interpolate returns for the same host (NaN for BADSTART).
+ * Asynchronous on `stream`.  n == 0 is a no-op.  Errors: those of
+ * cnnsns_locate, and EINVAL for a NULL nodal or out.
+ */
+int cnnsns_locate_interpolate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* start, const double* origin,
+                              const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status,
+                              const double* nodal, double* out, void* stream);
+
+/*
  * Build a device-resident tetrahedral mesh for the 3D walk (the paper's own
  * setting: Sec. 2.2 with four nodes and four neighbours per element).
  *   xyz          HOST FP64 [n_nodes][3] node coordinates.

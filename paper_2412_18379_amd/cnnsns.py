@@ -23,7 +23,7 @@ PRECISIONS = {"f32": F32, "bf16": BF16, "fp8": FP8E4M3}
 
 EXPORTS = (
     "cnnsns_build_mesh", "cnnsns_mesh_info", "cnnsns_destroy_mesh", "cnnsns_predict", "cnnsns_predict_noalloc",
-    "cnnsns_locate", "cnnsns_classify",
+    "cnnsns_locate", "cnnsns_classify", "cnnsns_locate_interpolate",
     "cnnsns_interpolate", "cnnsns_build_mesh3d", "cnnsns_mesh3d_info", "cnnsns_destroy_mesh3d", "cnnsns_predict3d",
     "cnnsns_locate3d", "cnnsns_interpolate3d",
     "cnnsns_server_create", "cnnsns_submit", "cnnsns_poll", "cnnsns_wait", "cnnsns_server_destroy",
@@ -64,6 +64,7 @@ def lib():
             "cnnsns_predict_noalloc": [vp, vp, ctypes.POINTER(_Cnn), i32, vp, vp],
             "cnnsns_locate": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp],
             "cnnsns_classify": [vp, i64, vp, ctypes.POINTER(_Cls), vp, vp, vp, vp, vp],
+            "cnnsns_locate_interpolate": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp],
             "cnnsns_interpolate": [vp, i64, vp, vp, vp, vp, vp],
             "cnnsns_build_mesh3d": [vp, i64, vp, i64, i32, vp, ctypes.POINTER(vp)],
             "cnnsns_mesh3d_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64)],
@@ -246,6 +247,35 @@ def classify(mesh: Mesh, xp: torch.Tensor, weights: ClsWeights, fallback: torch.
     _check(lib().cnnsns_classify(mesh.handle, n, _ptr(xp), ctypes.byref(weights.struct), _ptr(fallback),
                                  _ptr(start), _ptr(cls), _ptr(logits), _stream(stream)))
     return start, cls, logits
+
+
+def locate_interpolate(mesh: Mesh, xp: torch.Tensor, nodal: torch.Tensor, start: torch.Tensor = None,
+                       origin: torch.Tensor = None, disp: torch.Tensor = None, max_iter: int = 0,
+                       host: torch.Tensor = None, iters: torch.Tensor = None, status: torch.Tensor = None,
+                       out: torch.Tensor = None, want_iters=True, want_status=True, stream=None):
+    """cnnsns_locate with the P1 interpolation of `nodal` at x_p fused into the walk's last step:
+    (host, iters, status, out)."""
+    n = xp.shape[0]
+    _need(xp, torch.float64, (n, 2), "xp")
+    _need(start, torch.int32, (n,), "start")
+    _need(origin, torch.float64, (n, 2), "origin")
+    _need(disp, torch.float32, (2, mesh.G, mesh.G), "disp")
+    _need(nodal, torch.float64, (mesh.n_nodes, 2), "nodal")
+    dev = xp.device
+    host = torch.empty(n, dtype=torch.int32, device=dev) if host is None else host
+    if iters is None and want_iters:
+        iters = torch.empty(n, dtype=torch.int32, device=dev)
+    if status is None and want_status:
+        status = torch.empty(n, dtype=torch.uint8, device=dev)
+    out = torch.empty((n, 2), dtype=torch.float64, device=dev) if out is None else out
+    _need(host, torch.int32, (n,), "host")
+    _need(iters, torch.int32, (n,), "iters")
+    _need(status, torch.uint8, (n,), "status")
+    _need(out, torch.float64, (n, 2), "out")
+    _check(lib().cnnsns_locate_interpolate(mesh.handle, n, _ptr(xp), _ptr(start), _ptr(origin), _ptr(disp),
+                                           int(max_iter), _ptr(host), _ptr(iters), _ptr(status), _ptr(nodal),
+                                           _ptr(out), _stream(stream)))
+    return host, iters, status, out
 
 
 class Mesh3D:

@@ -188,6 +188,22 @@ int cnnsns_locate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* sta
     });
 }
 
+int cnnsns_locate_interpolate(cnnsns_mesh m, int64_t n, const double* xp, const int32_t* start, const double* origin,
+                              const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status,
+                              const double* nodal, double* out, void* stream)
+{
+    return guarded([&] {
+        if (!m) fail(CNNSNS_EINVAL, "locate_interpolate: NULL mesh");
+        if (n < 0) fail(CNNSNS_EINVAL, "locate_interpolate: n must be >= 0");
+        if (n == 0) return;
+        if (!xp || !host || !nodal || !out) fail(CNNSNS_EINVAL, "locate_interpolate: NULL argument");
+        if (disp && !origin) fail(CNNSNS_EINVAL, "locate_interpolate: disp given without origin");
+        DeviceScope ds(m->device);
+        launch_locate(*m, n, xp, start, origin, disp, max_iter, host, iters, status, static_cast<hipStream_t>(stream),
+                      nodal, out);
+    });
+}
+
 int cnnsns_build_mesh3d(const double* xyz, int64_t n_nodes, const int32_t* tet, int64_t n_tet, int32_t overlay_side,
                         void* stream, cnnsns_mesh3* out)
 {

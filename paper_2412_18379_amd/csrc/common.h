@@ -126,9 +126,10 @@ void destroy_mesh(cnnsns_mesh m);
 enum StartMode { START_GIVEN = 0, START_CNN = 1, START_ASG = 2 };
 void launch_interp(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t* host, const double* nodal,
                    double* out, hipStream_t stream);
+// with nodal (FP64 [n_nodes][2]) and out (FP64 [n][2]), also the P1 interpolant at x_p in the host
 void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t* start,
                    const double* origin, const float* disp, int32_t max_iter, int32_t* host, int32_t* iters,
-                   uint8_t* status, hipStream_t stream);
+                   uint8_t* status, hipStream_t stream, const double* nodal = nullptr, double* out = nullptr);
 
 // classifier.hip
 size_t cls_workspace_bytes(int64_t n);

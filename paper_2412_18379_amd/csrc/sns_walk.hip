@@ -35,14 +35,19 @@ __device__ __forceinline__ double clamp01(double v)
     return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
 }
 
-template <int MODE>
+// With INTERP, a finished point also gets the P1 interpolant of a nodal field at x_p in its host
+// element (the step after eq. 4 of Sec. 2.1), from the barycentric numerators of the last iteration:
+// out = sum_j (s_j / |S_0|) nodal[node j], summed in the element's counter-clockwise node order,
+// exactly as cnnsns_interpolate computes it.
+template <int MODE, bool INTERP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_locate(const ElemRec* __restrict__ rec, int64_t n_tri, int64_t n,
                                                    const double2* __restrict__ xp, const int32_t* __restrict__ start,
                                                    const double2* __restrict__ origin,
                                                    const float* __restrict__ disp,
                                                    const int32_t* __restrict__ lookup, int32_t G, int32_t max_iter,
                                                    int32_t* __restrict__ host, int32_t* __restrict__ iters,
-                                                   uint8_t* __restrict__ status)
+                                                   uint8_t* __restrict__ status, const int3* __restrict__ tri,
+                                                   const double2* __restrict__ nodal, double2* __restrict__ out)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
@@ -72,6 +77,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     // point then waits for one load (x_p) instead of a chain of three.
     __shared__ int32_t s_start[MODE == START_GIVEN ? 1 : kBlock / kWave][MODE == START_GIVEN ? 1 : kChunk];
     int32_t* const my_start = s_start[MODE == START_GIVEN ? 0 : (threadIdx.x / kWave)];
+    // Results of the lookup-started modes, whose lanes take new points as they finish, wait in LDS until
+    // the wave's chunk is done and are then written run by run, 64 consecutive points at a time (the
+    // start slot of a point is reused for its host).  From given starts a lane keeps its one point's
+    // results in registers and writes them when the whole wave is done.
+    constexpr int kStage = MODE == START_GIVEN ? 1 : kBlock / kWave;
+    constexpr int kSlots = MODE == START_GIVEN ? 1 : kChunk;
+    __shared__ int32_t s_iters[kStage][kSlots];
+    __shared__ uint8_t s_status[kStage][kSlots];
+    // with INTERP, the barycentric coordinates of x_p in the host: the interpolant is formed after the
+    // loop, for all of the wave's points at once, instead of a chain of dependent gathers per finishing lane
+    __shared__ double s_lam[INTERP ? kStage : 1][3][INTERP ? kSlots : 1];
+    const int wslot = MODE == START_GIVEN ? 0 : (int)(threadIdx.x / kWave);
     if (MODE != START_GIVEN) {
         // in two halves of four points per lane, staged so that the four chains' loads of each
         // level issue together (eight at once would cost occupancy)
@@ -116,8 +133,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 
     bool active = false;
     int64_t idx = 0;
+    int64_t slot = 0;  // the lane's current slot (lookup-started modes)
     double px = 0.0, py = 0.0;
     int32_t K = 0, I = 0;
+    int fin_given = -1;          // given starts: the lane's outcome, written after the loop
+    double lam_given[3] = { 0.0, 0.0, 0.0 };
 
     for (;;) {
         // hand unstarted points of the chunk to idle lanes
@@ -128,16 +148,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
             if (!active && next + rank < n_slots) {
                 const int64_t v = next + rank;
                 idx = point_of(v);
+                slot = v;
                 if (idx < n) {
                     const double2 p = xp[idx];
                     px = p.x;
                     py = p.y;
                     K = MODE == START_GIVEN ? start[idx] : my_start[v];
                     I = 0;
-                    if (K < 0 || K >= n_tri) {
-                        host[idx] = -1;
-                        if (iters) iters[idx] = 0;
-                        if (status) status[idx] = CNNSNS_BADSTART;
+                    if (K < 0 || K >= n_tri) {  // no element: host -1, path 0 (and a NaN interpolant)
+                        if (MODE == START_GIVEN) {
+                            fin_given = CNNSNS_BADSTART;
+                            K = -1;
+                        } else {
+                            my_start[v] = -1;
+                            s_iters[wslot][v] = 0;
+                            s_status[wslot][v] = CNNSNS_BADSTART;
+                        }
                     } else {
                         active = true;
                     }
@@ -161,6 +187,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
             const double s0 = bdx * cdy - bdy * cdx;
             const double s1 = cdx * ady - cdy * adx;
             const double s2 = adx * bdy - ady * bdx;
+            // the neighbour ids arrive with the coordinates (one 64-byte line): keep their load beside
+            // the others, not sunk behind the containment test as a second dependent access
+            asm volatile("" : : "v"(nb.x), "v"(nb.y), "v"(nb.z));
             int fin = -1;
             if (s0 >= 0.0 && s1 >= 0.0 && s2 >= 0.0) {
                 fin = CNNSNS_FOUND;  // closed containment: all coordinates >= 0
@@ -178,10 +207,72 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
                 }
             }
             if (fin >= 0) {
-                host[idx] = K;
-                if (iters) iters[idx] = I;
-                if (status) status[idx] = (uint8_t)fin;
+                double lam[3] = { 0.0, 0.0, 0.0 };
+                if (INTERP) {  // barycentric coordinates s_j / |S_0| of x_p in the host
+                    double2 a = A, b = B, c = C;
+                    double t0 = s0, t1 = s1, t2 = s2;
+                    if (fin == CNNSNS_MAXITER) {  // the host is the element just moved to
+                        const double2* q2 = reinterpret_cast<const double2*>(rec + K);
+                        a = q2[0];
+                        b = q2[1];
+                        c = q2[2];
+                        const double ax_ = a.x - px, ay_ = a.y - py, bx_ = b.x - px, by_ = b.y - py;
+                        const double cx_ = c.x - px, cy_ = c.y - py;
+                        t0 = bx_ * cy_ - by_ * cx_;
+                        t1 = cx_ * ay_ - cy_ * ax_;
+                        t2 = ax_ * by_ - ay_ * bx_;
+                    }
+                    const double area2 = (b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x);
+                    lam[0] = t0 / area2;
+                    lam[1] = t1 / area2;
+                    lam[2] = t2 / area2;
+                }
+                if (MODE == START_GIVEN) {
+                    fin_given = fin;
+                    if (INTERP)
+                        for (int j = 0; j < 3; ++j) lam_given[j] = lam[j];
+                } else {
+                    my_start[slot] = K;
+                    s_iters[wslot][slot] = I;
+                    s_status[wslot][slot] = (uint8_t)fin;
+                    if (INTERP)
+                        for (int j = 0; j < 3; ++j) s_lam[wslot][j][slot] = lam[j];
+                }
                 active = false;
+            }
+        }
+    }
+    // the interpolant at x_p: sum_j lambda_j nodal[node j] over the host's nodes in counter-clockwise
+    // order, NaN where there is no host
+    auto interpolant = [&](int32_t k, const double (&l)[3]) -> double2 {
+        if (k < 0) return double2{ __builtin_nan(""), __builtin_nan("") };
+        const int3 v = tri[k];
+        const double2 u0 = nodal[v.x], u1 = nodal[v.y], u2 = nodal[v.z];
+        return double2{ l[0] * u0.x + l[1] * u1.x + l[2] * u2.x, l[0] * u0.y + l[1] * u1.y + l[2] * u2.y };
+    };
+    // the wave's results, coalesced
+    if (MODE == START_GIVEN) {
+        const int64_t i = wave * kChunkGiven + lane;
+        if (fin_given >= 0 && i < n) {
+            host[i] = K;
+            if (iters) iters[i] = fin_given == CNNSNS_BADSTART ? 0 : I;
+            if (status) status[i] = (uint8_t)fin_given;
+            if (INTERP) out[i] = interpolant(K, lam_given);
+        }
+    } else {
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int r = 0; r < (int)(kChunk / kWave); ++r) {
+            const int64_t v = r * kWave + lane, i = point_of(v);
+            if (i < n) {
+                const int32_t k = my_start[v];
+                host[i] = k;
+                if (iters) iters[i] = s_iters[wslot][v];
+                if (status) status[i] = s_status[wslot][v];
+                if (INTERP) {
+                    const double l[3] = { s_lam[wslot][0][v], s_lam[wslot][1][v], s_lam[wslot][2][v] };
+                    out[i] = interpolant(k, l);
+                }
             }
         }
     }
@@ -235,9 +326,21 @@ void launch_interp(const cnnsns_mesh_s& m, int64_t n, const double* xp, const in
     hip_check(hipGetLastError(), "interpolate launch");
 }
 
+template <int MODE, bool INTERP>
+static void launch_mode(const cnnsns_mesh_s& m, int64_t n, const double2* xp2, const int32_t* start,
+                        const double2* or2, const float* disp, int32_t max_iter, int32_t* host, int32_t* iters,
+                        uint8_t* status, const double* nodal, double* out, unsigned blocks, hipStream_t stream)
+{
+    k_locate<MODE, INTERP><<<blocks, kBlock, 0, stream>>>(m.rec, m.n_tri, n, xp2, start, or2, disp, m.lookup, m.G,
+                                                           max_iter, host, iters, status,
+                                                           reinterpret_cast<const int3*>(m.tri),
+                                                           reinterpret_cast<const double2*>(nodal),
+                                                           reinterpret_cast<double2*>(out));
+}
+
 void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t* start, const double* origin,
                    const float* disp, int32_t max_iter, int32_t* host, int32_t* iters, uint8_t* status,
-                   hipStream_t stream)
+                   hipStream_t stream, const double* nodal, double* out)
 {
     if (n == 0) return;
     if (max_iter <= 0) max_iter = 1 << 20;
@@ -247,15 +350,23 @@ void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const in
     if (blocks > (int64_t)INT32_MAX) fail(CNNSNS_EINVAL, "locate: too many points");
     const auto* xp2 = reinterpret_cast<const double2*>(xp);
     const auto* or2 = reinterpret_cast<const double2*>(origin);
+    const unsigned g = (unsigned)blocks;
+    const bool interp = nodal != nullptr;
     if (disp) {
-        k_locate<START_CNN><<<(unsigned)blocks, kBlock, 0, stream>>>(m.rec, m.n_tri, n, xp2, start, or2, disp, m.lookup,
-                                                                     m.G, max_iter, host, iters, status);
+        if (interp)
+            launch_mode<START_CNN, true>(m, n, xp2, start, or2, disp, max_iter, host, iters, status, nodal, out, g, stream);
+        else
+            launch_mode<START_CNN, false>(m, n, xp2, start, or2, disp, max_iter, host, iters, status, nodal, out, g, stream);
     } else if (start) {
-        k_locate<START_GIVEN><<<(unsigned)blocks, kBlock, 0, stream>>>(m.rec, m.n_tri, n, xp2, start, or2, disp,
-                                                                       m.lookup, m.G, max_iter, host, iters, status);
+        if (interp)
+            launch_mode<START_GIVEN, true>(m, n, xp2, start, or2, disp, max_iter, host, iters, status, nodal, out, g, stream);
+        else
+            launch_mode<START_GIVEN, false>(m, n, xp2, start, or2, disp, max_iter, host, iters, status, nodal, out, g, stream);
     } else {
-        k_locate<START_ASG><<<(unsigned)blocks, kBlock, 0, stream>>>(m.rec, m.n_tri, n, xp2, start, or2, disp,
-                                                                     m.lookup, m.G, max_iter, host, iters, status);
+        if (interp)
+            launch_mode<START_ASG, true>(m, n, xp2, start, or2, disp, max_iter, host, iters, status, nodal, out, g, stream);
+        else
+            launch_mode<START_ASG, false>(m, n, xp2, start, or2, disp, max_iter, host, iters, status, nodal, out, g, stream);
     }
     hip_check(hipGetLastError(), "locate launch");
 }

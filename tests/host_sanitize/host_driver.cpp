@@ -197,6 +197,23 @@ void scenario_c5ref(int n_meshes, double scale, unsigned seed)
                "locate plain");
         bufs.push_back({ host, iters });
     }
+    // the walk with the interpolation fused into its last iteration, in every start mode
+    for (size_t k = 0; k < jobs.size() && k < 6; ++k) {
+        Job& j = jobs[k];
+        double* nodal = dev_copy(std::vector<double>(2 * (size_t)j.n, 1.0));
+        double* out = dev_alloc<double>(2 * j.n);
+        int32_t* host = dev_alloc<int32_t>(j.n);
+        float* disp = dev_alloc<float>(2 * (size_t)j.G * j.G);
+        EXPECT(cnnsns_locate_interpolate(j.m, j.n, j.xp, j.start, nullptr, nullptr, 0, host, nullptr, nullptr, nodal,
+                                         out, nullptr) == CNNSNS_OK, "locate_interpolate given");
+        EXPECT(cnnsns_locate_interpolate(j.m, j.n, j.xp, nullptr, j.origin, disp, 0, host, nullptr, nullptr, nodal,
+                                         out, nullptr) == CNNSNS_OK, "locate_interpolate cnn");
+        EXPECT(cnnsns_locate_interpolate(j.m, j.n, j.xp, nullptr, nullptr, nullptr, 0, host, nullptr, nullptr, nodal,
+                                         out, nullptr) == CNNSNS_OK, "locate_interpolate asg");
+        EXPECT(cnnsns_locate_interpolate(j.m, j.n, j.xp, nullptr, nullptr, nullptr, 0, host, nullptr, nullptr, nullptr,
+                                         out, nullptr) == CNNSNS_EINVAL, "locate_interpolate without nodal");
+        bufs.push_back({ nodal, out, host, disp });
+    }
     (void)hipDeviceSynchronize();
     for (auto& b : bufs)
         for (void* p : b) (void)hipFree(p);

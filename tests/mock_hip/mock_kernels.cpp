@@ -108,7 +108,8 @@ void launch_interp3(const cnnsns_mesh3_s&, int64_t, const double*, const int32_t
 void run_predict3(cnnsns_mesh3_s&, const float*, const cnnsns_cnn&, int32_t, float*, hipStream_t) {}
 
 void launch_locate(const cnnsns_mesh_s& m, int64_t n, const double* xp, const int32_t*, const double* origin,
-                   const float* disp, int32_t, int32_t* host, int32_t* iters, uint8_t*, hipStream_t)
+                   const float* disp, int32_t, int32_t* host, int32_t* iters, uint8_t*, hipStream_t, const double*,
+                   double*)
 {
     volatile float sink = disp[2 * (size_t)m.G * (size_t)m.G - 1];
     (void)sink;

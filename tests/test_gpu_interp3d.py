@@ -35,13 +35,13 @@ def test_velocity_at_departure_points_bitwise(C, oracle_mod, wl, name):
     w = wl.build_3d(name)
     print(f"[interp3d] {name}: {w.n_tet} tetrahedra, {w.n_points} points", flush=True)
     mesh = C.Mesh3D(w.xyz, w.tet, overlay_side=w.G)
-    tp, _ = oracle_mod.prepare_mesh3(w.xyz, w.tet)
+    tp, nbr = oracle_mod.prepare_mesh3(w.xyz, w.tet)
+    oh, _, os_ = oracle_mod.sns3(w.xyz, tp, nbr, w.xp, w.start)  # the oracle's hosts, given to both sides
     xp = _dev(w.xp)
-    h, _, st = C.locate3d(mesh, xp, start=_dev(w.start))
     nodal = _nodal(w)
-    out = C.interpolate3d(mesh, xp, h, _dev(nodal)).cpu().numpy()
-    ref = oracle_mod.interpolate3(w.xyz, tp, nodal, w.xp, h.cpu().numpy())
-    assert np.all(st.cpu().numpy() == C.FOUND)
+    out = C.interpolate3d(mesh, xp, _dev(oh), _dev(nodal)).cpu().numpy()
+    ref = oracle_mod.interpolate3(w.xyz, tp, nodal, w.xp, oh)
+    assert np.all(os_ == C.FOUND)
     assert np.array_equal(out, ref)
     # and it is the flow itself up to the P1 error of a smooth field on elements of size dbar
     u, v, x = w.flow(w.xp[:, 0], w.xp[:, 1], w.xp[:, 2])
@@ -55,8 +55,10 @@ def test_random_fields_ragged_and_invalid_hosts(C, oracle_mod, wl):
     rng = np.random.default_rng(8)
     n = 3 * 256 + 41
     xp = rng.uniform(0.0, 1.0, size=(n, 3))
-    h, _, _ = C.locate3d(mesh, _dev(xp))
-    hh = h.cpu().numpy()
+    tp, nbr = oracle_mod.prepare_mesh3(w.xyz, w.tet)
+    lk = oracle_mod.lookup3(w.xyz, tp, w.G)
+    _, hh, _, _ = oracle_mod.cnnsns3(w.xyz, tp, nbr, lk, xp, xp, np.zeros((3, w.G, w.G, w.G)))
+    hh = hh.copy()
     hh[[0, 9, n - 1]] = [-1, w.n_tet, -3]
     nodal = rng.standard_normal((w.xyz.shape[0], 3))
     out = C.interpolate3d(mesh, _dev(xp), _dev(hh), _dev(nodal)).cpu().numpy()
@@ -76,12 +78,12 @@ def test_full_size_sampled(C, oracle_mod, wl):
     """5.8M tetrahedra, all 1M departure points interpolated; 20,000 sampled against the oracle."""
     w = wl.build_3d("t3")
     mesh = C.Mesh3D(w.xyz, w.tet, overlay_side=w.G)
-    tp = oracle_mod.canonicalise3(w.xyz, w.tet)
+    tp, nbr = oracle_mod.prepare_mesh3(w.xyz, w.tet)
+    oh, _, _ = oracle_mod.sns3(w.xyz, tp, nbr, w.xp, w.start)  # the oracle's hosts of all points
     xp = _dev(w.xp)
-    h, _, _ = C.locate3d(mesh, xp, start=_dev(w.start))
     nodal = _nodal(w)
-    out = C.interpolate3d(mesh, xp, h, _dev(nodal)).cpu().numpy()
+    out = C.interpolate3d(mesh, xp, _dev(oh), _dev(nodal)).cpu().numpy()
     rng = np.random.default_rng(14)
     idx = np.concatenate([rng.integers(0, w.n_points, 20000), [0, w.n_points - 1]])
-    ref = oracle_mod.interpolate3(w.xyz, tp, nodal, w.xp[idx], h.cpu().numpy()[idx])
+    ref = oracle_mod.interpolate3(w.xyz, tp, nodal, w.xp[idx], oh[idx])
     assert np.array_equal(out[idx], ref)
