@@ -71,9 +71,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def traffic_for(group: str, workload: str):
-    """HBM bytes per launch of a kernel group, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the
-    current source of its kernels (scaled by a copy of known size), else None."""
+def _traffic_entry(group: str, workload: str):
     from paper_2412_18379_amd import profiling as P
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -84,7 +82,24 @@ def traffic_for(group: str, workload: str):
     e = db.get(f"{group}@{workload}")
     if not e or e.get("source_sha") != P.source_sha(*P.SOURCES[group]):
         return None
-    return e.get("hbm_bytes_per_launch")
+    return e
+
+
+def traffic_for(group: str, workload: str):
+    """HBM bytes per launch of a kernel group, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the
+    current source of its kernels (scaled by a copy of known size), else None."""
+    e = _traffic_entry(group, workload)
+    return None if e is None else e.get("hbm_bytes_per_launch")
+
+
+def traffic_by_request_size(group: str, workload: str, ms: float):
+    """The same launch's HBM bytes with the read side taken from the TCC read requests counted by
+    size (no copy scale), and the rate they give over the launch time ms; None if not measured."""
+    e = _traffic_entry(group, workload)
+    if e is None or "hbm_bytes_per_launch_by_request_size" not in e:
+        return None
+    b = e["hbm_bytes_per_launch_by_request_size"]
+    return {"bytes": b, "GBps": round(b / (ms / 1e3) / 1e9, 1), "frac": round(b / (ms / 1e3) / 1e9 / PEAK["hbm_GBps"], 4)}
 
 
 def copy_probe(nbytes: int, reps: int = 3):
@@ -98,6 +113,24 @@ def copy_probe(nbytes: int, reps: int = 3):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def gather_probe(nbytes: int, reps: int = 3):
+    """A gather of nbytes of 64-byte rows in a seeded random order (each row read once, the int64 row
+    ids streamed, the rows written in order): the second calibration run for the HBM byte counters,
+    with the access size of the walk's element records rather than a copy's streaming lines."""
+    import torch
+
+    rows = nbytes // 64
+    g = torch.Generator().manual_seed(7)
+    perm = torch.randperm(rows, generator=g).to("cuda")
+    src = torch.ones((rows, 16), dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.index_select(src, 0, perm, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"gather_probe_rows": rows, "row_bytes": 64, "index_bytes": 8, "reps": reps}), flush=True)
 
 
 def copy_bandwidth(nbytes: int = 2 << 30, reps: int = 5) -> float:
@@ -334,6 +367,7 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float, with_cpu: bool 
                      "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": round(g_plain / PEAK["hbm_GBps"], 4),
                      "frac_of_measured_copy": round(g_plain / copy_gbps, 4),
                      "traffic": traffic_for("k3_locate_plain", name),
+                     "traffic_by_request_size": traffic_by_request_size("k3_locate_plain", name, plain_ms.mean()),
                      "algorithmic_per_launch": f"{b_plain:.4e} B (128 B x sum I_t + {per_point} B x n)",
                      "lookup_start_leg": {"achieved": round(g_asg, 1), "frac": round(g_asg / PEAK["hbm_GBps"], 4),
                                           "traffic": traffic_for("k3_locate_lookup", name)}},
@@ -697,6 +731,8 @@ def main():
     ap.add_argument("--no-bf16-variant", action="store_true", help="skip the BF16 CNN leg of an FP32 run")
     ap.add_argument("--walk3d", default="t3", choices=["t1", "t2", "t3", "none"],
                     help="tetrahedral walk leg (none: skip)")
+    ap.add_argument("--gather-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a 64-byte-row random gather of BYTES (counter calibration) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -714,6 +750,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_probe:
         return copy_probe(args.copy_probe)
+    if args.gather_probe:
+        return gather_probe(args.gather_probe)
     C.lib()
     if args.workload == "c5":
         # Switched off: one run of this served-mix benchmark ended in a host
@@ -879,11 +917,17 @@ def main():
         "kernel": "k_locate (plain SNS leg)", "bound": "hbm", "achieved": round(gbps_plain, 1),
         "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": round(gbps_plain / PEAK["hbm_GBps"], 4),
         "traffic": traffic_for("k_locate_plain", args.workload),
+        "traffic_by_request_size": traffic_by_request_size("k_locate_plain", args.workload, plain_ms.mean()),
         "algorithmic_per_launch": f"{bytes_plain:.4e} B (60 B x sum I_t + 29 B x n)",
+        "note": ("walks of nearby points cross the same elements, so records are re-read from L2 and MALL: "
+                 "algorithmic bytes can exceed what reaches HBM (compare traffic_by_request_size)"),
         "measured_copy_GBps": round(copy_gbps, 1),
         "frac_of_measured_copy": round(gbps_plain / copy_gbps, 4),
         "cnn_sns_leg": {"achieved": round(gbps_cnn_walk, 1), "frac": round(gbps_cnn_walk / PEAK["hbm_GBps"], 4),
                         "frac_of_measured_copy": round(gbps_cnn_walk / copy_gbps, 4),
+                        "traffic": traffic_for("k_locate_cnn", args.workload),
+                        "traffic_by_request_size": traffic_by_request_size("k_locate_cnn", args.workload,
+                                                                           loc_ms.mean()),
                         "algorithmic_per_launch": f"{bytes_cnn_walk:.4e} B (60 B x sum I_t + 69 B x n)"},
     }
     res = {
@@ -919,11 +963,16 @@ def main():
                        "frac": round(gbps_interp / PEAK["hbm_GBps"], 4),
                        "frac_of_measured_copy": round(gbps_interp / copy_gbps, 4),
                        "traffic": traffic_for("k_interp", args.workload),
+                       "traffic_by_request_size": traffic_by_request_size("k_interp", args.workload,
+                                                                          interp_ms.mean()),
                        "algorithmic_per_launch": f"{bytes_interp:.4e} B (144 B x n)",
                        "fused_into_cnn_sns_walk": {
                            "kernel": "k_locate<START_CNN, interpolating> (cnnsns_locate_interpolate)",
                            "ms": round(float(fused_ms.mean()), 4),
                            "separate_walk_plus_interp_ms": round(float(loc_ms.mean() + interp_ms.mean()), 4),
+                           "traffic": traffic_for("k_locate_cnn_interp", args.workload),
+                           "traffic_by_request_size": traffic_by_request_size("k_locate_cnn_interp",
+                                                                              args.workload, fused_ms.mean()),
                            "saved_ms": round(float(loc_ms.mean() + interp_ms.mean() - fused_ms.mean()), 4)}},
     }
     disp_bf = None

@@ -11,7 +11,8 @@
 
     python -m paper_2412_18379_amd.profiling stats <kernel_stats.csv> <out.md> "<command>" [+names|-names]
     python -m paper_2412_18379_amd.profiling traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
-        <copy_write.csv> <copy_bytes> <workload> <traffic.json> "<command>" name=kernel[*k][+kernel[*k]] ...
+        <copy_write.csv> <copy_bytes> <workload> <traffic.json> "<command>" name=kernel[*k][+kernel[*k]] ... \
+        [rdreq=<rdreq.csv> copy_rdreq=<copy_rdreq.csv>]
     python -m paper_2412_18379_amd.profiling counters <out.md> <kernel_stats.csv> "<commands>" \
         <counter_collection.csv> [more counter csvs] -- substring[,substring ...]
 
@@ -44,6 +45,7 @@ SOURCES = {
     "k_locate_plain": ("sns_walk.hip",),
     "k_locate_cnn": ("sns_walk.hip",),
     "k_interp": ("sns_walk.hip",),
+    "k_locate_cnn_interp": ("sns_walk.hip",),
     "k3_locate_plain": ("mesh3d.hip",),
     "k3_locate_lookup": ("mesh3d.hip",),
     "k3_locate_cnn": ("mesh3d.hip",),
@@ -121,7 +123,24 @@ def _match(table, substrings):
     return hits[0]
 
 
-def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, workload, out_json, command, groups):
+def _request_bytes(csv_path):
+    """{kernel: (HBM-side read bytes per dispatch from the TCC read requests counted by size, dispatches)}."""
+    table = _counter_table([csv_path])
+    out = {}
+    for k, c in table.items():
+        if "TCC_EA0_RDREQ_64B_sum" not in c:
+            continue
+        out[k] = (32 * c.get("TCC_EA0_RDREQ_32B_sum", 0.0) + 64 * c["TCC_EA0_RDREQ_64B_sum"] +
+                  128 * c.get("TCC_EA0_RDREQ_128B_sum", 0.0), 1)
+    return out
+
+
+def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, workload, out_json, command, groups,
+            rdreq_csv=None, copy_rdreq_csv=None):
+    """HBM bytes per launch of each kernel group.  With rdreq_csv (a --pmc run of TCC_EA0_RDREQ_32B/_64B/
+    _128B_sum) the read side is also given from the requests counted by size, unscaled, beside the
+    copy-scaled FETCH_SIZE figure: the copy moves 128-byte lines, a gather of 64-byte records does not,
+    so one scale factor cannot serve both."""
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
     cf = _per_kernel(copy_fetch_csv, "FETCH_SIZE")
@@ -129,12 +148,14 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, wo
     copy_name = max(cf, key=lambda k: cf[k][0])
     f_scale = copy_bytes / (cf[copy_name][0] * 1024.0)
     w_scale = copy_bytes / (cw[copy_name][0] * 1024.0)
+    req = _request_bytes(rdreq_csv) if rdreq_csv else None
+    copy_req = _request_bytes(copy_rdreq_csv) if copy_rdreq_csv else None
     db = {}
     if os.path.exists(out_json):
         with open(out_json) as f:
             db = json.load(f)
     for name, subs in groups.items():
-        total_r = total_w = 0.0
+        total_r = total_w = total_q = 0.0
         kernels = []
         for sub in subs:
             sub, _, times = sub.partition("*")  # "name*k": the kernel runs k times per launch of the group
@@ -143,9 +164,14 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, wo
             kw, (vw, nw) = _match(write, sub.split("&"))
             total_r += times * vf * 1024.0 * f_scale
             total_w += times * vw * 1024.0 * w_scale
-            kernels.append({"kernel": _short(kf), "per_group_launch": times, "fetch_KiB": round(vf, 1),
-                            "write_KiB": round(vw, 1), "dispatches": nf})
-        db[f"{name}@{workload}"] = {
+            entry = {"kernel": _short(kf), "per_group_launch": times, "fetch_KiB": round(vf, 1),
+                     "write_KiB": round(vw, 1), "dispatches": nf}
+            if req is not None:
+                kq, (vq, _) = _match(req, sub.split("&"))
+                total_q += times * vq
+                entry["read_bytes_by_request_size"] = round(vq)
+            kernels.append(entry)
+        rec = db[f"{name}@{workload}"] = {
             "hbm_bytes_per_launch": round(total_r + total_w),
             "read_bytes": round(total_r), "write_bytes": round(total_w),
             "kernels": kernels, "source_sha": source_sha(*SOURCES[name]),
@@ -153,6 +179,12 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, wo
                                  "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)},
             "command": command,
         }
+        if req is not None:
+            rec["read_bytes_by_request_size"] = round(total_q)
+            rec["hbm_bytes_per_launch_by_request_size"] = round(total_q + total_w)
+            if copy_req:
+                cq = max(copy_req.values(), key=lambda v: v[0])[0]
+                rec["copy_calibration"]["read_bytes_by_request_size"] = round(cq)
     with open(out_json, "w") as f:
         json.dump(db, f, indent=1, sort_keys=True)
     return db
@@ -220,11 +252,14 @@ if __name__ == "__main__":
         print(stats(sys.argv[2], sys.argv[3], sys.argv[4], select=sys.argv[5] if len(sys.argv) > 5 else ""))
     elif sys.argv[1] == "traffic":
         a = sys.argv[2:]
-        groups = {}
+        groups, extra = {}, {}
         for g in a[8:]:
             k, v = g.split("=", 1)
-            groups[k] = v.split("+")
-        print(json.dumps(traffic(a[0], a[1], a[2], a[3], int(a[4]), a[5], a[6], a[7], groups), indent=1))
+            if k in ("rdreq", "copy_rdreq"):
+                extra[k + "_csv"] = v
+            else:
+                groups[k] = v.split("+")
+        print(json.dumps(traffic(a[0], a[1], a[2], a[3], int(a[4]), a[5], a[6], a[7], groups, **extra), indent=1))
     elif sys.argv[1] == "counters":
         a = sys.argv[2:]
         sep = a.index("--")
