@@ -724,8 +724,8 @@ def main():
                     help="legs for the 2K- and 1M-triangle configurations (FP32 and BF16 CNN) with the oracle "
                          "on one host thread beside them")
     ap.add_argument("--online", default="on", choices=["on", "off"],
-                    help="in-loop training of both predictors from the walks of the first 3 steps of an "
-                         "unsteady flow, then CNN-SNS in the later steps")
+                    help="in-loop training of both predictors (and, with a 3D leg, the 3D displacement CNN) from "
+                         "the walks of the first 3 steps of an unsteady flow, then CNN-SNS in the later steps")
     ap.add_argument("--classifier", default="on", choices=["on", "off"],
                     help="the paper's per-point classifier CNN leg (on: time it beside the displacement form)")
     ap.add_argument("--no-bf16-variant", action="store_true", help="skip the BF16 CNN leg of an FP32 run")
@@ -1051,6 +1051,18 @@ def main():
         res["classifier_leg"] = classifier_leg(C, T, w, mesh, xp, start, K, args.warmup, float(plain_ms.mean()))
     if args.walk3d != "none":
         res["walk3d_leg"] = walk3d_leg(args.walk3d, K, args.warmup, copy_gbps, with_cpu=not args.no_cpu_baseline)
+    if args.online == "on" and args.walk3d != "none":
+        # the 3D displacement CNN trained in the loop from the tetrahedral walk's own hosts
+        from paper_2412_18379_amd import online as O
+        t0 = time.perf_counter()
+        rep = O.run3d(C, args.walk3d, n_steps=6, n_t=3, disp_steps=6000, log=log)
+        rep.pop("weights")
+        later = [s for s in rep["steps"] if s["step"] >= rep["n_t"]]
+        rep["summary"] = {k: round(float(np.mean([s[k] for s in later])), 3) for k in (
+            "plain_mean_path", "cnn_sns_mean_path", "cnn_sns_bf16_mean_path", "passthrough_net_mean_path",
+            "lookup_at_xp_mean_path", "hosts_equal_plain")}
+        rep["summary"]["wall_s"] = round(time.perf_counter() - t0, 2)
+        res["online_training_3d_leg"] = rep
     if not args.no_cpu_baseline:
         band = args.cpu_band_rows or {"c2": 1024, "c3": 1536, "c4": 1024}[args.workload]
         t0 = time.perf_counter()

@@ -433,17 +433,31 @@ def kuhn_mesh(n: int, seed: int, jitter: float = 0.15):
 
 class ABCFlow:
     """Arnold-Beltrami-Childress flow on the unit cube (divergence-free):
-    u = A sin 2 pi z + C cos 2 pi y, v = B sin 2 pi x + A cos 2 pi z, w = C sin 2 pi y + B cos 2 pi x."""
+    u = A sin(2 pi z + p_z) + C cos(2 pi y + p_y), v = B sin(2 pi x + p_x) + A cos(2 pi z + p_z),
+    w = C sin(2 pi y + p_y) + B cos(2 pi x + p_x), with phases p = (p_x, p_y, p_z) (zero by default)."""
 
-    def __init__(self, A: float = 1.0, B: float = 0.8, C: float = 0.6):
+    def __init__(self, A: float = 1.0, B: float = 0.8, C: float = 0.6, phase=(0.0, 0.0, 0.0)):
         self.A, self.B, self.C = A, B, C
+        self.px, self.py, self.pz = (float(p) for p in phase)
 
     def __call__(self, x, y, z):
         t = 2.0 * np.pi
-        u = self.A * np.sin(t * z) + self.C * np.cos(t * y)
-        v = self.B * np.sin(t * x) + self.A * np.cos(t * z)
-        w = self.C * np.sin(t * y) + self.B * np.cos(t * x)
+        ax, ay, az = t * x + self.px, t * y + self.py, t * z + self.pz
+        u = self.A * np.sin(az) + self.C * np.cos(ay)
+        v = self.B * np.sin(ax) + self.A * np.cos(az)
+        w = self.C * np.sin(ay) + self.B * np.cos(ax)
         return u, v, w
+
+
+class UnsteadyABC:
+    """A time-dependent ABC flow: the phases drift by omega_a * drift radians per time step
+    (omega_a ~ U[0.5, 1.5] per axis, drawn from seed); step 0 is ABCFlow()."""
+
+    def __init__(self, seed: int, drift: float = 0.15):
+        self.w = np.random.default_rng(seed).uniform(0.5, 1.5, size=3) * drift
+
+    def at(self, step: int) -> ABCFlow:
+        return ABCFlow(phase=tuple(self.w * step))
 
 
 def overlay_velocity_3d(flow, G: int) -> np.ndarray:
