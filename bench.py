@@ -604,7 +604,7 @@ def config_legs(C, T, K: int, warmup: int, with_cpu: bool):
     plain = timed(lambda: C.locate(mesh, xp, start=start, host=host, iters=iters, want_status=False))
     hp, ip = host.cpu().numpy(), iters.cpu().numpy()
     legs = {}
-    for prec, name in (("f32", "c2"), ("bf16", "c4")):
+    for prec, name in (("f32", "c2"), ("bf16", "c4"), ("fp8", "c4_fp8")):
         pred = timed(lambda: C.predict(mesh, vel, Wt, prec, disp=disp))
         loc = timed(lambda: C.locate(mesh, xp, origin=origin, disp=disp, host=host, iters=iters, want_status=False))
         ic = iters.cpu().numpy()
@@ -618,11 +618,15 @@ def config_legs(C, T, K: int, warmup: int, with_cpu: bool):
                       "_disp": disp.cpu().numpy().astype(np.float64), "_iters": ic}
     legs["c2"]["workload"] = "1M-triangle jittered Delaunay, 999,698 centroid points, ~20 diameters, G=1024, FP32 CNN"
     legs["c4"]["workload"] = "C2 with the BF16 CNN (FP32 accumulation), walk in FP64"
-    legs["c4"]["mean_path_change_vs_f32"] = round(float(legs["c4"]["_iters"].mean() - legs["c2"]["_iters"].mean()), 4)
+    legs["c4_fp8"]["workload"] = ("C2 with the FP8 e4m3 CNN (per-channel power-of-two weight scales, FP32 "
+                                  "accumulation; the stretch form of C4), walk in FP64")
+    for name in ("c4", "c4_fp8"):
+        legs[name]["mean_path_change_vs_f32"] = round(float(legs[name]["_iters"].mean() -
+                                                            legs["c2"]["_iters"].mean()), 4)
     if O is not None:
         tc, nbr = O.prepare_mesh(w.xy, w.tri)
         ref = O.cnn_forward(w.vel, ws, bs)  # FP64, all host threads
-        for name in ("c2", "c4"):
+        for name in ("c2", "c4", "c4_fp8"):
             err = np.hypot(*(legs[name]["_disp"] - ref)) / w.dbar
             legs[name]["disp_error_vs_fp64_oracle_diameters"] = {"max": round(float(err.max()), 6),
                                                                   "mean": round(float(err.mean()), 7)}
@@ -649,13 +653,13 @@ def config_legs(C, T, K: int, warmup: int, with_cpu: bool):
                        f"oracle's own displacement grid ({t_cnnsns_walk:.2f}s); plain SNS of all points "
                        f"{t_walk:.2f}s"),
             "plain_sns_value": round(n / t_walk, 1)}
-    for name in ("c2", "c4"):
+    for name in ("c2", "c4", "c4_fp8"):
         legs[name].pop("_disp")
         legs[name].pop("_iters")
         out[name] = legs[name]
     mesh.close()
     log(f"configs: c1 {out['c1']['plain_sns_points_per_s']:.3g} points/s; c2 {out['c2']['speedup_vs_plain_sns']}x; "
-        f"c4 {out['c4']['speedup_vs_plain_sns']}x")
+        f"c4 {out['c4']['speedup_vs_plain_sns']}x; c4 fp8 {out['c4_fp8']['speedup_vs_plain_sns']}x")
     return out
 
 
@@ -975,53 +979,53 @@ def main():
                                                                               args.workload, fused_ms.mean()),
                            "saved_ms": round(float(loc_ms.mean() + interp_ms.mean() - fused_ms.mean()), 4)}},
     }
-    disp_bf = None
-    if precision == "f32" and not args.no_bf16_variant:
-        # the same step with the BF16 CNN (precision variant): time, walk lengths, hosts
-        disp_bf = torch.empty_like(disp)
+    disp_var = {}
+    for vp in (("bf16", "fp8") if precision == "f32" and not args.no_bf16_variant else ()):
+        # the same step with a lower-precision CNN (precision variants): time, walk lengths, hosts
+        dv = disp_var[vp] = torch.empty_like(disp)
         host_b = torch.empty_like(host)
         iters_b = torch.empty_like(iters)
 
-        def step_bf():
-            C.predict(mesh, vel, Wt, "bf16", disp=disp_bf)
-            C.locate(mesh, xp, origin=origin, disp=disp_bf, host=host_b, iters=iters_b, status=status)
+        def step_v():
+            C.predict(mesh, vel, Wt, vp, disp=dv)
+            C.locate(mesh, xp, origin=origin, disp=dv, host=host_b, iters=iters_b, status=status)
 
         for _ in range(args.warmup):
-            step_bf()
+            step_v()
         torch.cuda.synchronize()
         eb = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
         t0 = time.perf_counter()
         for k in range(K):
             eb[k][0].record(stream)
-            C.predict(mesh, vel, Wt, "bf16", disp=disp_bf)
+            C.predict(mesh, vel, Wt, vp, disp=dv)
             eb[k][1].record(stream)
-            C.locate(mesh, xp, origin=origin, disp=disp_bf, host=host_b, iters=iters_b, status=status)
+            C.locate(mesh, xp, origin=origin, disp=dv, host=host_b, iters=iters_b, status=status)
             eb[k][2].record(stream)
         torch.cuda.synchronize()
         wall_b = time.perf_counter() - t0
         pb = np.array([eb[k][0].elapsed_time(eb[k][1]) for k in range(K)])
         lb = np.array([eb[k][1].elapsed_time(eb[k][2]) for k in range(K)])
         it_b = iters_b.cpu().numpy()
-        res["bf16_variant"] = {
+        pk = PEAK[f"{vp}_TFLOPs"]
+        issued = 2.0 * cnn_issued_macs(G, "bf16")  # the FP8 pass has the BF16 pass's tiling
+        res[f"{vp}_variant"] = {
             "points_per_s": round(n / wall_b * K, 1), "ms_per_step": round(wall_b * 1e3 / K, 4),
             "predict_ms": round(float(pb.mean()), 4), "locate_ms": round(float(lb.mean()), 4),
             "speedup_vs_plain_sns": round(float(plain_ms.mean() / (pb + lb).mean()), 3),
             "mean_path_length": round(float(it_b.mean()), 3),
             "mean_path_change_vs_f32": round(float(it_b.mean() - it_c.mean()), 4),
             "host_agreement_with_f32_path": float(np.mean(host_b.cpu().numpy() == host_c)),
-            "cnn_roofline": {"achieved": round(2.0 * cnn_issued_macs(G, "bf16") / (pb.mean() / 1e3) / 1e12, 3),
-                             "peak": PEAK["bf16_TFLOPs"], "unit": "TFLOP/s",
-                             "frac": round(2.0 * cnn_issued_macs(G, "bf16") / (pb.mean() / 1e3) / 1e12 /
-                                           PEAK["bf16_TFLOPs"], 4),
-                             "algorithmic_per_launch": (f"{2 * cnn_issued_macs(G, 'bf16'):.4e} FLOP issued "
-                                                        f"({cnn_issued_macs(G, 'bf16') / (G * G):.0f} MAC per "
+            "cnn_roofline": {"achieved": round(issued / (pb.mean() / 1e3) / 1e12, 3),
+                             "peak": pk, "unit": "TFLOP/s",
+                             "frac": round(issued / (pb.mean() / 1e3) / 1e12 / pk, 4),
+                             "algorithmic_per_launch": (f"{issued:.4e} FLOP issued "
+                                                        f"({issued / 2 / (G * G):.0f} MAC per "
                                                         f"cell with padding and recomputed halos)"),
                              "useful_work": {"macs_per_cell": CNN_MACS_PER_PIXEL,
-                                             "frac": round(cnn_flops / (pb.mean() / 1e3) / 1e12 /
-                                                           PEAK["bf16_TFLOPs"], 4)},
-                             "traffic": traffic_for("cnn_forward_bf16", args.workload)},
+                                             "frac": round(cnn_flops / (pb.mean() / 1e3) / 1e12 / pk, 4)},
+                             "traffic": traffic_for(f"cnn_forward_{vp}", args.workload)},
         }
-        log(f"BF16 CNN-SNS: {res['bf16_variant']['ms_per_step']:.3f} ms/step (predict {pb.mean():.3f} ms), "
+        log(f"{vp.upper()} CNN-SNS: {res[f'{vp}_variant']['ms_per_step']:.3f} ms/step (predict {pb.mean():.3f} ms), "
             f"mean I_t {it_b.mean():.2f}")
     if precision != "f32":
         # the same step with the FP32 CNN: how much the lower precision lengthens the walks
@@ -1090,9 +1094,9 @@ def main():
             ratio = float((np.abs(got - ref_band) / (1e-5 * np.abs(ref_band) + 1e-5 * scale + 1e-30)).max())
             res["f32_parity_on_band"] = {"worst_error_over_tolerance": round(ratio, 4), "pass": ratio <= 1.0,
                                          "sample": sample}
-            if disp_bf is not None:
-                res["bf16_variant"]["disp_error_vs_fp64_oracle_diameters"] = disp_error(disp_bf)
-                res["bf16_variant"]["error_sample"] = sample
+            for vp, dv in disp_var.items():
+                res[f"{vp}_variant"]["disp_error_vs_fp64_oracle_diameters"] = disp_error(dv)
+                res[f"{vp}_variant"]["error_sample"] = sample
         res["cpu_baseline"] = cb
     else:
         res["cpu_baseline"] = None

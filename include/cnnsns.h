@@ -65,8 +65,10 @@ enum {
     CNNSNS_F32 = 0,     /* FP32 operands and activations, FP32 accumulation (the 32 -> 32 layers
                            as Winograd F(2x2,3x3) contractions: within 1e-5 of the exact result) */
     CNNSNS_BF16 = 1,    /* BF16 operands and activations, FP32 accumulation */
-    CNNSNS_FP8E4M3 = 2, /* reserved for FP8 e4m3 with per-channel scales: not available in this
-                           build, cnnsns_predict and cnnsns_server_create return EINVAL for it */
+    CNNSNS_FP8E4M3 = 2, /* FP8 e4m3 (OCP: 3 mantissa bits, largest finite 448) operands with
+                           FP32 accumulation: a power-of-two scale per layer and output channel
+                           for the weights, per layer for the activations (cnnsns_predict only:
+                           the serving loop and the 3D pass return EINVAL for it) */
 };
 
 typedef struct cnnsns_mesh_s* cnnsns_mesh;
@@ -129,16 +131,22 @@ int cnnsns_destroy_mesh(cnnsns_mesh m);
  * Alg. 2, in the displacement-regression form described above):
  *   vel   DEVICE FP32 [2][G][G], (u, v) at the cell centres, row = y index.
  *   w     the weights (device pointers, see cnnsns_cnn).
- *   precision  CNNSNS_F32 or CNNSNS_BF16 (CNNSNS_FP8E4M3 gives EINVAL).
+ *   precision  CNNSNS_F32, CNNSNS_BF16 or CNNSNS_FP8E4M3.
  *   disp  DEVICE FP32 [2][G][G] output (caller-owned): predicted (dx, dy).
  * The mesh keeps a workspace for the forward pass, allocated on first use and
  * grown when needed (FP32: one 32-channel FP32 activation of 128 G^2 bytes
- * plus 128 KiB of transformed weights; BF16: 40 KiB of packed weights) until
- * it is destroyed.  Passes on one mesh share it: a pass is ordered on the
+ * plus 128 KiB of transformed weights; BF16: 40 KiB of packed weights; FP8:
+ * 20 KiB of packed weights and 2 KiB of scales) until it is destroyed.
+ * FP8: the weight scale of output channel o of a layer is the smallest power of
+ * two s with max|w_o| / s <= 448; the velocity's is that of max|u, v| over the
+ * grid (a reduction pass before the forward pass); the scale of the
+ * activations after layer l bounds them for any input of that magnitude:
+ * P_l = max_o (1.25 sum_{i,t} |w_oit| P_{l-1} + |b_o|) with P_0 = max|u, v|,
+ * scale the smallest power of two s with P_l / s <= 448.  Values are rounded
+ * to nearest even; none can exceed the format.  Passes on one mesh share it: a pass is ordered on the
  * device after the previous pass on that mesh, also across streams and
  * threads (growing it synchronises the device).  Asynchronous on `stream`.
- * Errors: EINVAL (also for CNNSNS_FP8E4M3, before any allocation), ENOMEM,
- * EHIP.
+ * Errors: EINVAL (an unknown precision before any allocation), ENOMEM, EHIP.
  */
 int cnnsns_predict(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t precision, float* disp,
                    void* stream);
@@ -152,8 +160,8 @@ int cnnsns_predict(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t
  * hipFree or other allocating call.  Every call on one GPU uses that GPU's
  * array: calls that overlap on one GPU (other streams, other threads) race
  * and give wrong results; a call may follow another on the same stream.
- *   precision  CNNSNS_F32 (workspace 128 G^2 bytes + 128 KiB: G <= 512) or
- *              CNNSNS_BF16 (40 KiB: any G).
+ *   precision  CNNSNS_F32 (workspace 128 G^2 bytes + 128 KiB: G <= 512),
+ *              CNNSNS_BF16 (40 KiB: any G) or CNNSNS_FP8E4M3 (22 KiB: any G).
  * Other arguments as in cnnsns_predict.  Asynchronous on `stream`.  Errors:
  * EINVAL (null argument, precision, or a workspace beyond the array's
  * size), EHIP.
@@ -314,7 +322,7 @@ int cnnsns_destroy_mesh3d(cnnsns_mesh3 m);
  *   vel   FP32 [3][G][G][G] (component, z, y, x) velocity at the cell centres.
  *   w     weights as in cnnsns_predict, with 3 x 3 x 3 kernels: w[0] FP32
  *         [32][3][3][3][3], w[1], w[2] [32][32][3][3][3], w[3] [3][32][3][3][3]
- *         (OIDHW); b[0..2] [32], b[3] [3]; fp8_scale unused.
+ *         (OIDHW); b[0..2] [32], b[3] [3].
  *   precision  CNNSNS_F32, or CNNSNS_BF16: layers 2 and 3 with BF16 weights
  *              and activations (rounded to nearest even) on the matrix cores,
  *              FP32 accumulation; layer 1 writes BF16 activations and layer 4

@@ -27,6 +27,7 @@ SOURCES = {
     "mesh3d.hip": ["-ffp-contract=off"],
     "cnn.hip": [],
     "cnn_bf16.hip": [],
+    "cnn_fp8.hip": [],
     "cnn3d.hip": [],
     "classifier.hip": [],
     "api.cpp": [],

@@ -140,8 +140,8 @@ int cnnsns_predict(cnnsns_mesh m, const float* vel, const cnnsns_cnn* w, int32_t
         if (!m || !vel || !w || !disp) fail(CNNSNS_EINVAL, "predict: NULL argument");
         for (int l = 0; l < 4; ++l)
             if (!w->w[l] || !w->b[l]) fail(CNNSNS_EINVAL, "predict: NULL weight or bias pointer");
-        if (precision == CNNSNS_FP8E4M3) fail(CNNSNS_EINVAL, "predict: FP8 is not implemented");
-        if (precision != CNNSNS_F32 && precision != CNNSNS_BF16) fail(CNNSNS_EINVAL, "predict: unknown precision");
+        if (precision != CNNSNS_F32 && precision != CNNSNS_BF16 && precision != CNNSNS_FP8E4M3)
+            fail(CNNSNS_EINVAL, "predict: unknown precision");
         DeviceScope ds(m->device);
         run_predict(*m, vel, *w, precision, disp, static_cast<hipStream_t>(stream));
     });

@@ -690,6 +690,7 @@ unsigned cnn_persistent_grid()
 size_t cnn_workspace_bytes(int32_t G, int32_t precision)
 {
     if (precision == CNNSNS_BF16) return cnn_bf16_workspace_bytes();
+    if (precision == CNNSNS_FP8E4M3) return cnn_fp8_workspace_bytes();
     return sizeof(float) * (2 * (size_t)NU + (size_t)C * (size_t)G * (size_t)G);
 }
 
@@ -701,7 +702,11 @@ void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision
         cnn_bf16_forward(G, vel, ws, w, disp, persistent_grid(1 << 30), stream);
         return;
     }
-    if (precision != CNNSNS_F32) fail(CNNSNS_EINVAL, "predict: FP8 is not implemented");
+    if (precision == CNNSNS_FP8E4M3) {
+        cnn_fp8_forward(G, vel, w, disp, ws, persistent_grid(1 << 30), stream);
+        return;
+    }
+    if (precision != CNNSNS_F32) fail(CNNSNS_EINVAL, "predict: unknown precision");
     float* u2 = static_cast<float*>(ws);
     float* u3 = u2 + NU;
     float* act2 = u3 + NU;
@@ -753,20 +758,21 @@ size_t cnn_scratch_bytes()
 void run_predict_noalloc(const cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision,
                          float* disp, hipStream_t stream)
 {
-    if (precision != CNNSNS_F32 && precision != CNNSNS_BF16)
-        fail(CNNSNS_EINVAL, "predict_noalloc: precision must be CNNSNS_F32 or CNNSNS_BF16");
+    if (precision != CNNSNS_F32 && precision != CNNSNS_BF16 && precision != CNNSNS_FP8E4M3)
+        fail(CNNSNS_EINVAL, "predict_noalloc: unknown precision");
     const size_t need = cnn_workspace_bytes(m.G, precision);
     if (need > kScratchBytes)
         fail(CNNSNS_EINVAL, "predict_noalloc: this overlay needs a workspace of " + std::to_string(need) +
                                 " bytes, more than the " + std::to_string(kScratchBytes) +
-                                " bytes of the preallocated one (FP32 takes G <= 512; BF16 any G)");
+                                " bytes of the preallocated one (FP32 takes G <= 512; BF16 and FP8 any G)");
     run_cnn(m.G, vel, w, precision, disp, scratch_for_current_device(), stream);
 }
 
 void run_predict(cnnsns_mesh_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
                  hipStream_t stream)
 {
-    if (precision != CNNSNS_F32 && precision != CNNSNS_BF16) fail(CNNSNS_EINVAL, "predict: unsupported precision");
+    if (precision != CNNSNS_F32 && precision != CNNSNS_BF16 && precision != CNNSNS_FP8E4M3)
+        fail(CNNSNS_EINVAL, "predict: unsupported precision");
     std::lock_guard<std::mutex> lock(m.ws.mu);
     workspace_acquire(m.ws, cnn_workspace_bytes(m.G, precision), stream, "predict");
     run_cnn(m.G, vel, w, precision, disp, m.ws.ptr, stream);

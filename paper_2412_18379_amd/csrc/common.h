@@ -142,6 +142,9 @@ size_t cnn_workspace_bytes(int32_t G, int32_t precision);
 void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp, void* ws,
              hipStream_t stream);
 // cnn_bf16.hip
+size_t cnn_fp8_workspace_bytes();
+void cnn_fp8_forward(int32_t G, const float* vel, const cnnsns_cnn& w, float* disp, void* ws, unsigned grid,
+                     hipStream_t stream);
 size_t cnn_bf16_workspace_bytes();
 void cnn_bf16_pack(const cnnsns_cnn& w, void* packed, hipStream_t stream);
 void cnn_bf16_forward(int32_t G, const float* vel, const void* packed, const cnnsns_cnn& w, float* disp,

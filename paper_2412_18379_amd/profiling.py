@@ -42,6 +42,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = {
     "cnn_forward_f32": ("cnn.hip",),
     "cnn_forward_bf16": ("cnn_bf16.hip",),
+    "cnn_forward_fp8": ("cnn_fp8.hip",),
     "k_locate_plain": ("sns_walk.hip",),
     "k_locate_cnn": ("sns_walk.hip",),
     "k_interp": ("sns_walk.hip",),

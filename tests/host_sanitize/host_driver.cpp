@@ -217,12 +217,21 @@ void scenario_c5ref(int n_meshes, double scale, unsigned seed)
     (void)hipDeviceSynchronize();
     for (auto& b : bufs)
         for (void* p : b) (void)hipFree(p);
-    // FP32 on a few of them (the workspace grows from the BF16 size), then FP8 is refused
+    // FP32 on a few of them (the workspace grows from the BF16 size), then FP8 (it fits the grown
+    // workspace), and an unknown precision is refused
     for (size_t k = 0; k < jobs.size() && k < 4; ++k) {
         float* disp = dev_alloc<float>(2 * (size_t)jobs[k].G * jobs[k].G);
         EXPECT(cnnsns_predict(jobs[k].m, jobs[k].vel, &W.w, CNNSNS_F32, disp, nullptr) == CNNSNS_OK, "predict f32");
-        EXPECT(cnnsns_predict(jobs[k].m, jobs[k].vel, &W.w, CNNSNS_FP8E4M3, disp, nullptr) == CNNSNS_EINVAL,
-               "fp8 refused");
+        EXPECT(cnnsns_predict(jobs[k].m, jobs[k].vel, &W.w, CNNSNS_FP8E4M3, disp, nullptr) == CNNSNS_OK, "predict fp8");
+        EXPECT(cnnsns_predict(jobs[k].m, jobs[k].vel, &W.w, 7, disp, nullptr) == CNNSNS_EINVAL, "unknown precision");
+        (void)hipFree(disp);
+    }
+    // FP8 on a fresh mesh first: the workspace is allocated at the FP8 size, then grows for BF16
+    if (!jobs.empty()) {
+        Job& j = jobs.back();
+        float* disp = dev_alloc<float>(2 * (size_t)j.G * j.G);
+        EXPECT(cnnsns_predict(j.m, j.vel, &W.w, CNNSNS_FP8E4M3, disp, nullptr) == CNNSNS_OK, "predict fp8 first");
+        EXPECT(cnnsns_predict(j.m, j.vel, &W.w, CNNSNS_BF16, disp, nullptr) == CNNSNS_OK, "predict bf16 after fp8");
         (void)hipFree(disp);
     }
     for (Job& j : jobs) free_job(j);
@@ -445,12 +454,13 @@ void scenario_noalloc()
     const long before = mock_mallocs();
     for (int rep = 0; rep < 3; ++rep)
         for (Job* j : { &a, &b })
-            for (int prec : { CNNSNS_BF16, CNNSNS_F32 })
+            for (int prec : { CNNSNS_BF16, CNNSNS_F32, CNNSNS_FP8E4M3 })
                 EXPECT(cnnsns_predict_noalloc(j->m, j->vel, &W.w, prec, disp, nullptr) == CNNSNS_OK, "noalloc");
     EXPECT(cnnsns_predict_noalloc(c.m, c.vel, &W.w, CNNSNS_BF16, disp, nullptr) == CNNSNS_OK, "noalloc bf16 G=1024");
     EXPECT(cnnsns_predict_noalloc(c.m, c.vel, &W.w, CNNSNS_F32, disp, nullptr) == CNNSNS_EINVAL,
            "noalloc f32 beyond the scratch size");
-    EXPECT(cnnsns_predict_noalloc(c.m, c.vel, &W.w, CNNSNS_FP8E4M3, disp, nullptr) == CNNSNS_EINVAL, "noalloc fp8");
+    EXPECT(cnnsns_predict_noalloc(c.m, c.vel, &W.w, CNNSNS_FP8E4M3, disp, nullptr) == CNNSNS_OK, "noalloc fp8 G=1024");
+    EXPECT(cnnsns_predict_noalloc(c.m, c.vel, &W.w, 7, disp, nullptr) == CNNSNS_EINVAL, "noalloc unknown precision");
     EXPECT(mock_mallocs() == before, "no device allocation");
     (void)hipDeviceSynchronize();
     (void)hipFree(disp);

@@ -26,7 +26,7 @@ HERE = os.path.join(ROOT, "tests", "host_sanitize")
 CSRC = os.path.join(ROOT, "paper_2412_18379_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CLANGXX = "/opt/rocm/llvm/bin/clang++"
-PRODUCT = ["mesh.hip", "sns_walk.hip", "cnn.hip", "cnn_bf16.hip", "mesh3d.hip", "cnn3d.hip", "classifier.hip",
+PRODUCT = ["mesh.hip", "sns_walk.hip", "cnn.hip", "cnn_bf16.hip", "cnn_fp8.hip", "mesh3d.hip", "cnn3d.hip", "classifier.hip",
            "api.cpp", "serve.cpp"]
 SANITIZERS = {"asan": ["address", "undefined"], "tsan": ["thread"]}
 

@@ -3,8 +3,8 @@
 
 Through the C ABI it must give what cnnsns_predict gives on the same inputs
 (the same kernels: bitwise equal), on two calls in a row, the second with a
-smaller overlay, in both precisions; an FP32 overlay beyond the array's size
-is refused.
+smaller overlay, in every precision; an FP32 overlay beyond the array's size
+and an unknown precision are refused.
 """
 import numpy as np
 import pytest
@@ -28,7 +28,7 @@ def _case(C, wl, n_side, G, seed):
     return mesh, torch.from_numpy(w.vel).cuda()
 
 
-@pytest.mark.parametrize("precision", ["bf16", "f32"])
+@pytest.mark.parametrize("precision", ["bf16", "f32", "fp8"])
 def test_noalloc_equals_predict(C, wl, precision):
     ws, bs = wl.random_weights(11)
     W = C.Weights(ws, bs)
@@ -54,10 +54,11 @@ def test_noalloc_limits(C, wl):
         C.predict_noalloc(mesh, vel, W, disp, "f32")
     assert e.value.code == C.EINVAL
     with pytest.raises(C.CnnsnsError) as e:
-        C.predict_noalloc(mesh, vel, W, disp, "fp8")
+        C.predict_noalloc(mesh, vel, W, disp, 7)
     assert e.value.code == C.EINVAL
-    ref = C.predict(mesh, vel, W, "bf16")
-    C.predict_noalloc(mesh, vel, W, disp, "bf16")  # BF16 needs only the packed weights: any G
-    torch.cuda.synchronize()
-    assert torch.equal(disp, ref)
+    for precision in ("bf16", "fp8"):  # they need only packed weights (and scales): any G
+        ref = C.predict(mesh, vel, W, precision)
+        C.predict_noalloc(mesh, vel, W, disp, precision)
+        torch.cuda.synchronize()
+        assert torch.equal(disp, ref)
     mesh.close()
