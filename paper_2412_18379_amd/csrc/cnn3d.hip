@@ -15,10 +15,13 @@
 // sit in LDS in operand order (108 KiB, loaded once per block), the
 // activations come through the caches (a cell's 32 channels are one 128-byte
 // line).  Layers 1 and 4 (3 -> 32, 32 -> 3) are 9 % of the work.  Layer 1 runs
-// on the vector ALUs, one cell per lane; layer 4 reads its input as the matrix
-// layers do and runs on the vector ALUs in FP32 (four lanes per cell, 8 of the
-// 32 input channels each) or, in the BF16 pass, on the matrix cores with its
-// 3 outputs padded to 16.
+// on the matrix cores in FP32 as a z-sweep (k3c_zconv1: three velocity planes
+// staged in LDS, K = one tap's three components and a zero); layer 4 reads its
+// input once per plane in a z-sweep and runs on the vector ALUs in FP32
+// (k3c_zconv4_f32).  The BF16 pass (BF16
+// operands after layer 1, FP32 accumulation) runs layers 2-4 as z-sweeps that
+// stage three input planes at a time in LDS (described before
+// k3c_zsweep_bf16), layer 4 with its 3 outputs padded to 16.
 //
 // Activations between layers: FP32 [G^3][32], cell-major (z, y, x; x fastest),
 // 32 channels per cell.  Input velocity and output displacement: FP32
@@ -43,7 +46,6 @@ constexpr int NWT = TAPS * 4 * 64 * 4;  // operand-ordered weights of one 32 -> 
 constexpr int NWB = TAPS * 2 * 64;      // the same in BF16 (bf16x8 entries)
 constexpr int kBlock = 256;       // vector-ALU layers
 constexpr int kWaves32 = 12;      // matrix layers: waves per block (three per SIMD, at most 170 registers)
-constexpr int kWaves4 = 16;       // layer 4: waves per block
 constexpr int kSeg = 64;          // cells per wavefront work item (four 16-cell blocks)
 
 // wt[((tap * 2 + nb) * 2 + h) * 64 + l) * 4 + j] = W[16 nb + l%16][8 (l/16) + 4h + j][tap]
@@ -54,80 +56,6 @@ __global__ void k3c_wprep(const float* __restrict__ w, float* __restrict__ wt)
     const int j = k & 3, l = (k >> 2) & 63, h = (k >> 8) & 1, nb = (k >> 9) & 1, tap = k >> 10;
     const int o = 16 * nb + (l & 15), ci = 8 * (l >> 4) + 4 * h + j;
     wt[k] = w[(o * C + ci) * TAPS + tap];
-}
-
-// Layer 1: 3 -> 32 with ReLU, one cell per lane; weights in LDS as [cin][tap][32].  A block of
-// 256 threads takes 4 rows x 64 cells of one plane and first stages their 3 x 3 x 3 neighbourhood
-// of the velocity (3 components x 3 planes x 6 rows x 66 cells, zero outside the grid) in LDS,
-// so each input value is read from memory once per block instead of once per tap.  The output
-// activations are FP32, or BF16 rounded to nearest even for the BF16 pass.
-constexpr int kC1R = 4, kC1W = 64;  // rows and cells of a block
-template <class T>
-__global__ __launch_bounds__(kC1R * kC1W) void k3c_conv1(int32_t G, const float* __restrict__ vel,
-                                                         const float* __restrict__ w, const float* __restrict__ b,
-                                                         T* __restrict__ out)
-{
-    constexpr int VR = kC1R + 2, VW = kC1W + 2, VP = VR * VW;  // one staged plane
-    __shared__ float s_w[CIO * TAPS * C];
-    __shared__ float s_b[C];
-    __shared__ float s_v[CIO * 3 * VP];
-    const int tid = threadIdx.x;
-    for (int k = tid; k < CIO * TAPS * C; k += kC1R * kC1W) {
-        const int o = k % C, ct = k / C;  // ct = cin * 27 + tap
-        s_w[k] = w[o * CIO * TAPS + ct];
-    }
-    if (tid < C) s_b[tid] = b[tid];
-    const int segs = (G + kC1W - 1) / kC1W, bands = (G + kC1R - 1) / kC1R;
-    const int64_t blk = blockIdx.x;
-    const int x0 = (int)(blk % segs) * kC1W, y0 = (int)((blk / segs) % bands) * kC1R;
-    const int z = (int)(blk / ((int64_t)segs * bands));
-    const int64_t n = (int64_t)G * G * G;
-    for (int e = tid; e < CIO * 3 * VP; e += kC1R * kC1W) {
-        const int c = e % VW, r = (e / VW) % VR, dz = (e / VP) % 3, ci = e / (3 * VP);
-        const int Z = z + dz - 1, Y = y0 + r - 1, X = x0 + c - 1;
-        s_v[e] = (Z >= 0 && Z < G && Y >= 0 && Y < G && X >= 0 && X < G)
-                     ? vel[(int64_t)ci * n + ((int64_t)Z * G + Y) * G + X]
-                     : 0.f;
-    }
-    __syncthreads();
-    const int tx = tid % kC1W, ty = tid / kC1W;
-    const int x = x0 + tx, y = y0 + ty;
-    if (x >= G || y >= G) return;
-    float acc[C];
-#pragma unroll
-    for (int o = 0; o < C; ++o) acc[o] = s_b[o];
-    for (int ci = 0; ci < CIO; ++ci) {
-        for (int t = 0; t < TAPS; ++t) {
-            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            const float a = s_v[((ci * 3 + dz) * VR + ty + dy) * VW + tx + dx];
-            const v4f* wr = reinterpret_cast<const v4f*>(s_w + (ci * TAPS + t) * C);
-#pragma unroll
-            for (int q = 0; q < C / 4; ++q) {
-                const v4f wq = wr[q];
-                acc[4 * q] += wq.x * a;
-                acc[4 * q + 1] += wq.y * a;
-                acc[4 * q + 2] += wq.z * a;
-                acc[4 * q + 3] += wq.w * a;
-            }
-        }
-    }
-    const int64_t v = ((int64_t)z * G + y) * G + x;
-    if constexpr (sizeof(T) == 4) {
-        v4f* dst = reinterpret_cast<v4f*>(out + v * C);
-#pragma unroll
-        for (int q = 0; q < C / 4; ++q)
-            dst[q] = v4f{ fmaxf(acc[4 * q], 0.f), fmaxf(acc[4 * q + 1], 0.f), fmaxf(acc[4 * q + 2], 0.f),
-                          fmaxf(acc[4 * q + 3], 0.f) };
-    } else {
-        bf16x8* dst = reinterpret_cast<bf16x8*>(out + v * C);
-#pragma unroll
-        for (int q = 0; q < C / 8; ++q) {
-            v8f r;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) r[j] = fmaxf(acc[8 * q + j], 0.f);
-            dst[q] = __builtin_convertvector(r, bf16x8);
-        }
-    }
 }
 
 // The work items (64 cells of an x row) of a persistent block: the blocks of one XCD (block id
@@ -248,83 +176,10 @@ __global__ void k3c_wprep_bf16(const float* __restrict__ w, bf16x8* __restrict__
     wb[k] = __builtin_convertvector(v, bf16x8);
 }
 
-// Layers 2 and 3 in BF16 (BF16 activations and weights, FP32 accumulation): one
-// v_mfma_f32_16x16x32_bf16 per tap covers all 32 input channels of 16 cells x 16 output
-// channels.  Lane l's B operand is channels 8 (l/16) .. +7 of cell l%16 (one 16-byte load), and
-// it receives output channels 16 nb + 4 (l/16) + r of cell l%16, stored as four BF16 after ReLU.
-// Persistent blocks of 16 wavefronts, the next tap loaded while this tap's 8 instructions run.
-__global__ __launch_bounds__(16 * 64) void k3c_conv32_bf16(int32_t G, const bf16* __restrict__ in,
-                                                          const bf16x8* __restrict__ wb,
-                                                          const float* __restrict__ bias, bf16* __restrict__ out)
-{
-    __shared__ bf16x8 s_w[NWB];
-    for (int k = threadIdx.x; k < NWB; k += 16 * 64) s_w[k] = wb[k];
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int col = lane & 15, grp = lane >> 4;
-    const int segs = (G + kSeg - 1) / kSeg;
-    int64_t i0, i1;
-    item_range((int64_t)G * G * segs, i0, i1);
-    const v4f bv0 = *reinterpret_cast<const v4f*>(bias + 4 * grp);
-    const v4f bv1 = *reinterpret_cast<const v4f*>(bias + 16 + 4 * grp);
-    for (int64_t item = i0 + wave; item < i1; item += 16) {
-        const int seg = (int)(item % segs);
-        const int64_t row = item / segs;
-        const int y = (int)(row % G), z = (int)(row / G);
-        const int x0 = seg * kSeg;
-        v4f acc[4][2];
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-            acc[mb][0] = bv0;
-            acc[mb][1] = bv1;
-        }
-        auto load = [&](int t, bf16x8 (&bo)[4]) {
-            const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, dx = t % 3 - 1;
-            const bool ok = Z >= 0 && Z < G && Y >= 0 && Y < G;
-            const bf16* src = in + ((int64_t)(ok ? Z : 0) * G + (ok ? Y : 0)) * G * C + 8 * grp;
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb) {
-                const int X = x0 + 16 * mb + col + dx;
-                if (ok && X >= 0 && X < G)
-                    bo[mb] = *reinterpret_cast<const bf16x8*>(src + (int64_t)X * C);
-                else
-                    bo[mb] = bf16x8{ 0, 0, 0, 0, 0, 0, 0, 0 };
-            }
-        };
-        bf16x8 bop[4], bnx[4];
-        load(0, bop);
-#pragma unroll 1
-        for (int t = 0; t < TAPS; ++t) {
-            if (t + 1 < TAPS) load(t + 1, bnx);
-            const bf16x8 a0 = s_w[(t * 2) * 64 + lane], a1 = s_w[(t * 2 + 1) * 64 + lane];
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb) {
-                acc[mb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bop[mb], acc[mb][0], 0, 0, 0);
-                acc[mb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bop[mb], acc[mb][1], 0, 0, 0);
-            }
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb) bop[mb] = bnx[mb];
-        }
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-            const int X = x0 + 16 * mb + col;
-            if (X >= G) continue;
-            bf16* dst = out + (row * G + X) * C + 4 * grp;
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                const v4f a = acc[mb][nb];
-                const v4f r{ fmaxf(a.x, 0.f), fmaxf(a.y, 0.f), fmaxf(a.z, 0.f), fmaxf(a.w, 0.f) };
-                *reinterpret_cast<bf16x4*>(dst + 16 * nb) = __builtin_convertvector(r, bf16x4);
-            }
-        }
-    }
-}
-
 // Layer 4 in the BF16 pass on the matrix cores: the 3 output channels padded to one 16-row A
 // block, wb4[tap * 64 + l] = W4[l%16][8 (l/16) + j][tap] as BF16 (zero for rows >= 3), so a tap is
-// one v_mfma_f32_16x16x32_bf16 per 16 cells.  Lanes 0..15 receive output channels 0..3 of
-// their cell, the first three of which are written with the bias added.
+// one v_mfma_f32_16x16x32_bf16 per 16 cells; lanes 0..15 receive output channels 0..3 of their
+// cell, the first three of which are written with the bias added.
 __global__ void k3c_wprep4_bf16(const float* __restrict__ w, bf16x8* __restrict__ wb)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -337,148 +192,328 @@ __global__ void k3c_wprep4_bf16(const float* __restrict__ w, bf16x8* __restrict_
     wb[k] = __builtin_convertvector(v, bf16x8);
 }
 
-__global__ __launch_bounds__(16 * 64) void k3c_conv4_bf16(int32_t G, const bf16* __restrict__ in,
-                                                         const bf16x8* __restrict__ wb, const float* __restrict__ b,
-                                                         float* __restrict__ disp)
+// Layers 2-4 of the BF16 pass as z-sweeps through LDS.  A block owns a column of ZY x ZX cells
+// and ZP consecutive planes; it keeps the three input planes that its current output plane reads,
+// each as a (ZY + 2) x (ZX + 2) slab with the one-cell border (zero outside the grid), in a ring
+// in LDS, so every input cell is read from memory once per block (plus the borders) instead of
+// once per tap.  While a plane's 27 taps run on the matrix cores, the plane after next is loaded
+// into registers; it replaces the oldest slab after the plane is done.  Eight wavefronts take two
+// 16-cell M-blocks each (the 256 cells of a plane; sixteen wavefronts of one M-block each ran
+// 10% slower); a tap is one v_mfma_f32_16x16x32_bf16 per M-block and 16 output channels (NB such
+// blocks: two for 32 -> 32, one for 32 -> 3 with the outputs padded to 16).
+constexpr int ZY = 8, ZX = 32, ZP = 32;           // cells per block: rows, columns, planes
+constexpr int ZSY = ZY + 2, ZSX = ZX + 2;         // slab with its border
+constexpr int ZCS = 40;                           // bf16 per slab cell (32 channels + 8 pad: 80 bytes)
+constexpr int ZSLAB = ZSY * ZSX * ZCS;            // bf16 per slab
+constexpr int kZThreads = 512;
+constexpr int ZCHUNKS = ZSY * ZSX * 4;            // 16-byte pieces of a slab
+constexpr int ZCH_PER_THREAD = (ZCHUNKS + kZThreads - 1) / kZThreads;
+static_assert(ZY * ZX == (kZThreads / 64) * 2 * 16, "two M-blocks per wavefront cover a plane");
+
+template <int NB>
+__global__ __launch_bounds__(kZThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k3c_zsweep_bf16(
+    int32_t G, const bf16* __restrict__ in, const bf16x8* __restrict__ wb, const float* __restrict__ bias,
+    bf16* __restrict__ out, float* __restrict__ disp)
 {
-    __shared__ bf16x8 s_w[TAPS * 64];
-    for (int k = threadIdx.x; k < TAPS * 64; k += 16 * 64) s_w[k] = wb[k];
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    __shared__ __attribute__((aligned(16))) bf16 s_slab[3 * ZSLAB];
+    __shared__ bf16x8 s_w[TAPS * NB * 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, grp = lane >> 4;
-    const int segs = (G + kSeg - 1) / kSeg;
-    const int64_t n = (int64_t)G * G * G;
-    const float b0 = b[0], b1 = b[1], b2 = b[2];
-    int64_t i0, i1;
-    item_range((int64_t)G * G * segs, i0, i1);
-    for (int64_t item = i0 + wave; item < i1; item += 16) {
-        const int seg = (int)(item % segs);
-        const int64_t row = item / segs;
-        const int y = (int)(row % G), z = (int)(row / G);
-        const int x0 = seg * kSeg;
-        v4f acc[4];
+    for (int k = tid; k < TAPS * NB * 64; k += kZThreads) s_w[k] = wb[k];
+    const int tiles_x = (G + ZX - 1) / ZX, tiles_y = (G + ZY - 1) / ZY;
+    const int64_t b = blockIdx.x;
+    const int tx0 = (int)(b % tiles_x) * ZX, ty0 = (int)((b / tiles_x) % tiles_y) * ZY;
+    const int z0 = (int)(b / ((int64_t)tiles_x * tiles_y)) * ZP;
+    const int z1 = min(z0 + ZP, G);
+    const int64_t GG = (int64_t)G * G;
+
+    // the wavefront's M-blocks: cells (ty0 + r, tx0 + 16 h + col) with r = wave, h = 0, 1
+    const int r = wave;
+    // slab offsets (bf16) of the lane's operand for tap (dy, dx) = (0, 0), per M-block
+    int base[2];
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb) acc[mb] = v4f{ 0.f, 0.f, 0.f, 0.f };
-        auto load = [&](int t, bf16x8 (&bo)[4]) {
-            const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, dx = t % 3 - 1;
-            const bool ok = Z >= 0 && Z < G && Y >= 0 && Y < G;
-            const bf16* src = in + ((int64_t)(ok ? Z : 0) * G + (ok ? Y : 0)) * G * C + 8 * grp;
+    for (int h = 0; h < 2; ++h) base[h] = (r * ZSX + 16 * h + col) * ZCS + 8 * grp;
+
+    bf16x8 pf[ZCH_PER_THREAD];
+    auto fetch = [&](int p) {  // plane p of the slab into registers (zero outside the grid)
 #pragma unroll
-            for (int mb = 0; mb < 4; ++mb) {
-                const int X = x0 + 16 * mb + col + dx;
-                if (ok && X >= 0 && X < G)
-                    bo[mb] = *reinterpret_cast<const bf16x8*>(src + (int64_t)X * C);
-                else
-                    bo[mb] = bf16x8{ 0, 0, 0, 0, 0, 0, 0, 0 };
+        for (int k = 0; k < ZCH_PER_THREAD; ++k) {
+            const int e = tid + k * kZThreads;
+            bf16x8 v = bf16x8{ 0, 0, 0, 0, 0, 0, 0, 0 };
+            if (e < ZCHUNKS) {
+                const int cell = e >> 2, part = e & 3;
+                const int gy = ty0 + cell / ZSX - 1, gx = tx0 + cell % ZSX - 1;
+                if (p >= 0 && p < G && gy >= 0 && gy < G && gx >= 0 && gx < G)
+                    v = *reinterpret_cast<const bf16x8*>(in + ((int64_t)p * GG + (int64_t)gy * G + gx) * C + 8 * part);
             }
-        };
-        bf16x8 bop[4], bnx[4];
-        load(0, bop);
-        for (int t = 0; t < TAPS; ++t) {
-            if (t + 1 < TAPS) load(t + 1, bnx);
-            const bf16x8 a = s_w[t * 64 + lane];
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bop[mb], acc[mb], 0, 0, 0);
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb) bop[mb] = bnx[mb];
+            pf[k] = v;
         }
-        if (grp == 0) {
+    };
+    auto stash = [&](int p) {
+        bf16* dst = s_slab + ((p + 3) % 3) * ZSLAB;
 #pragma unroll
-            for (int mb = 0; mb < 4; ++mb) {
-                const int X = x0 + 16 * mb + col;
-                if (X >= G) continue;
-                const int64_t c = row * G + X;
-                disp[c] = acc[mb].x + b0;
-                disp[n + c] = acc[mb].y + b1;
-                disp[2 * n + c] = acc[mb].z + b2;
+        for (int k = 0; k < ZCH_PER_THREAD; ++k) {
+            const int e = tid + k * kZThreads;
+            if (e < ZCHUNKS) *reinterpret_cast<bf16x8*>(dst + (e >> 2) * ZCS + 8 * (e & 3)) = pf[k];
+        }
+    };
+    fetch(z0 - 1);
+    stash(z0 - 1);
+    fetch(z0);
+    stash(z0);
+    fetch(z0 + 1);
+    stash(z0 + 1);
+    __syncthreads();
+
+    v4f bl[2];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        if (NB == 2) {
+            bl[nb] = *reinterpret_cast<const v4f*>(bias + 16 * nb + 4 * grp);
+        } else {  // rows 4 grp + j of the single output block: channels 0..2 are real
+            bl[nb] = v4f{ 0.f, 0.f, 0.f, 0.f };
+        }
+    }
+    for (int z = z0; z < z1; ++z) {
+        if (z + 2 < z1 + 1) fetch(z + 2);  // lands while this plane computes
+        v4f acc[2][NB];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[h][nb] = bl[nb];
+#pragma unroll 1
+        for (int dz = 0; dz < 3; ++dz) {
+            const bf16* sl = s_slab + ((z + dz - 1 + 3) % 3) * ZSLAB;
+#pragma unroll
+            for (int t9 = 0; t9 < 9; ++t9) {
+                const int t = dz * 9 + t9, off = ((t9 / 3) * ZSX + t9 % 3) * ZCS;
+                const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(sl + base[0] + off);
+                const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(sl + base[1] + off);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const bf16x8 w = s_w[(t * NB + nb) * 64 + lane];
+                    acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, a0, acc[0][nb], 0, 0, 0);
+                    acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, a1, acc[1][nb], 0, 0, 0);
+                }
             }
         }
+        // results: lane (col, grp) holds rows 4 grp + j (output channels 16 nb + 4 grp + j) of cell col
+        const int gy = ty0 + r;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gx = tx0 + 16 * h + col;
+            if (gy >= G || gx >= G) continue;
+            const int64_t c = (int64_t)z * GG + (int64_t)gy * G + gx;
+            if (NB == 2) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const v4f a = acc[h][nb];
+                    const v4f v{ fmaxf(a.x, 0.f), fmaxf(a.y, 0.f), fmaxf(a.z, 0.f), fmaxf(a.w, 0.f) };
+                    *reinterpret_cast<bf16x4*>(out + c * C + 16 * nb + 4 * grp) = __builtin_convertvector(v, bf16x4);
+                }
+            } else if (grp == 0) {
+                disp[c] = acc[h][0].x + bias[0];
+                disp[GG * G + c] = acc[h][0].y + bias[1];
+                disp[2 * GG * G + c] = acc[h][0].z + bias[2];
+            }
+        }
+        __syncthreads();           // every wavefront is done with the slab of plane z - 1
+        if (z + 2 < z1 + 1) stash(z + 2);
+        __syncthreads();
     }
 }
 
-__device__ __forceinline__ void conv4_item(int32_t G, const float* __restrict__ in, const v4f* s_w, int segs,
-                                           int64_t item, int col, int grp, int64_t n, float bias,
-                                           float* __restrict__ disp)
+// Layer 1 (3 -> 32) as a z-sweep on the matrix cores in FP32 (both passes; the BF16 pass rounds
+// its output): the velocity's three planes in LDS as (u, v, w, 0) per cell, one
+// v_mfma_f32_16x16x4f32 per tap and 16 output channels with K = the three components and a zero,
+// the weights (one float per lane, tap and block of 16 output channels) held in registers.
+constexpr int Z1CS = 4;  // floats per slab cell
+
+constexpr int kZ1Threads = 1024;  // one 16-cell M-block per wavefront
+template <class T>
+__global__ __launch_bounds__(kZ1Threads) void k3c_zconv1(int32_t G, const float* __restrict__ vel,
+                                                        const float* __restrict__ w, const float* __restrict__ bias,
+                                                        T* __restrict__ out)
 {
-    const int seg = (int)(item % segs);
-    const int64_t row = item / segs;
-    const int y = (int)(row % G), z = (int)(row / G);
-    const int x0 = seg * kSeg;
-    float acc[4][CIO];
+    constexpr int NCELL = ZSY * ZSX;
+    static_assert(NCELL <= kZ1Threads && ZY * ZX == (kZ1Threads / 64) * 16, "one slab cell per thread");
+    __shared__ __attribute__((aligned(16))) float s_v[3 * NCELL * Z1CS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    // A operands: lane (col, grp) holds W[16 nb + col][grp][tap] (zero for grp = 3)
+    float wa[TAPS][2];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int t = 0; t < TAPS; ++t)
 #pragma unroll
-        for (int o = 0; o < CIO; ++o) acc[mb][o] = 0.f;
-    for (int t = 0; t < TAPS; ++t) {
-        const int Z = z + t / 9 - 1, Y = y + (t / 3) % 3 - 1, dx = t % 3 - 1;
-        if (Z < 0 || Z >= G || Y < 0 || Y >= G) continue;
-        const float* src = in + ((int64_t)Z * G + Y) * G * C + 8 * grp;
-        const v4f* wq = s_w + (t * 4 + grp) * 6;  // 24 floats: [channel][output]
-        const v4f w0 = wq[0], w1 = wq[1], w2 = wq[2], w3 = wq[3], w4 = wq[4], w5 = wq[5];
-        const float wv[24] = { w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w, w2.x, w2.y, w2.z, w2.w,
-                               w3.x, w3.y, w3.z, w3.w, w4.x, w4.y, w4.z, w4.w, w5.x, w5.y, w5.z, w5.w };
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-            const int X = x0 + 16 * mb + col + dx;
-            if (X < 0 || X >= G) continue;
-            const v4f* p = reinterpret_cast<const v4f*>(src + (int64_t)X * C);
-            const v4f a0 = p[0], a1 = p[1];
-            const float av[8] = { a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w };
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-#pragma unroll
-                for (int o = 0; o < CIO; ++o) acc[mb][o] += wv[c * CIO + o] * av[c];
+        for (int nb = 0; nb < 2; ++nb) wa[t][nb] = grp < CIO ? w[((16 * nb + col) * CIO + grp) * TAPS + t] : 0.f;
+    const int tiles_x = (G + ZX - 1) / ZX, tiles_y = (G + ZY - 1) / ZY;
+    const int64_t b = blockIdx.x;
+    const int tx0 = (int)(b % tiles_x) * ZX, ty0 = (int)((b / tiles_x) % tiles_y) * ZY;
+    const int z0 = (int)(b / ((int64_t)tiles_x * tiles_y)) * ZP;
+    const int z1 = min(z0 + ZP, G);
+    const int64_t GG = (int64_t)G * G, n = GG * G;
+    const int r = wave >> 1, h = wave & 1;
+
+    v4f pf;
+    auto fetch = [&](int p) {  // thread tid < NCELL: its slab cell of plane p (zero outside the grid)
+        pf = v4f{ 0.f, 0.f, 0.f, 0.f };
+        if (tid < NCELL) {
+            const int gy = ty0 + tid / ZSX - 1, gx = tx0 + tid % ZSX - 1;
+            if (p >= 0 && p < G && gy >= 0 && gy < G && gx >= 0 && gx < G) {
+                const int64_t c = (int64_t)p * GG + (int64_t)gy * G + gx;
+                pf = v4f{ vel[c], vel[n + c], vel[2 * n + c], 0.f };
+            }
         }
-    }
-    // add the four lane groups (lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same cell)
+    };
+    auto stash = [&](int p) {
+        if (tid < NCELL) *reinterpret_cast<v4f*>(s_v + (((p + 3) % 3) * NCELL + tid) * Z1CS) = pf;
+    };
+    fetch(z0 - 1);
+    stash(z0 - 1);
+    fetch(z0);
+    stash(z0);
+    fetch(z0 + 1);
+    stash(z0 + 1);
+    __syncthreads();
+    const v4f bl0 = *reinterpret_cast<const v4f*>(bias + 4 * grp);
+    const v4f bl1 = *reinterpret_cast<const v4f*>(bias + 16 + 4 * grp);
+    const int cell0 = r * ZSX + 16 * h + col;  // the lane's output cell in the slab, and its channel
+    for (int z = z0; z < z1; ++z) {
+        if (z + 2 < z1 + 1) fetch(z + 2);
+        v4f acc0 = bl0, acc1 = bl1;
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+        for (int dz = 0; dz < 3; ++dz) {
+            const float* sl = s_v + ((z + dz - 1 + 3) % 3) * NCELL * Z1CS + cell0 * Z1CS + grp;
+#pragma unroll
+            for (int t9 = 0; t9 < 9; ++t9) {
+                const float a = sl[((t9 / 3) * ZSX + t9 % 3) * Z1CS];
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[dz * 9 + t9][0], a, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[dz * 9 + t9][1], a, acc1, 0, 0, 0);
+            }
+        }
+        const int gy = ty0 + r, gx = tx0 + 16 * h + col;
+        if (gy < G && gx < G) {
+            T* dst = out + ((int64_t)z * GG + (int64_t)gy * G + gx) * C + 4 * grp;
+            const v4f v0{ fmaxf(acc0.x, 0.f), fmaxf(acc0.y, 0.f), fmaxf(acc0.z, 0.f), fmaxf(acc0.w, 0.f) };
+            const v4f v1{ fmaxf(acc1.x, 0.f), fmaxf(acc1.y, 0.f), fmaxf(acc1.z, 0.f), fmaxf(acc1.w, 0.f) };
+            if constexpr (sizeof(T) == 4) {
+                *reinterpret_cast<v4f*>(dst) = v0;
+                *reinterpret_cast<v4f*>(dst + 16) = v1;
+            } else {
+                *reinterpret_cast<bf16x4*>(dst) = __builtin_convertvector(v0, bf16x4);
+                *reinterpret_cast<bf16x4*>(dst + 16) = __builtin_convertvector(v1, bf16x4);
+            }
+        }
+        __syncthreads();
+        if (z + 2 < z1 + 1) stash(z + 2);
+        __syncthreads();
+    }
+}
+
+// Layer 4 of the FP32 pass (32 -> 3) as a z-sweep on the vector ALUs: a block owns a column of
+// Z4Y x Z4X cells (one per thread) and Z4P output planes, and reads each input plane once, as one
+// slab with its one-cell border in LDS.  An input plane p feeds output planes p + 1, p and p - 1
+// (kernel depth index 0, 1, 2), so a thread keeps the partial sums of three output planes; after
+// plane p, output plane p - 1 is complete and written.  The weights are uniform across the block
+// (scalar loads); the next plane's slab is loaded into registers while this one is used.
+constexpr int Z4Y = 8, Z4X = 64, Z4P = 16;
+constexpr int Z4SY = Z4Y + 2, Z4SX = Z4X + 2;
+constexpr int Z4CS = C + 4;  // floats per slab cell (32 channels + 4 pad)
+constexpr int kZ4Threads = Z4Y * Z4X;
+constexpr int Z4CHUNKS = Z4SY * Z4SX * (C / 4);
+constexpr int Z4CH_PER_THREAD = (Z4CHUNKS + kZ4Threads - 1) / kZ4Threads;
+
+// w4t[(t9 * C + ci) * 9 + d * 3 + o] = W4[o][ci][d * 9 + t9]: for one (dy, dx) the 288 weights
+// of all channels, depths and outputs are contiguous (scalar loads of whole lines)
+__global__ void k3c_wprep4_f32(const float* __restrict__ w, float* __restrict__ w4t)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= TAPS * C * CIO) return;
+    const int o = k % 3, d = (k / 3) % 3, ci = (k / 9) % C, t9 = k / (9 * C);
+    w4t[k] = w[(o * C + ci) * TAPS + d * 9 + t9];
+}
+
+__global__ __launch_bounds__(kZ4Threads) void k3c_zconv4_f32(int32_t G, const float* __restrict__ in,
+                                                              const float* __restrict__ w,
+                                                              const float* __restrict__ bias, float* __restrict__ disp)
+{
+    __shared__ __attribute__((aligned(16))) float s_a[Z4SY * Z4SX * Z4CS];
+    const int tid = threadIdx.x;
+    const int tiles_x = (G + Z4X - 1) / Z4X, tiles_y = (G + Z4Y - 1) / Z4Y;
+    const int64_t b = blockIdx.x;
+    const int tx0 = (int)(b % tiles_x) * Z4X, ty0 = (int)((b / tiles_x) % tiles_y) * Z4Y;
+    const int z0 = (int)(b / ((int64_t)tiles_x * tiles_y)) * Z4P;
+    const int z1 = min(z0 + Z4P, G);
+    const int64_t GG = (int64_t)G * G, n = GG * G;
+    const int r = tid / Z4X, c = tid % Z4X;
+    const int gy = ty0 + r, gx = tx0 + c;
+    const float b0 = bias[0], b1 = bias[1], b2 = bias[2];
+
+    v4f pf[Z4CH_PER_THREAD];
+    auto fetch = [&](int p) {
+#pragma unroll
+        for (int k = 0; k < Z4CH_PER_THREAD; ++k) {
+            const int e = tid + k * kZ4Threads;
+            v4f v{ 0.f, 0.f, 0.f, 0.f };
+            if (e < Z4CHUNKS) {
+                const int cell = e / (C / 4), part = e % (C / 4);
+                const int y = ty0 + cell / Z4SX - 1, x = tx0 + cell % Z4SX - 1;
+                if (p >= 0 && p < G && y >= 0 && y < G && x >= 0 && x < G)
+                    v = *reinterpret_cast<const v4f*>(in + ((int64_t)p * GG + (int64_t)y * G + x) * C + 4 * part);
+            }
+            pf[k] = v;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int k = 0; k < Z4CH_PER_THREAD; ++k) {
+            const int e = tid + k * kZ4Threads;
+            if (e < Z4CHUNKS) *reinterpret_cast<v4f*>(s_a + (e / (C / 4)) * Z4CS + 4 * (e % (C / 4))) = pf[k];
+        }
+    };
+    // acc[d][o]: output plane p + 1 - d, component o
+    float acc[3][CIO];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int o = 0; o < CIO; ++o) acc[d][o] = 0.f;
+    fetch(z0 - 1);
+    for (int p = z0 - 1; p <= z1; ++p) {
+        __syncthreads();  // every thread is done with the previous plane's slab
+        stash();
+        __syncthreads();
+        if (p + 1 <= z1) fetch(p + 1);  // lands while this plane is used
+#pragma unroll 1
+        for (int t9 = 0; t9 < 9; ++t9) {
+            const int dy = t9 / 3, dx = t9 % 3;
+            const v4f* a4 = reinterpret_cast<const v4f*>(s_a + ((r + dy) * Z4SX + c + dx) * Z4CS);
+#pragma unroll 2
+            for (int q = 0; q < C / 4; ++q) {
+                const v4f a = a4[q];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ci = 4 * q + j;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+#pragma unroll
+                        for (int o = 0; o < CIO; ++o) acc[d][o] += w[(t9 * C + ci) * 9 + d * 3 + o] * a[j];
+                }
+            }
+        }
+        const int zo = p - 1;  // complete now: its last input plane was p
+        if (zo >= z0 && zo < z1 && gy < G && gx < G) {
+            const int64_t cell = (int64_t)zo * GG + (int64_t)gy * G + gx;
+            disp[cell] = acc[2][0] + b0;
+            disp[n + cell] = acc[2][1] + b1;
+            disp[2 * n + cell] = acc[2][2] + b2;
+        }
 #pragma unroll
         for (int o = 0; o < CIO; ++o) {
-            float v = acc[mb][o];
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
-            acc[mb][o] = v;
-        }
-    // lane group g < 3 writes output component g for the 64 cells
-    if (grp < CIO) {
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-            const int X = x0 + 16 * mb + col;
-            if (X >= G) continue;
-            const float v = grp == 0 ? acc[mb][0] : (grp == 1 ? acc[mb][1] : acc[mb][2]);
-            disp[(int64_t)grp * n + row * G + X] = v + bias;
+            acc[2][o] = acc[1][o];
+            acc[1][o] = acc[0][o];
+            acc[0][o] = 0.f;
         }
     }
-}
-
-
-// Layer 4: 32 -> 3, no ReLU.  A wavefront takes a work item of 64 cells of an x row as the
-// matrix layers do, and reads activations the same way: lane l loads channels 8 (l/16) .. +7 of
-// cell l%16 of each 16-cell block (four lanes cover a cell's 128-byte line), forms the partial
-// sums of its 8 channels for the 3 outputs, and the four lane groups' sums are added across lanes.
-// Weights in LDS as [tap][lane group][8 channels][3].
-__global__ __launch_bounds__(kWaves4 * 64) void k3c_conv4(int32_t G, const float* __restrict__ in,
-                                                           const float* __restrict__ w, const float* __restrict__ b,
-                                                           float* __restrict__ disp)
-{
-    __shared__ v4f s_w[TAPS * C * CIO / 4];
-    float* const sw = reinterpret_cast<float*>(s_w);
-    for (int k = threadIdx.x; k < TAPS * C * CIO; k += kWaves4 * 64) {
-        const int o = k % CIO, ci = (k / CIO) % C, t = k / (CIO * C);  // ci = 8 group + channel
-        sw[k] = w[(o * C + ci) * TAPS + t];
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int col = lane & 15, grp = lane >> 4;
-    const int segs = (G + kSeg - 1) / kSeg;
-    const int64_t n = (int64_t)G * G * G;
-    const float bias = b[grp < CIO ? grp : 0];
-    int64_t i0, i1;
-    item_range((int64_t)G * G * segs, i0, i1);
-    for (int64_t item = i0 + (threadIdx.x >> 6); item < i1; item += kWaves4)
-        conv4_item(G, in, s_w, segs, item, col, grp, n, bias, disp);
 }
 
 }  // namespace
@@ -486,7 +521,7 @@ __global__ __launch_bounds__(kWaves4 * 64) void k3c_conv4(int32_t G, const float
 size_t cnn3_workspace_bytes(int32_t G)
 {
     const size_t cells = (size_t)G * G * G;
-    return 2 * cells * C * sizeof(float) + 2 * (size_t)NWT * sizeof(float);
+    return 2 * cells * C * sizeof(float) + 2 * (size_t)NWT * sizeof(float) + (size_t)TAPS * C * CIO * sizeof(float);
 }
 
 void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, int32_t precision, float* disp,
@@ -498,9 +533,8 @@ void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, int3
     const int32_t G = m.G;
     const int64_t cells = (int64_t)G * G * G;
     const unsigned grid = cnn_persistent_grid();
-    const int64_t c1blocks = (int64_t)G * ((G + kC1R - 1) / kC1R) * ((G + kC1W - 1) / kC1W);
-    if (c1blocks > (int64_t)UINT32_MAX) fail(CNNSNS_EINVAL, "predict3d: overlay too large");
-    const unsigned c1grid = (unsigned)c1blocks;
+    const int64_t zblocks = (int64_t)((G + ZX - 1) / ZX) * ((G + ZY - 1) / ZY) * ((G + ZP - 1) / ZP);
+    if (zblocks > (int64_t)UINT32_MAX) fail(CNNSNS_EINVAL, "predict3d: overlay too large");
     float* act0 = static_cast<float*>(m.ws.ptr);
     float* act1 = act0 + cells * C;
     float* wt2 = act1 + cells * C;
@@ -512,19 +546,23 @@ void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, int3
         bf16x8* wb3 = reinterpret_cast<bf16x8*>(wt3);
         k3c_wprep_bf16<<<(NWB + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[1], wb2);
         k3c_wprep_bf16<<<(NWB + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[2], wb3);
-        k3c_conv1<bf16><<<c1grid, kC1R * kC1W, 0, stream>>>(G, vel, w.w[0], w.b[0], b0);
-        k3c_conv32_bf16<<<grid, 16 * 64, 0, stream>>>(G, b0, wb2, w.b[1], b1);
-        k3c_conv32_bf16<<<grid, 16 * 64, 0, stream>>>(G, b1, wb3, w.b[2], b0);
+        k3c_zconv1<bf16><<<(unsigned)zblocks, kZ1Threads, 0, stream>>>(G, vel, w.w[0], w.b[0], b0);
+        k3c_zsweep_bf16<2><<<(unsigned)zblocks, kZThreads, 0, stream>>>(G, b0, wb2, w.b[1], b1, nullptr);
+        k3c_zsweep_bf16<2><<<(unsigned)zblocks, kZThreads, 0, stream>>>(G, b1, wb3, w.b[2], b0, nullptr);
         bf16x8* wb4 = wb3 + NWB;
         k3c_wprep4_bf16<<<(TAPS * 64 + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[3], wb4);
-        k3c_conv4_bf16<<<grid, 16 * 64, 0, stream>>>(G, b0, wb4, w.b[3], disp);
+        k3c_zsweep_bf16<1><<<(unsigned)zblocks, kZThreads, 0, stream>>>(G, b0, wb4, w.b[3], nullptr, disp);
     } else {
         k3c_wprep<<<(NWT + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[1], wt2);
         k3c_wprep<<<(NWT + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[2], wt3);
-        k3c_conv1<float><<<c1grid, kC1R * kC1W, 0, stream>>>(G, vel, w.w[0], w.b[0], act0);
+        k3c_zconv1<float><<<(unsigned)zblocks, kZ1Threads, 0, stream>>>(G, vel, w.w[0], w.b[0], act0);
         k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act0, wt2, w.b[1], act1);
         k3c_conv32<<<grid, kWaves32 * 64, 0, stream>>>(G, act1, wt3, w.b[2], act0);
-        k3c_conv4<<<grid, kWaves4 * 64, 0, stream>>>(G, act0, w.w[3], w.b[3], disp);
+        const int64_t z4blocks = (int64_t)((G + Z4X - 1) / Z4X) * ((G + Z4Y - 1) / Z4Y) * ((G + Z4P - 1) / Z4P);
+        if (z4blocks > (int64_t)UINT32_MAX) fail(CNNSNS_EINVAL, "predict3d: overlay too large");
+        float* w4t = wt3 + NWT;
+        k3c_wprep4_f32<<<(TAPS * C * CIO + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[3], w4t);
+        k3c_zconv4_f32<<<(unsigned)z4blocks, kZ4Threads, 0, stream>>>(G, act0, w4t, w.b[3], disp);
     }
     hip_check(hipGetLastError(), "predict3d launch");
     workspace_used(m.ws, stream);

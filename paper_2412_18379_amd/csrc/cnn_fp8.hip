@@ -85,85 +85,119 @@ __global__ void k_fp8_clear(Fp8Scales* s)
     if (threadIdx.x == 0 && blockIdx.x == 0) s->vmax_bits = 0u;
 }
 
-// max |u|, |v| over the 2 G^2 velocity values: wave maxima, one atomic per wavefront
-__global__ __launch_bounds__(256) void k_fp8_absmax(int64_t count, const float* __restrict__ vel, Fp8Scales* s)
+// max |u|, |v| over the 2 G^2 velocity values: a block reduces its share through LDS and makes one
+// atomic update (one per wavefront on a single word serialises thousands of updates)
+constexpr int kMaxThreads = 512;
+__global__ __launch_bounds__(kMaxThreads) void k_fp8_absmax(int64_t count, const float* __restrict__ vel, Fp8Scales* s)
 {
+    __shared__ float s_m[kMaxThreads / 64];
     float m = 0.f;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x)
         m = fmaxf(m, fabsf(vel[k]));
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(&s->vmax_bits, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kMaxThreads / 64; ++w) m = fmaxf(m, s_m[w]);
+        atomicMax(&s->vmax_bits, __float_as_uint(m));
+    }
 }
 
-// Weight scales, activation scales and the packed e4m3 weights; one block.
+// Weight scales, activation scales and the packed e4m3 weights; one block of 1024 threads.  The
+// FP32 weights are staged in LDS (78 KiB), each wavefront reduces the max and the sum of |w| of
+// its output channels, the first wavefront chains the layer bounds (one lane per channel), and
+// all threads pack.
+constexpr int NW1 = C * 2 * 9, NW23 = C * C * 9, NW4 = 2 * C * 9;
 __global__ __launch_bounds__(1024) void k_fp8_prep(const float* __restrict__ w1, const float* __restrict__ w2,
                                                    const float* __restrict__ w3, const float* __restrict__ w4,
                                                    const float* __restrict__ b1, const float* __restrict__ b2,
                                                    const float* __restrict__ b3, Fp8Scales* s,
                                                    fp8x8* __restrict__ packed)
 {
-    __shared__ float s_rsum[3][C];  // sum of |w| over inputs and taps per output channel, layers 1..3
-    const int tid = threadIdx.x;
-    // per output channel: max |w| (its scale) and sum |w|
-    if (tid < 3 * C + 2) {
-        const int l = tid < 3 * C ? tid / C : 3, o = tid < 3 * C ? tid % C : tid - 3 * C;
-        const float* w = l == 0 ? w1 : (l == 1 ? w2 : (l == 2 ? w3 : w4));
+    __shared__ float s_w[NW1 + 2 * NW23 + NW4];
+    __shared__ float s_rsum[3][C];   // sum of |w| over inputs and taps per output channel, layers 1..3
+    __shared__ float s_scale[4][C];  // weight scale per layer and output channel
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float* const sw1 = s_w;
+    float* const sw2 = sw1 + NW1;
+    float* const sw3 = sw2 + NW23;
+    float* const sw4 = sw3 + NW23;
+    for (int k = tid; k < NW1; k += 1024) sw1[k] = w1[k];
+    for (int k = tid; k < NW23; k += 1024) {
+        sw2[k] = w2[k];
+        sw3[k] = w3[k];
+    }
+    for (int k = tid; k < NW4; k += 1024) sw4[k] = w4[k];
+    __syncthreads();
+    // channel c = 0 .. 97: layer c / 32 (layer 4: c = 96, 97), output channel c % 32
+    for (int c = wave; c < 3 * C + 2; c += 16) {
+        const int l = c < 3 * C ? c / C : 3, o = c < 3 * C ? c % C : c - 3 * C;
+        const float* w = l == 0 ? sw1 : (l == 1 ? sw2 : (l == 2 ? sw3 : sw4));
         const int per = (l == 0 ? 2 : C) * 9;
         float mx = 0.f, sm = 0.f;
-        for (int k = 0; k < per; ++k) {
+        for (int k = lane; k < per; k += 64) {
             const float a = fabsf(w[o * per + k]);
             mx = fmaxf(mx, a);
             sm += a;
         }
-        s->s_w[l][o] = pow2_at_least(mx / 448.f);
-        if (l < 3) s_rsum[l][o] = sm;
+        for (int off = 32; off > 0; off >>= 1) {
+            mx = fmaxf(mx, __shfl_xor(mx, off));
+            sm += __shfl_xor(sm, off);
+        }
+        if (lane == 0) {
+            s_scale[l][o] = pow2_at_least(mx / 448.f);
+            if (l < 3) s_rsum[l][o] = sm;
+        }
     }
     __syncthreads();
-    if (tid == 0) {
+    if (wave == 0) {
         const float margin = 1.25f;  // covers the rounding of operands (at most 2^-4 each)
-        const float* bs[3] = { b1, b2, b3 };
+        const int o = lane & (C - 1);
+        const float bl[3] = { b1[o], b2[o], b3[o] };
         float A = __uint_as_float(s->vmax_bits);
         float s_in = pow2_at_least(A / 448.f);
-        s->s_v = s_in;
+        if (lane == 0) s->s_v = s_in;
         for (int l = 0; l < 3; ++l) {
-            float P = 0.f;
-            for (int o = 0; o < C; ++o) P = fmaxf(P, margin * s_rsum[l][o] * A + fabsf(bs[l][o]));
+            float P = margin * s_rsum[l][o] * A + fabsf(bl[l]);
+            for (int off = 16; off > 0; off >>= 1) P = fmaxf(P, __shfl_xor(P, off));
             const float s_out = pow2_at_least(P / 448.f);
-            s->s_a[l] = s_out;
-            for (int o = 0; o < C; ++o) {
-                const float sc = s->s_w[l][o] * s_in;
-                s->init[l][o] = bs[l][o] / sc;
+            if (lane < C) {
+                const float sc = s_scale[l][o] * s_in;
+                s->s_w[l][o] = s_scale[l][o];
+                s->init[l][o] = bl[l] / sc;
                 s->fac[l][o] = sc / s_out;
             }
+            if (lane == 0) s->s_a[l] = s_out;
             A = P;
             s_in = s_out;
         }
-        s->out4[0] = s->s_w[3][0] * s_in;
-        s->out4[1] = s->s_w[3][1] * s_in;
+        if (lane < 2) {
+            s->s_w[3][lane] = s_scale[3][lane];
+            s->out4[lane] = s_scale[3][lane] * s_in;
+        }
     }
-    __syncthreads();
-    for (int e = tid; e < PACKED; e += blockDim.x) {
+    for (int e = tid; e < PACKED; e += 1024) {
         const int l = e & 63, i = l & 15, q = l >> 4;
         float v[8];
         if (e < P1) {
             const int o = (e >> 6) * 16 + i;
-            const float r = 1.f / s->s_w[0][o];
+            const float r = 1.f / s_scale[0][o];
             for (int j = 0; j < 8; ++j) {
                 const int k = 8 * q + j;
-                v[j] = k < 18 ? w1[(o * 2 + (k & 1)) * 9 + (k >> 1)] * r : 0.f;
+                v[j] = k < 18 ? sw1[(o * 2 + (k & 1)) * 9 + (k >> 1)] * r : 0.f;
             }
         } else if (e < P1 + 2 * P2) {
             const int f = e - P1;
             const int layer = f < P2 ? 1 : 2;
-            const float* w = f < P2 ? w2 : w3;
+            const float* w = f < P2 ? sw2 : sw3;
             const int g = f % P2, t = g / 128, o = ((g >> 6) & 1) * 16 + i;
-            const float r = 1.f / s->s_w[layer][o];
+            const float r = 1.f / s_scale[layer][o];
             for (int j = 0; j < 8; ++j) v[j] = w[(o * C + chan_at(8 * q + j)) * 9 + t] * r;
         } else {
             const int n = 16 * ((e - P1 - 2 * P2) >> 6) + i;
-            const float r = n < 18 ? 1.f / s->s_w[3][n / 9] : 0.f;
+            const float r = n < 18 ? 1.f / s_scale[3][n / 9] : 0.f;
             for (int j = 0; j < 8; ++j)
-                v[j] = n < 18 ? w4[((n / 9) * C + chan_at(8 * q + j)) * 9 + n % 9] * r : 0.f;
+                v[j] = n < 18 ? sw4[((n / 9) * C + chan_at(8 * q + j)) * 9 + n % 9] * r : 0.f;
         }
         uint64_t word = 0;
         for (int j = 0; j < 8; j += 2) word |= (uint64_t)to_e4m3_pair(v[j], v[j + 1]) << (8 * j);
@@ -439,8 +473,8 @@ void cnn_fp8_forward(int32_t G, const float* vel, const cnnsns_cnn& w, float* di
     Fp8Scales* sc = reinterpret_cast<Fp8Scales*>(static_cast<char*>(ws) + sizeof(fp8x8) * (size_t)PACKED);
     const int64_t count = 2 * (int64_t)G * G;
     k_fp8_clear<<<1, 64, 0, stream>>>(sc);
-    const unsigned rb = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (count + 255) / 256));
-    k_fp8_absmax<<<rb, 256, 0, stream>>>(count, vel, sc);
+    const unsigned rb = (unsigned)std::min<int64_t>(512, std::max<int64_t>(1, (count + kMaxThreads - 1) / kMaxThreads));
+    k_fp8_absmax<<<rb, kMaxThreads, 0, stream>>>(count, vel, sc);
     k_fp8_prep<<<1, 1024, 0, stream>>>(w.w[0], w.w[1], w.w[2], w.w[3], w.b[0], w.b[1], w.b[2], sc, packed);
     const int tx = (int)cdiv(G, OW), nt = tx * (int)cdiv(G, OH);
     unsigned g = grid < (unsigned)nt ? grid : (unsigned)nt;

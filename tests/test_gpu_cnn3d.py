@@ -163,7 +163,8 @@ def _within_bf16_bar(got, ref):
     return float((err.max(axis=1) / scale).max()), float((err.mean(axis=1) / scale).max())
 
 
-@pytest.mark.parametrize("G", [5, 17, 33])
+# 33 and 70: ragged z-sweep blocks in every dimension (8 x 32 cells, 32 planes per block)
+@pytest.mark.parametrize("G", [5, 17, 33, 70])
 def test_bf16_forward_full_grid(C, oracle_mod, G):
     rng = np.random.default_rng(200 + G)
     vel = rng.standard_normal((3, G, G, G)).astype(np.float32)
