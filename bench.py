@@ -336,7 +336,9 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float, with_cpu: bool 
                          "path_length_p50_p99_max": [pct(it_a, 50), pct(it_a, 99), int(it_a.max())],
                          "found_frac": float(np.mean(st_a == C.FOUND)),
                          "host_agreement_with_plain": float(np.mean(host_a == host_p))},
-        "cnn_sns": {"weights": "constructed pass-through (-dt u of the origin's cell), not trained",
+        "cnn_sns": {"weights": ("constructed pass-through (-dt u of the origin's cell); the forward pass costs the "
+                                "same for any weights, and the net trained in the loop is timed and walked in "
+                                "online_training_3d_leg"),
                     "predict_ms": round(float(p3_ms.mean()), 4), "locate_ms": round(float(l3_ms.mean()), 4),
                     "step_ms": round(float((p3_ms + l3_ms).mean()), 4),
                     "points_per_s": round(n / ((p3_ms + l3_ms).mean() / 1e3), 1),
@@ -345,7 +347,7 @@ def walk3d_leg(name: str, K: int, warmup: int, copy_gbps: float, with_cpu: bool 
                     "path_length_p50_p99_max": [pct(it_c, 50), pct(it_c, 99), int(it_c.max())],
                     "found_frac": float(np.mean(st_c == C.FOUND)),
                     "host_agreement_with_plain": float(np.mean(host_c == host_p)),
-                    "cnn_roofline": {"kernel": "3D cnn forward (k3c_conv1 + 2 x k3c_conv32 + k3c_conv4)",
+                    "cnn_roofline": {"kernel": "3D cnn forward (k3c_zconv1 + 2 x k3c_conv32 + k3c_zconv4_f32)",
                                      "bound": "mfma", "achieved": round(cnn3_tf, 3), "peak": PEAK["f32_TFLOPs"],
                                      "unit": "TFLOP/s", "frac": round(cnn3_tf / PEAK["f32_TFLOPs"], 4),
                                      "traffic": traffic_for("cnn3_forward_f32", name),
