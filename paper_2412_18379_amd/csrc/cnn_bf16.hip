@@ -197,7 +197,7 @@ __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* _
         // result: lane (i, q) holds region pixels (g + m) 16 + 4q + r, channels i and 16 + i
 #pragma unroll
         for (int m = 0; m < MB; ++m)
-            if (NMB % BPW == 0 || g + m < NMB)
+            if (NMB == BPW * kWaves || g + m < NMB)
                 store_block<WO, EDGE>(out, (g + m) * 16 + 4 * q, i, acc[m][0], acc[m][1], oy0, ox0, G);
     }
 }
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             }
 #pragma unroll
             for (int m = 0; m < MB1; ++m) {
-                if (NMB1 % BPW1 == 0 || g + m < NMB1) {
+                if (NMB1 == BPW1 * kWaves || g + m < NMB1) {
                     if (edge)
                         store_block<W1, true>(bufA, (g + m) * 16 + 4 * q, i, d[m][0], d[m][1], ty0 - 3, tx0 - 3, G);
                     else

@@ -288,7 +288,7 @@ __device__ __forceinline__ void conv32_fp8(const uint8_t* __restrict__ in, uint8
         }
 #pragma unroll
         for (int m = 0; m < MB; ++m)
-            if (NMB % BPW == 0 || g + m < NMB)
+            if (NMB == BPW * kWaves || g + m < NMB)
                 store_block<WO, EDGE>(out, (g + m) * 16 + 4 * q, i, acc[m][0], acc[m][1], flo, fhi, oy0, ox0, G);
     }
 }
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             }
 #pragma unroll
             for (int m = 0; m < MB1; ++m) {
-                if (NMB1 % BPW1 == 0 || g + m < NMB1) {
+                if (NMB1 == BPW1 * kWaves || g + m < NMB1) {
                     if (edge)
                         store_block<W1, true>(bufA, (g + m) * 16 + 4 * q, i, d[m][0], d[m][1], f1lo, f1hi, ty0 - 3,
                                               tx0 - 3, G);
