@@ -264,6 +264,12 @@ __global__ __launch_bounds__(kZThreads) __attribute__((amdgpu_waves_per_eu(2, 2)
     fetch(z0 + 1);
     stash(z0 + 1);
     __syncthreads();
+    // the first 16 output channels' weights stay in registers for the whole sweep (all of the
+    // layer's weights do not fit beside the operands at two wavefronts per SIMD); the other block's
+    // are read from LDS per tap
+    bf16x8 wr[TAPS];
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) wr[t] = s_w[(t * NB) * 64 + lane];
 
     v4f bl[2];
 #pragma unroll
@@ -281,7 +287,7 @@ __global__ __launch_bounds__(kZThreads) __attribute__((amdgpu_waves_per_eu(2, 2)
         for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) acc[h][nb] = bl[nb];
-#pragma unroll 1
+#pragma unroll
         for (int dz = 0; dz < 3; ++dz) {
             const bf16* sl = s_slab + ((z + dz - 1 + 3) % 3) * ZSLAB;
 #pragma unroll
@@ -291,7 +297,7 @@ __global__ __launch_bounds__(kZThreads) __attribute__((amdgpu_waves_per_eu(2, 2)
                 const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(sl + base[1] + off);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const bf16x8 w = s_w[(t * NB + nb) * 64 + lane];
+                    const bf16x8 w = nb == 0 ? wr[t] : s_w[(t * NB + nb) * 64 + lane];
                     acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, a0, acc[0][nb], 0, 0, 0);
                     acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, a1, acc[1][nb], 0, 0, 0);
                 }
@@ -403,6 +409,119 @@ __global__ __launch_bounds__(kZ1Threads) void k3c_zconv1(int32_t G, const float*
                 *reinterpret_cast<bf16x4*>(dst) = __builtin_convertvector(v0, bf16x4);
                 *reinterpret_cast<bf16x4*>(dst + 16) = __builtin_convertvector(v1, bf16x4);
             }
+        }
+        __syncthreads();
+        if (z + 2 < z1 + 1) stash(z + 2);
+        __syncthreads();
+    }
+}
+
+// Layer 1 of the BF16 pass on the BF16 matrix cores with split operands: each velocity value
+// v = v_h + v_l and each weight w = w_h + w_l as a BF16 pair (v_h, w_h rounded to nearest, the
+// rest rounded again), and w v taken as w_h v_h + w_h v_l + w_l v_h, which is within about 2^-16
+// of it, far below the BF16 rounding of the layer's output.  A slab cell holds
+// (v_h0, v_h1, v_h2, v_l0, v_l1, v_l2, 0, 0); a tap takes K = 16 (two lane groups that both read
+// that cell): weights (w_h, w_h, 0) against it for the first group, (w_l, 0, 0) for the second,
+// so a K = 32 step covers two taps (14 steps for 27 taps, the last half empty).
+constexpr int NW1S = 14 * 2 * 64;  // bf16x8 operands of the split layer 1
+
+// wb[(s * 2 + nb) * 64 + l]: output channel 16 nb + l%16; lane group g = l/16 takes tap 2 s + g/2
+__global__ void k3c_wprep1_split(const float* __restrict__ w, bf16x8* __restrict__ wb)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NW1S) return;
+    const int l = k & 63, nb = (k >> 6) & 1, st = k >> 7, g = l >> 4;
+    const int o = 16 * nb + (l & 15), t = 2 * st + (g >> 1);
+    bf16x8 v = bf16x8{ 0, 0, 0, 0, 0, 0, 0, 0 };
+    if (t < TAPS) {
+#pragma unroll
+        for (int ci = 0; ci < CIO; ++ci) {
+            const float x = w[(o * CIO + ci) * TAPS + t];
+            const bf16 hi = (bf16)x;
+            const bf16 lo = (bf16)(x - (float)hi);
+            if ((g & 1) == 0) {
+                v[ci] = hi;
+                v[3 + ci] = hi;
+            } else {
+                v[ci] = lo;
+            }
+        }
+    }
+    wb[k] = v;
+}
+
+__global__ __launch_bounds__(kZ1Threads) void k3c_zconv1_split(int32_t G, const float* __restrict__ vel,
+                                                               const bf16x8* __restrict__ wb,
+                                                               const float* __restrict__ bias, bf16* __restrict__ out)
+{
+    constexpr int NCELL = ZSY * ZSX;
+    static_assert(NCELL <= kZ1Threads && ZY * ZX == (kZ1Threads / 64) * 16, "one slab cell per thread");
+    static_assert((NWB + NW1S) * sizeof(bf16x8) <= NWT * sizeof(float), "layer 1's operands fit after layer 2's");
+    __shared__ __attribute__((aligned(16))) bf16x8 s_v[3 * NCELL];
+    __shared__ bf16x8 s_w[NW1S];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    for (int k = tid; k < NW1S; k += kZ1Threads) s_w[k] = wb[k];
+    const int tiles_x = (G + ZX - 1) / ZX, tiles_y = (G + ZY - 1) / ZY;
+    const int64_t b = blockIdx.x;
+    const int tx0 = (int)(b % tiles_x) * ZX, ty0 = (int)((b / tiles_x) % tiles_y) * ZY;
+    const int z0 = (int)(b / ((int64_t)tiles_x * tiles_y)) * ZP;
+    const int z1 = min(z0 + ZP, G);
+    const int64_t GG = (int64_t)G * G, n = GG * G;
+    const int r = wave >> 1, h = wave & 1;
+
+    bf16x8 pf;
+    auto fetch = [&](int p) {  // thread tid < NCELL: its slab cell of plane p (zero outside the grid)
+        float v[3] = { 0.f, 0.f, 0.f };
+        if (tid < NCELL) {
+            const int gy = ty0 + tid / ZSX - 1, gx = tx0 + tid % ZSX - 1;
+            if (p >= 0 && p < G && gy >= 0 && gy < G && gx >= 0 && gx < G) {
+                const int64_t c = (int64_t)p * GG + (int64_t)gy * G + gx;
+                v[0] = vel[c];
+                v[1] = vel[n + c];
+                v[2] = vel[2 * n + c];
+            }
+        }
+        pf = bf16x8{ 0, 0, 0, 0, 0, 0, 0, 0 };
+#pragma unroll
+        for (int ci = 0; ci < CIO; ++ci) {
+            const bf16 hi = (bf16)v[ci];
+            pf[ci] = hi;
+            pf[3 + ci] = (bf16)(v[ci] - (float)hi);
+        }
+    };
+    auto stash = [&](int p) {
+        if (tid < NCELL) s_v[((p + 3) % 3) * NCELL + tid] = pf;
+    };
+    fetch(z0 - 1);
+    stash(z0 - 1);
+    fetch(z0);
+    stash(z0);
+    fetch(z0 + 1);
+    stash(z0 + 1);
+    __syncthreads();
+    const v4f bl0 = *reinterpret_cast<const v4f*>(bias + 4 * grp);
+    const v4f bl1 = *reinterpret_cast<const v4f*>(bias + 16 + 4 * grp);
+    const int cell0 = r * ZSX + 16 * h + col;
+    for (int z = z0; z < z1; ++z) {
+        if (z + 2 < z1 + 1) fetch(z + 2);
+        v4f acc0 = bl0, acc1 = bl1;
+#pragma unroll
+        for (int st = 0; st < 14; ++st) {
+            int t = 2 * st + (grp >> 1);
+            t = t < TAPS ? t : 13;  // zero weights: any finite operand serves
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            const bf16x8 a = s_v[((z + dz - 1 + 3) % 3) * NCELL + cell0 + dy * ZSX + dx];
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[(st * 2) * 64 + lane], a, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[(st * 2 + 1) * 64 + lane], a, acc1, 0, 0, 0);
+        }
+        const int gy = ty0 + r, gx = tx0 + 16 * h + col;
+        if (gy < G && gx < G) {
+            bf16* dst = out + ((int64_t)z * GG + (int64_t)gy * G + gx) * C + 4 * grp;
+            const v4f v0{ fmaxf(acc0.x, 0.f), fmaxf(acc0.y, 0.f), fmaxf(acc0.z, 0.f), fmaxf(acc0.w, 0.f) };
+            const v4f v1{ fmaxf(acc1.x, 0.f), fmaxf(acc1.y, 0.f), fmaxf(acc1.z, 0.f), fmaxf(acc1.w, 0.f) };
+            *reinterpret_cast<bf16x4*>(dst) = __builtin_convertvector(v0, bf16x4);
+            *reinterpret_cast<bf16x4*>(dst + 16) = __builtin_convertvector(v1, bf16x4);
         }
         __syncthreads();
         if (z + 2 < z1 + 1) stash(z + 2);
@@ -546,7 +665,9 @@ void run_predict3(cnnsns_mesh3_s& m, const float* vel, const cnnsns_cnn& w, int3
         bf16x8* wb3 = reinterpret_cast<bf16x8*>(wt3);
         k3c_wprep_bf16<<<(NWB + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[1], wb2);
         k3c_wprep_bf16<<<(NWB + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[2], wb3);
-        k3c_zconv1<bf16><<<(unsigned)zblocks, kZ1Threads, 0, stream>>>(G, vel, w.w[0], w.b[0], b0);
+        bf16x8* wb1 = wb2 + NWB;  // after layer 2's operands in their 108 KiB region
+        k3c_wprep1_split<<<(NW1S + kBlock - 1) / kBlock, kBlock, 0, stream>>>(w.w[0], wb1);
+        k3c_zconv1_split<<<(unsigned)zblocks, kZ1Threads, 0, stream>>>(G, vel, wb1, w.b[0], b0);
         k3c_zsweep_bf16<2><<<(unsigned)zblocks, kZThreads, 0, stream>>>(G, b0, wb2, w.b[1], b1, nullptr);
         k3c_zsweep_bf16<2><<<(unsigned)zblocks, kZThreads, 0, stream>>>(G, b1, wb3, w.b[2], b0, nullptr);
         bf16x8* wb4 = wb3 + NWB;
