@@ -163,8 +163,9 @@ def _within_bf16_bar(got, ref):
     return float((err.max(axis=1) / scale).max()), float((err.mean(axis=1) / scale).max())
 
 
-# 33 and 70: ragged z-sweep blocks in every dimension (8 x 32 cells, 32 planes per block)
-@pytest.mark.parametrize("G", [5, 17, 33, 70])
+# 1-3: grids smaller than one block's column; 33 and 70: ragged z-sweep blocks in every dimension
+# (8 x 32 cells and 32 planes per block)
+@pytest.mark.parametrize("G", [1, 2, 3, 5, 17, 33, 70])
 def test_bf16_forward_full_grid(C, oracle_mod, G):
     rng = np.random.default_rng(200 + G)
     vel = rng.standard_normal((3, G, G, G)).astype(np.float32)
