@@ -124,7 +124,8 @@ __global__ void k_pool_mean(int32_t G, const ElemRec* __restrict__ rec, const in
     pool[c] = p;
 }
 
-// Module 1 (window, conv1, conv2, pooling) and module 2's first layer, one wavefront per particle: writes
+// Module 1 (window, conv1, conv2, pooling) and module 2's first layer, one wavefront per particle at a time
+// (persistent blocks loop over the particles with the weights staged once): writes
 // z[i][0 .. 255] and m1[i][0 .. 255] (row strides ldz, ldm).
 __global__ __launch_bounds__(kBlock) void k_cls_module1(
     int64_t n, const double2* __restrict__ xp, int32_t G, const double2* __restrict__ pool,
@@ -136,8 +137,9 @@ __global__ __launch_bounds__(kBlock) void k_cls_module1(
     __shared__ float s_w1[kC * 2 * 9], s_b1[kC], s_b2[kC];
     __shared__ float s_w2[9][kC][kC + 1];  // [tap][in channel][out channel], padded
     __shared__ float s_in[kWaves][2][kPW * kPW];
+    // conv1's output on the bordered window; conv2's output goes to its interior once conv2 has read it
     __shared__ float s_a1[kWaves][kPW * kPW][kC + 1];
-    __shared__ float s_a2[kWaves][kNA][kC + 1];
+    __shared__ float s_x1[kH1][3];  // module 2's first layer: (w0, w1, bias) per output
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int k = tid; k < kC * 2 * 9; k += kBlock) s_w1[k] = w1[k];
@@ -149,29 +151,65 @@ __global__ __launch_bounds__(kBlock) void k_cls_module1(
         s_b1[tid] = b1[tid];
         s_b2[tid] = b2[tid];
     }
-    const int64_t i = (int64_t)blockIdx.x * kWaves + wave;
-    const bool live = i < n;
+    for (int j = tid; j < kH1; j += kBlock) {
+        s_x1[j][0] = wx1[2 * j];
+        s_x1[j][1] = wx1[2 * j + 1];
+        s_x1[j][2] = bx1[j];
+    }
     float* in = &s_in[wave][0][0];
     for (int k = lane; k < 2 * kPW * kPW; k += 64) in[k] = 0.f;
     for (int k = lane; k < kPW * kPW * (kC + 1); k += 64) (&s_a1[wave][0][0])[k] = 0.f;
-    __syncthreads();  // the zero borders before the window and conv1 outputs land on them
-    float xo0 = 0.f, xo1 = 0.f;
-    if (live) {
-        const double2 p = xp[i];
-        const int32_t cx = cell_of(p.x, G), cy = cell_of(p.y, G);
-        for (int o = lane; o < kNA; o += 64) {
-            const int dy = o / kW - kR, dx = o % kW - kR;
-            const double2 q = pool[(int64_t)clamp_cell(cy + dy, G) * G + clamp_cell(cx + dx, G)];
-            const int at = (dy + kR + 1) * kPW + (dx + kR + 1);
-            in[at] = (float)((q.x - p.x) * (double)G);
-            in[kPW * kPW + at] = (float)((q.y - p.y) * (double)G);
-        }
-        xo0 = (float)(p.x * (double)G - ((double)cx + 0.5));
-        xo1 = (float)(p.y * (double)G - ((double)cy + 0.5));
+    __syncthreads();  // the weights and the zero borders, which no point's writes touch
+    // a wavefront takes points i, i + the grid's wavefront count, ...: its window, conv1 output and
+    // conv2 output are its own LDS regions, so only the wavefront's own accesses need ordering
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    };
+    const int row = lane & 15, kq = lane >> 4;
+    int base[6];
+#pragma unroll
+    for (int mb = 0; mb < 6; ++mb) {
+        const int px = min(mb * 16 + row, kNA - 1), r = px / kW, c = px % kW;
+        base[mb] = r * kPW + c;  // top-left tap in the bordered window
     }
-    __syncthreads();
-    // conv1 (2 -> 16) on the vector ALUs: a lane per pixel, 16 outputs each
-    if (live) {
+    // the window's pooled values of the wavefront's next particle are gathered into registers while
+    // the current one computes (lane o holds window cells o and o + 64)
+    const int64_t stride = (int64_t)gridDim.x * kWaves;
+    double2 pn = double2{ 0.0, 0.0 };
+    double2 qn[2] = { double2{ 0.0, 0.0 }, double2{ 0.0, 0.0 } };
+    auto gather = [&](int64_t k) {
+        pn = xp[k];
+        const int32_t gx = cell_of(pn.x, G), gy = cell_of(pn.y, G);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int o = lane + 64 * u;
+            if (o < kNA) {
+                const int dy = o / kW - kR, dx = o % kW - kR;
+                qn[u] = pool[(int64_t)clamp_cell(gy + dy, G) * G + clamp_cell(gx + dx, G)];
+            }
+        }
+    };
+    int64_t i = (int64_t)blockIdx.x * kWaves + wave;
+    if (i < n) gather(i);
+    for (; i < n; i += stride) {
+        const double2 p = pn;
+        const int32_t cx = cell_of(p.x, G), cy = cell_of(p.y, G);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int o = lane + 64 * u;
+            if (o < kNA) {
+                const int dy = o / kW - kR, dx = o % kW - kR;
+                const int at = (dy + kR + 1) * kPW + (dx + kR + 1);
+                in[at] = (float)((qn[u].x - p.x) * (double)G);
+                in[kPW * kPW + at] = (float)((qn[u].y - p.y) * (double)G);
+            }
+        }
+        const float xo0 = (float)(p.x * (double)G - ((double)cx + 0.5));
+        const float xo1 = (float)(p.y * (double)G - ((double)cy + 0.5));
+        wave_sync();
+        if (i + stride < n) gather(i + stride);
+        // conv1 (2 -> 16) on the vector ALUs: a lane per pixel, 16 outputs each
         for (int px = lane; px < kNA; px += 64) {
             const int r = px / kW, c = px % kW;
             float acc[kC];
@@ -189,51 +227,42 @@ __global__ __launch_bounds__(kBlock) void k_cls_module1(
 #pragma unroll
             for (int o = 0; o < kC; ++o) dst[o] = fmaxf(acc[o], 0.f);
         }
-    }
-    __syncthreads();
-    // conv2 (16 -> 16) on the matrix cores: rows = pixels (6 blocks of 16, the last partly repeated),
-    // columns = output channels, k = 16 tap + input channel in 36 steps of 4
-    if (live) {
-        const int row = lane & 15, kq = lane >> 4;
-        int base[6];
-#pragma unroll
-        for (int mb = 0; mb < 6; ++mb) {
-            const int px = min(mb * 16 + row, kNA - 1), r = px / kW, c = px % kW;
-            base[mb] = r * kPW + c;  // top-left tap in the bordered window
-        }
+        wave_sync();
+        // conv2 (16 -> 16) on the matrix cores: rows = pixels (6 blocks of 16, the last partly
+        // repeated), columns = output channels, k = 16 tap + input channel in 36 steps of 4
         v4f acc[6];
 #pragma unroll
         for (int mb = 0; mb < 6; ++mb) acc[mb] = v4f{ 0.f, 0.f, 0.f, 0.f };
         for (int s = 0; s < 36; ++s) {
             const int t = s >> 2, ch = 4 * (s & 3) + kq;
             const int off = (t / 3) * kPW + t % 3;
-            const float b = s_w2[t][ch][row];
+            const float bw = s_w2[t][ch][row];
 #pragma unroll
             for (int mb = 0; mb < 6; ++mb)
-                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_a1[wave][base[mb] + off][ch], b, acc[mb], 0, 0, 0);
+                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_a1[wave][base[mb] + off][ch], bw, acc[mb], 0, 0, 0);
         }
-        // lane holds pixels 16 mb + 4 kq + e of output channel `row`
+        wave_sync();  // conv2 has read all of conv1's output
+        // lane holds pixels 16 mb + 4 kq + e of output channel `row`: into the interior of the window
 #pragma unroll
         for (int mb = 0; mb < 6; ++mb)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int px = mb * 16 + 4 * kq + e;
-                if (px < kNA) s_a2[wave][px][row] = fmaxf(acc[mb][e] + s_b2[row], 0.f);
+                if (px < kNA) s_a1[wave][(px / kW + 1) * kPW + px % kW + 1][row] = fmaxf(acc[mb][e] + s_b2[row], 0.f);
             }
-    }
-    __syncthreads();
-    if (live) {
+        wave_sync();
         // 2 x 2 average pooling, [channel][row][col] order
         for (int f = lane; f < kNF; f += 64) {
             const int ch = f >> 4, pr = (f >> 2) & 3, pc = f & 3;
-            const int p0 = 2 * pr * kW + 2 * pc;
-            const float q = ((s_a2[wave][p0][ch] + s_a2[wave][p0 + 1][ch]) + s_a2[wave][p0 + kW][ch]) +
-                            s_a2[wave][p0 + kW + 1][ch];
+            const int p0 = (2 * pr + 1) * kPW + 2 * pc + 1;
+            const float q = ((s_a1[wave][p0][ch] + s_a1[wave][p0 + 1][ch]) + s_a1[wave][p0 + kPW][ch]) +
+                            s_a1[wave][p0 + kPW + 1][ch];
             z[i * ldz + f] = q * 0.25f;
         }
         // module 2, first layer: FC 2 -> 256 on x_p's offset
         for (int j = lane; j < kH1; j += 64)
-            m1[i * ldm + j] = fmaxf(bx1[j] + wx1[2 * j] * xo0 + wx1[2 * j + 1] * xo1, 0.f);
+            m1[i * ldm + j] = fmaxf(s_x1[j][2] + s_x1[j][0] * xo0 + s_x1[j][1] * xo1, 0.f);
+        wave_sync();  // the next point's window and conv1 output replace these
     }
 }
 
@@ -422,7 +451,9 @@ void run_classify(cnnsns_mesh_s& m, int64_t n, const double* xp, const cnnsns_cl
     for (int64_t c0 = 0; c0 < n; c0 += ch) {
         const int mc = (int)(n - c0 < ch ? n - c0 : ch);
         float* L = logits ? logits + c0 * kNA : Lw;
-        k_cls_module1<<<blocks_for(mc, kBlock / 64), kBlock, 0, stream>>>(
+        // persistent: three blocks per compute unit fit its LDS
+        const unsigned mblocks = std::min<unsigned>(blocks_for(mc, kBlock / 64), cnn_persistent_grid() * 3);
+        k_cls_module1<<<mblocks, kBlock, 0, stream>>>(
             mc, xp2 + c0, m.G, static_cast<const double2*>(m.cls_pool), w.w[0], w.b[0], w.w[1], w.b[1], w.w[2], w.b[2],
             Z, kNZ, Hb, kH2);
         const dim3 g256(blocks_for(mc, 64), kH1 / 64), g512(blocks_for(mc, 64), kH2 / 64), g81(blocks_for(mc, 64), 2);
