@@ -55,10 +55,10 @@ def cnn_issued_macs(G: int, precision: str) -> float:
     raise ValueError(precision)
 
 
-# the classifier CNN (Sec. 2.3) per point: matrix-core MACs issued (conv2 on 96 rows of 16 x 144, the FC
-# layers 256 x 256, 512 x 512 and 512 x 128 with the 81 logits padded to two 64-column tiles) and the
-# products the network needs (conv1 and module 2's first layer run on the vector ALUs)
-CLS_ISSUED_MACS = 96 * 144 * 16 + 256 * 256 + 512 * 512 + 512 * 128  # 614,400
+# the classifier CNN (Sec. 2.3) per point: matrix-core MACs issued (conv1 on 96 rows of 16 x 20, conv2 on
+# 96 rows of 16 x 144, the FC layers 256 x 256, 512 x 512 and 512 x 128 with the 81 logits padded to two
+# 64-column tiles) and the products the network needs (module 2's first layer runs on the vector ALUs)
+CLS_ISSUED_MACS = 96 * 20 * 16 + 96 * 144 * 16 + 256 * 256 + 512 * 512 + 512 * 128  # 645,120
 CLS_USEFUL_MACS = 81 * 18 * 16 + 81 * 144 * 16 + 2 * 256 + 256 * 256 + 512 * 512 + 512 * 81  # 579,616
 REC_BYTES = 60  # algorithmic bytes of one element record: 6 FP64 coordinates + 3 int32 neighbours
 # one tetrahedron record: 12 FP64 coordinates, 4 int32 neighbours and the 4 int32 node ids that put

@@ -127,7 +127,7 @@ __global__ void k_pool_mean(int32_t G, const ElemRec* __restrict__ rec, const in
 // Module 1 (window, conv1, conv2, pooling) and module 2's first layer, one wavefront per particle at a time
 // (persistent blocks loop over the particles with the weights staged once): writes
 // z[i][0 .. 255] and m1[i][0 .. 255] (row strides ldz, ldm).
-__global__ __launch_bounds__(kBlock) void k_cls_module1(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_cls_module1(
     int64_t n, const double2* __restrict__ xp, int32_t G, const double2* __restrict__ pool,
     const float* __restrict__ w1, const float* __restrict__ b1, const float* __restrict__ w2,
     const float* __restrict__ b2, const float* __restrict__ wx1, const float* __restrict__ bx1,
@@ -173,6 +173,13 @@ __global__ __launch_bounds__(kBlock) void k_cls_module1(
         const int px = min(mb * 16 + row, kNA - 1), r = px / kW, c = px % kW;
         base[mb] = r * kPW + c;  // top-left tap in the bordered window
     }
+    // conv1's B operands: lane (row, kq) supplies output channel `row` at k = 4 st + kq = 9 ci + tap
+    float w1k[5];
+#pragma unroll
+    for (int st = 0; st < 5; ++st) {
+        const int k = 4 * st + kq;
+        w1k[st] = k < 18 ? s_w1[(row * 2 + k / 9) * 9 + k % 9] : 0.f;
+    }
     // the window's pooled values of the wavefront's next particle are gathered into registers while
     // the current one computes (lane o holds window cells o and o + 64)
     const int64_t stride = (int64_t)gridDim.x * kWaves;
@@ -209,23 +216,31 @@ __global__ __launch_bounds__(kBlock) void k_cls_module1(
         const float xo1 = (float)(p.y * (double)G - ((double)cy + 0.5));
         wave_sync();
         if (i + stride < n) gather(i + stride);
-        // conv1 (2 -> 16) on the vector ALUs: a lane per pixel, 16 outputs each
-        for (int px = lane; px < kNA; px += 64) {
-            const int r = px / kW, c = px % kW;
-            float acc[kC];
+        // conv1 (2 -> 16) on the matrix cores: rows = pixels (6 blocks of 16, the last partly repeated),
+        // columns = output channels, k = 9 channel + tap (18, padded to 20: five steps of 4)
+        {
+            v4f a1[6];
 #pragma unroll
-            for (int o = 0; o < kC; ++o) acc[o] = s_b1[o];
-#pragma unroll 1
-            for (int ci = 0; ci < 2; ++ci)
-#pragma unroll 1
-                for (int t = 0; t < 9; ++t) {
-                    const float v = in[ci * kPW * kPW + (r + t / 3) * kPW + c + t % 3];
+            for (int mb = 0; mb < 6; ++mb) a1[mb] = v4f{ 0.f, 0.f, 0.f, 0.f };
 #pragma unroll
-                    for (int o = 0; o < kC; ++o) acc[o] += s_w1[(o * 2 + ci) * 9 + t] * v;
+            for (int st = 0; st < 5; ++st) {
+                const int k = 4 * st + kq, ci = k / 9, t = k % 9;
+                const int off = ci * kPW * kPW + (t / 3) * kPW + t % 3;
+#pragma unroll
+                for (int mb = 0; mb < 6; ++mb) {
+                    const float av = k < 18 ? in[base[mb] + off] : 0.f;
+                    a1[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, w1k[st], a1[mb], 0, 0, 0);
                 }
-            float* dst = s_a1[wave][(r + 1) * kPW + c + 1];
+            }
+            // lane holds pixels 16 mb + 4 kq + e of output channel `row`
 #pragma unroll
-            for (int o = 0; o < kC; ++o) dst[o] = fmaxf(acc[o], 0.f);
+            for (int mb = 0; mb < 6; ++mb)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int px = mb * 16 + 4 * kq + e;
+                    if (px < kNA)
+                        s_a1[wave][(px / kW + 1) * kPW + px % kW + 1][row] = fmaxf(a1[mb][e] + s_b1[row], 0.f);
+                }
         }
         wave_sync();
         // conv2 (16 -> 16) on the matrix cores: rows = pixels (6 blocks of 16, the last partly
