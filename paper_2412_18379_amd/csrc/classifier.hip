@@ -282,56 +282,66 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 }
 
 // C[m][n] = act(bias[n] + sum_k A[m][k] W[n][k]) for m < M, n < N (W in [out][in] layout); K a multiple of 16,
-// rows of A and W 16-byte aligned.  64 x 64 output tiles, four wavefronts of 32 x 32 each.
+// rows of A and W 16-byte aligned.  128 x 128 output tiles, four wavefronts of 64 x 64 each (4 x 4 blocks of
+// v_mfma_f32_16x16x4f32, so each operand read from LDS feeds four instructions); the next 16-wide K slice
+// is loaded into registers while this one's products issue.
+constexpr int kDT = 128;  // dense tile side
 template <bool RELU>
 __global__ __launch_bounds__(kBlock) void k_dense_f32(int M, int N, int K, const float* __restrict__ A, int lda,
                                                       const float* __restrict__ Wt, const float* __restrict__ bias,
                                                       float* __restrict__ Cm, int ldc)
 {
-    __shared__ float sA[2][64][17], sB[2][64][17];
-    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    __shared__ float sA[2][kDT][17], sB[2][kDT][17];
+    const int m0 = blockIdx.x * kDT, n0 = blockIdx.y * kDT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
     const int row = lane & 15, kq = lane >> 4;
-    const int sr = tid >> 2, sc = (tid & 3) * 4;  // the float4 this thread stages
-    v4f acc[2][2];
+    // the two float4 of each operand tile this thread stages: rows tid / 4 and tid / 4 + 64
+    const int sr = tid >> 2, sc = (tid & 3) * 4;
+    v4f acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = v4f{ 0.f, 0.f, 0.f, 0.f };
-    auto fetch = [&](int k0, v4f& va, v4f& vb) {
-        va = m0 + sr < M ? *reinterpret_cast<const v4f*>(A + (int64_t)(m0 + sr) * lda + k0 + sc)
-                         : v4f{ 0.f, 0.f, 0.f, 0.f };
-        vb = n0 + sr < N ? *reinterpret_cast<const v4f*>(Wt + (int64_t)(n0 + sr) * K + k0 + sc)
-                         : v4f{ 0.f, 0.f, 0.f, 0.f };
-    };
-    auto stash = [&](int buf, const v4f& va, const v4f& vb) {
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{ 0.f, 0.f, 0.f, 0.f };
+    auto fetch = [&](int k0, v4f (&va)[2], v4f (&vb)[2]) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            sA[buf][sr][sc + e] = va[e];
-            sB[buf][sr][sc + e] = vb[e];
+        for (int h = 0; h < 2; ++h) {
+            const int r = sr + 64 * h;
+            va[h] = m0 + r < M ? *reinterpret_cast<const v4f*>(A + (int64_t)(m0 + r) * lda + k0 + sc)
+                               : v4f{ 0.f, 0.f, 0.f, 0.f };
+            vb[h] = n0 + r < N ? *reinterpret_cast<const v4f*>(Wt + (int64_t)(n0 + r) * K + k0 + sc)
+                               : v4f{ 0.f, 0.f, 0.f, 0.f };
         }
     };
-    v4f va, vb;
+    auto stash = [&](int buf, const v4f (&va)[2], const v4f (&vb)[2]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sA[buf][sr + 64 * h][sc + e] = va[h][e];
+                sB[buf][sr + 64 * h][sc + e] = vb[h][e];
+            }
+    };
+    v4f va[2], vb[2];
     fetch(0, va, vb);
     stash(0, va, vb);
     __syncthreads();
     int buf = 0;
     for (int k0 = 0; k0 < K; k0 += 16) {
         const bool more = k0 + 16 < K;
-        if (more) fetch(k0 + 16, va, vb);  // lands while this chunk's products issue
+        if (more) fetch(k0 + 16, va, vb);  // lands while this slice's products issue
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
-            float a[2], b[2];
+            float a[4], b[4];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) {
+            for (int x = 0; x < 4; ++x) {
                 a[x] = sA[buf][wm + 16 * x + row][kk + kq];
                 b[x] = sB[buf][wn + 16 * x + row][kk + kq];
             }
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+            for (int x = 0; x < 4; ++x)
 #pragma unroll
-                for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
+                for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
         }
         if (more) stash(buf ^ 1, va, vb);
         __syncthreads();
@@ -339,9 +349,9 @@ __global__ __launch_bounds__(kBlock) void k_dense_f32(int M, int N, int K, const
     }
     // lane holds rows 4 kq + e of column `row` of each 16 x 16 block
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
+        for (int y = 0; y < 4; ++y) {
             const int n = n0 + wn + 16 * y + row;
             if (n >= N) continue;
             const float bn = bias[n];
@@ -471,7 +481,8 @@ void run_classify(cnnsns_mesh_s& m, int64_t n, const double* xp, const cnnsns_cl
         k_cls_module1<<<mblocks, kBlock, 0, stream>>>(
             mc, xp2 + c0, m.G, static_cast<const double2*>(m.cls_pool), w.w[0], w.b[0], w.w[1], w.b[1], w.w[2], w.b[2],
             Z, kNZ, Hb, kH2);
-        const dim3 g256(blocks_for(mc, 64), kH1 / 64), g512(blocks_for(mc, 64), kH2 / 64), g81(blocks_for(mc, 64), 2);
+        const dim3 g256(blocks_for(mc, kDT), kH1 / kDT), g512(blocks_for(mc, kDT), kH2 / kDT),
+            g81(blocks_for(mc, kDT), (kNA + kDT - 1) / kDT);
         k_dense_f32<true><<<g256, kBlock, 0, stream>>>(mc, kH1, kH1, Hb, kH2, w.w[3], w.b[3], Z + kNF, kNZ);
         k_dense_f32<true><<<g512, kBlock, 0, stream>>>(mc, kH2, kNZ, Z, kNZ, w.w[4], w.b[4], Hb, kH2);
         k_dense_f32<false><<<g81, kBlock, 0, stream>>>(mc, kNA, kH2, Hb, kH2, w.w[5], w.b[5], L, kNA);
