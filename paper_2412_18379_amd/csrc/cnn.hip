@@ -11,13 +11,14 @@
 //           to 20) on the matrix cores into LDS on the 16 x 32 tile plus a
 //           one-pixel border, then conv2, stored from registers as the
 //           32-channel activation, pixel-major ([G][G][32]).
-//   conv34: 4 wavefronts, one per SIMD (each may hold 512 registers, which
-//           its two rows of conv3 blocks and the conv4 operands use):
-//           conv3 on a 16 x 32 region (the 14 x 30 output tile plus a
-//           one-pixel border); its results feed conv4 (N = 2) in registers:
-//           per region pixel, its 18 (output channel, tap) contributions on
-//           the matrix cores, kept in LDS, then a 9-term sum per output pixel;
-//           writes the 2-channel displacement.
+//   conv34: 8 wavefronts, two per SIMD, each owning one 16-channel block of
+//           conv3's output for two rows of 2 x 2 blocks: conv3 on a 16 x 32
+//           region (the 14 x 30 output tile plus a one-pixel border); its
+//           results feed conv4 (N = 2) in registers: per region pixel, the
+//           block's partial sums of its 18 (output channel, tap)
+//           contributions on the matrix cores, kept in LDS, then a 9-term sum
+//           of both blocks' partials per output pixel; writes the 2-channel
+//           displacement.
 // The two 32 -> 32 layers use the Winograd minimal filtering algorithm
 // F(2x2, 3x3) (Lavin and Gray, 2016): per 2 x 2 output block and channel
 // pair, 16 products in a transformed domain replace 36 direct ones, so the
@@ -35,8 +36,6 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;  // 4 wavefronts
-constexpr int kWaves = kThreads / 64;
 constexpr int RH = 16, RW = 32;          // MFMA region per block
 constexpr int IH = RH + 2, IW = RW + 2;  // its input tile (one-pixel border)
 constexpr int NIN = IH * IW;             // 612 input pixels
@@ -46,15 +45,12 @@ constexpr int PS = 36;                   // LDS floats per pixel (32 channels + 
 constexpr int OH34 = RH - 2, OW34 = RW - 2;  // conv34 output tile (region minus its border)
 constexpr int NU = 16 * 2 * 2 * 64 * 4;  // Winograd-domain 32->32 weights (floats)
 constexpr int VH = IH + 2, VW = IW + 2;  // velocity tile (two-pixel border) 20 x 36
-constexpr int VEL_PER_THREAD = (2 * VH * VW + kThreads - 1) / kThreads;
 constexpr int CHUNKS = NIN * C / 4;      // float4 chunks of an input tile
-constexpr int CHUNKS_PER_THREAD = (CHUNKS + kThreads - 1) / kThreads;
 constexpr int L1_MBLOCKS = (NIN + 15) / 16;
 constexpr int NIN_PAD = L1_MBLOCKS * 16;     // conv1's 39 M-blocks write whole blocks
 
 static_assert(NU == 16 * C * C, "transformed weights cover the whole layer");
 static_assert(NREG * PS <= NIN * PS, "output tile aliases the input tile");
-static_assert(kWaves * 4 == RH, "each wavefront takes two rows of 2 x 2 output blocks");
 constexpr int kThreads12 = 512;  // conv12: 8 wavefronts, two per SIMD, one row of 2 x 2 blocks each
 constexpr int kWaves12 = kThreads12 / 64;
 static_assert(kWaves12 * 2 == RH, "one row of 2 x 2 output blocks per wavefront");
@@ -152,104 +148,12 @@ __device__ __forceinline__ void wino_weights(const v4f* __restrict__ su, int grp
     }
 }
 
-// conv 32 -> 32 (no bias) over the block's 16 x 32 region, in two rounds: in
-// round r wave w computes block row ty = w + 4r (region rows 2 ty, 2 ty + 1).
-// s_in holds the 32-channel input on the 18 x 34 tile around the region, s_u
-// the transformed weights.  After each round, emit(r, y) receives the wave's
-// results: y[e][nb][r'], e = 2a + b, is region pixel (2 ty + a, 2 (l%16) + b),
-// output channel 16 nb + 4 (l/16) + r'.
-//
-// A round's contraction runs in 8 groups (2 channel halves x 4 groups of 4
-// transformed positions), 32 matrix instructions each, with 8 independent
-// accumulators between two updates of one.  Every LDS read is issued one group
-// ahead of its use: the next group's weights; during a round's first group its
-// second half's input patch, and during its fifth group the next round's first
-// patch (scheduling barriers keep the compiler from sinking these reads).  The
-// input transform of each prefetched patch is spread between the matrix
-// instructions of the group before its use, so the matrix core waits only for
-// the output transform between rounds.
-template <class Emit>
-__device__ __forceinline__ void conv32_wino(const float* __restrict__ s_in, const float* __restrict__ s_u, int wave,
-                                            int lane, Emit&& emit)
-{
-    const int tx = lane & 15, g = lane >> 4;
-    const v4f* su = reinterpret_cast<const v4f*>(s_u) + lane;
-    v4f d[4][4], dn[4][4], bc[4][2], bn[4][2];
-    wino_patch(s_in, wave, tx, g, 0, d);
-    wino_weights(su, 0, 0, bc);
-    wino_input_transform(d);
-#pragma unroll
-    for (int round = 0; round < 2; ++round) {
-        const int ty = wave + 4 * round;
-        v4f acc[16][2];
-#pragma unroll
-        for (int xn = 0; xn < 16; ++xn) {
-            acc[xn][0] = v4f{ 0.f, 0.f, 0.f, 0.f };
-            acc[xn][1] = v4f{ 0.f, 0.f, 0.f, 0.f };
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const bool final_half = round == 1 && h == 1;  // nothing to prefetch after it
-#pragma unroll
-            for (int grp = 0; grp < 4; ++grp) {
-                if (!(final_half && grp == 3)) wino_weights(su, (grp + 1) & 3, grp == 3 ? (h + 1) & 1 : h, bn);
-                if (grp == 0 && !final_half) wino_patch(s_in, h == 0 ? ty : ty + 4, tx, g, h == 0 ? 1 : 0, dn);
-                // keep these reads a whole group ahead of their use
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-#pragma unroll
-                    for (int x = 0; x < 4; ++x) {
-                        const int xn = 4 * grp + x;
-                        const float a = d[xn >> 2][xn & 3][j];
-                        acc[xn][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][0][j], a, acc[xn][0], 0, 0, 0);
-                        acc[xn][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][1][j], a, acc[xn][1], 0, 0, 0);
-                    }
-                    if (grp == 3 && !final_half) {
-                        // the prefetched patch's input transform, between the matrix instructions
-                        __builtin_amdgcn_sched_barrier(0);
-                        wino_input_transform_part(dn, j);
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                }
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    bc[x][0] = bn[x][0];
-                    bc[x][1] = bn[x][1];
-                }
-            }
-            if (!final_half) {
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) d[a][b] = dn[a][b];
-            }
-        }
-        // Y = A^T M A for the lane's block and 8 output channels (4 at a time)
-        v4f y[4][2];
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-            v4f m0[4], m1[4];
-#pragma unroll
-            for (int nu = 0; nu < 4; ++nu) {
-                m0[nu] = acc[nu][nb] + acc[4 + nu][nb] + acc[8 + nu][nb];
-                m1[nu] = acc[4 + nu][nb] - acc[8 + nu][nb] - acc[12 + nu][nb];
-            }
-            y[0][nb] = m0[0] + m0[1] + m0[2];
-            y[1][nb] = m0[1] - m0[2] - m0[3];
-            y[2][nb] = m1[0] + m1[1] + m1[2];
-            y[3][nb] = m1[1] - m1[2] - m1[3];
-        }
-        emit(round, y);
-    }
-}
-
 // conv 32 -> 32 (no bias) for the single block row ty of the region (region
-// rows 2 ty, 2 ty + 1), the form used when each of eight wavefronts owns one
-// row: the same contraction as conv32_wino, without its cross-round
-// prefetch (the second wavefront of the SIMD covers the waits), so that a
-// wavefront needs under 256 registers.  emit(y) receives the results as in
-// conv32_wino.
+// rows 2 ty, 2 ty + 1), each of eight wavefronts owning one row, with no
+// prefetch across rows (the second wavefront of the SIMD covers the waits), so
+// that a wavefront needs under 256 registers.  emit(y) receives y[e][nb][r'],
+// e = 2a + b: region pixel (2 ty + a, 2 (l%16) + b), output channel
+// 16 nb + 4 (l/16) + r'.
 template <class Emit>
 __device__ __forceinline__ void conv32_wino_row(const float* __restrict__ s_in, const float* __restrict__ s_u,
                                                 int ty, int lane, Emit&& emit)
@@ -296,6 +200,51 @@ __device__ __forceinline__ void conv32_wino_row(const float* __restrict__ s_in, 
         y[2][nb] = m1[0] + m1[1] + m1[2];
         y[3][nb] = m1[1] - m1[2] - m1[3];
     }
+    emit(y);
+}
+
+// conv 32 -> 32 (no bias) for block row ty of the region and the 16 output channels of block nb:
+// conv32_wino_row's contraction for one output-channel block, so that a wavefront holds 16
+// accumulators and two wavefronts per SIMD fit their registers.  emit(y) receives y[e], e = 2a + b:
+// region pixel (2 ty + a, 2 (l%16) + b), output channels 16 nb + 4 (l/16) + r.
+template <class Emit>
+__device__ __forceinline__ void conv32_wino_nb(const float* __restrict__ s_in, const float* __restrict__ s_u, int ty,
+                                               int nb, int lane, Emit&& emit)
+{
+    const int tx = lane & 15, g = lane >> 4;
+    const v4f* su = reinterpret_cast<const v4f*>(s_u) + lane;
+    v4f acc[16];
+#pragma unroll
+    for (int xn = 0; xn < 16; ++xn) acc[xn] = v4f{ 0.f, 0.f, 0.f, 0.f };
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        v4f d[4][4];
+        wino_patch(s_in, ty, tx, g, h, d);
+        wino_input_transform(d);
+#pragma unroll
+        for (int grp = 0; grp < 4; ++grp) {
+            v4f bc[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) bc[x] = su[(((4 * grp + x) * 2 + nb) * 2 + h) * 64];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const int xn = 4 * grp + x;
+                    acc[xn] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][j], d[xn >> 2][xn & 3][j], acc[xn], 0, 0, 0);
+                }
+        }
+    }
+    v4f m0[4], m1[4], y[4];
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        m0[nu] = acc[nu] + acc[4 + nu] + acc[8 + nu];
+        m1[nu] = acc[4 + nu] - acc[8 + nu] - acc[12 + nu];
+    }
+    y[0] = m0[0] + m0[1] + m0[2];
+    y[1] = m0[1] - m0[2] - m0[3];
+    y[2] = m1[0] + m1[1] + m1[2];
+    y[3] = m1[1] - m1[2] - m1[3];
     emit(y);
 }
 
@@ -495,8 +444,19 @@ __global__ __launch_bounds__(kThreads12) __attribute__((amdgpu_waves_per_eu(2, 2
     }
 }
 
-// conv3 + ReLU on the tile plus a one-pixel border, then conv4 -> disp [2][G][G].
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_conv34_f32(
+// conv3 + ReLU then conv4 on a 14 x 30 output tile: eight wavefronts, two per SIMD.  Wavefront w takes
+// output-channel block nb = w / 4 of conv3 for block rows w % 4 and w % 4 + 4 (two rounds), so each
+// holds 16 accumulators; conv4's contraction is split the same way (each block's 16 channels give a
+// partial sum) and the two partials are added in the tap sums.
+constexpr int kThreads34 = 512;
+constexpr int CHUNKS_PER_THREAD34 = (CHUNKS + kThreads34 - 1) / kThreads34;
+constexpr int ZS34 = 18;                  // floats per pixel of a partial: the 18 (output, tap) columns
+constexpr int ZAREA = NREG / 2 * ZS34;    // one round's 256 pixels, one partial
+constexpr int ZOFF1 = 8 * IW * PS;        // round 1's partials: past the input rows 0 .. 7 that hold round 0's
+static_assert(2 * ZAREA <= ZOFF1, "round 0's partials fit in the input rows that round 1 does not read");
+static_assert(ZOFF1 + 2 * ZAREA <= NIN * PS, "round 1's partials fit after them");
+
+__global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_conv34_f32(
     int32_t G, int tiles_x, int ntiles, const float* __restrict__ act2, const float* __restrict__ u3,
     const float* __restrict__ b3, const float* __restrict__ w4, const float* __restrict__ b4,
     float* __restrict__ disp)
@@ -505,7 +465,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     __shared__ __attribute__((aligned(16))) float s_u[NU];
     __shared__ __attribute__((aligned(16))) float s_w17[2][C];  // w4[1][c][7], w4[1][c][8]
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, q = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nb = wave >> 2, wr = wave & 3;
     const int64_t GG = (int64_t)G * G;
 
     TileIter it(ntiles);
@@ -513,53 +475,41 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 
     load_u(u3, s_u);
     // conv3 biases of the lane's output channels 16 nb + 4q + r
-    v4f bias3[2];
+    v4f bias3;
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+    for (int r = 0; r < 4; ++r) bias3[r] = b3[16 * nb + 4 * q + r];
+    // conv4 A operands (rows n = i = 9 o + tap, the first 16 of the 18 columns): in k-step s, lane
+    // (i, q) supplies input channel 16 nb + 4q + s, the channels the Winograd result places in it
+    float aw4[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) bias3[nb][r] = b3[16 * nb + 4 * q + r];
-    // conv4 A operands (rows n = i = 9 o + tap, the first 16 of the 18 columns): in k-step s,
-    // lane (i, q) supplies input channel 4q + s (s < 4) or 16 + 4q + s - 4, the channels that
-    // the Winograd result places in this lane
-    float aw4[8];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const int n = i, c = s < 4 ? 4 * q + s : 16 + 4 * q + s - 4;
-        aw4[s] = w4[((n / 9) * C + c) * 9 + n % 9];
+    for (int st = 0; st < 4; ++st) {
+        const int n = i, c = 16 * nb + 4 * q + st;
+        aw4[st] = w4[((n / 9) * C + c) * 9 + n % 9];
     }
-    // the last two columns (n = 16, 17: output channel 1, taps 7 and 8) are vector dot
-    // products, not a second matrix instruction of which they would be 2 of 16 columns
-    for (int k = tid; k < 2 * C; k += kThreads) s_w17[k / C][k % C] = w4[(C + k % C) * 9 + 7 + k / C];
+    // the last two columns (n = 16, 17: output channel 1, taps 7 and 8) are vector dot products
+    for (int k = tid; k < 2 * C; k += kThreads34) s_w17[k / C][k % C] = w4[(C + k % C) * 9 + 7 + k / C];
     const float bias4[2] = { b4[0], b4[1] };
 
     // next tile's input, as float4 chunks (8 per pixel) of the 18 x 34 tile
-    v4f pa[CHUNKS_PER_THREAD];
+    v4f pa[CHUNKS_PER_THREAD34];
     auto fetch_act = [&](int t) {
         const int y0 = (t / tiles_x) * OH34 - 1, x0 = (t % tiles_x) * OW34 - 1;  // conv3 region origin
-        // chunk e = tid + 256 k is pixel (tid >> 3) + 32 k, channels 4 (tid & 7) .. +3; the
-        // pixel's (row, column) in the 18 x 34 tile advance by 32 columns per k.  The empty
-        // asm keeps the compiler from precomputing all 20 positions outside the tile loop.
-        int row = 0, col = tid >> 3;
-        asm volatile("" : "+v"(col));
-        const int part = tid & 7;
 #pragma unroll
-        for (int k = 0; k < CHUNKS_PER_THREAD; ++k) {
-            const int gy = y0 - 1 + row, gx = x0 - 1 + col;
+        for (int k = 0; k < CHUNKS_PER_THREAD34; ++k) {
+            int e = tid + k * kThreads34;
+            asm volatile("" : "+v"(e));  // positions recomputed per tile, not held in registers
+            const int px = e >> 3, part = e & 7;
+            const int gy = y0 - 1 + px / IW, gx = x0 - 1 + px % IW;
             v4f v = v4f{ 0.f, 0.f, 0.f, 0.f };
-            if (tid + k * kThreads < CHUNKS && (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G)
+            if (e < CHUNKS && (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G)
                 v = *reinterpret_cast<const v4f*>(act2 + ((int64_t)gy * G + gx) * C + part * 4);
             pa[k] = v;
-            col += kThreads / 8;
-            if (col >= IW) {
-                col -= IW;
-                ++row;
-            }
         }
     };
     auto stash_act = [&]() {
 #pragma unroll
-        for (int k = 0; k < CHUNKS_PER_THREAD; ++k) {
-            const int e = tid + k * kThreads;
+        for (int k = 0; k < CHUNKS_PER_THREAD34; ++k) {
+            const int e = tid + k * kThreads34;
             if (e < CHUNKS) *reinterpret_cast<v4f*>(s_in + (e >> 3) * PS + (e & 7) * 4) = pa[k];
         }
     };
@@ -570,87 +520,73 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     for (; it.t < it.end; it.t += it.step) {
         const int ty0 = (it.t / tiles_x) * OH34, tx0 = (it.t % tiles_x) * OW34;  // output tile origin
         const int y0 = ty0 - 1, x0 = tx0 - 1;                                      // conv3 region origin
-
         const int next = it.t + it.step;
 
-        // conv3 in two rounds of block rows.  Each round's results go straight into conv4: for
-        // every pixel p of the round, Z[p][n] = sum_c act3[p][c] w4[n / 9][c][n % 9] (n < 18) as a
-        // contraction on the matrix cores (A = conv4 weights, B = the lane's act3 channels), stored
-        // at stride ZS over tile rows the remaining reads no longer need: the first round's
-        // (pixels 0 .. 255) below tile row 8, which the second round does not read, and the
-        // second's after it, each after every wave has finished reading.
-        constexpr int ZS = 20;
-        static_assert(NREG / 2 * ZS <= 8 * IW * PS && NREG * ZS <= NIN * PS, "Z placement");
-        conv32_wino(s_in, s_u, wave, lane, [&](int round, const v4f (&y)[4][2]) {
-            __syncthreads();
-            // the lane's four pixels (row, 2 i + (e & 1)) at once, so that their four
-            // accumulation chains, dot products and lane exchanges overlap
-            v4f act[4][2];
+#pragma unroll 1
+        for (int round = 0; round < 2; ++round) {
+            // each round's results go straight into conv4: for every pixel p of the round,
+            // Z_nb[p][n] = sum over block nb's channels c of act3[p][c] w4[n / 9][c][n % 9] (n < 18), stored
+            // over input rows that the remaining reads no longer need, after every wave has read them
+            conv32_wino_nb(s_in, s_u, wr + 4 * round, nb, lane, [&](const v4f (&y)[4]) {
+                __syncthreads();
+                v4f act[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gy = y0 + 2 * (wave + 4 * round) + (e >> 1), gx = x0 + 2 * i + (e & 1);
-                const bool in = (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G;  // conv4's zero padding
+                for (int e = 0; e < 4; ++e) {
+                    const int gy = y0 + 2 * (wr + 4 * round) + (e >> 1), gx = x0 + 2 * i + (e & 1);
+                    const bool in = (unsigned)gy < (unsigned)G && (unsigned)gx < (unsigned)G;  // conv4's zero padding
+                    act[e] = y[e] + bias3;
 #pragma unroll
-                for (int nb = 0; nb < 2; ++nb) {
-                    act[e][nb] = y[e][nb] + bias3[nb];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) act[e][nb][r] = in ? fmaxf(act[e][nb][r], 0.f) : 0.f;
+                    for (int r = 0; r < 4; ++r) act[e][r] = in ? fmaxf(act[e][r], 0.f) : 0.f;
                 }
-            }
-            v4f z0[4];
+                v4f z0[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) z0[e] = v4f{ 0.f, 0.f, 0.f, 0.f };
+                for (int e = 0; e < 4; ++e) z0[e] = v4f{ 0.f, 0.f, 0.f, 0.f };
 #pragma unroll
-            for (int s = 0; s < 8; ++s)
+                for (int st = 0; st < 4; ++st)
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    z0[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw4[s], s < 4 ? act[e][0][s] : act[e][1][s - 4],
-                                                                 z0[e], 0, 0, 0);
-            // columns 16, 17: the lane's 8 channels, then the sum over the four lanes (i, 0..3)
-            // that hold the pixel's other channels
-            float z16[4] = { 0.f, 0.f, 0.f, 0.f }, z17[4] = { 0.f, 0.f, 0.f, 0.f };
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
+                    for (int e = 0; e < 4; ++e)
+                        z0[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw4[st], act[e][st], z0[e], 0, 0, 0);
+                float z16[4] = { 0.f, 0.f, 0.f, 0.f }, z17[4] = { 0.f, 0.f, 0.f, 0.f };
                 const v4f u = *reinterpret_cast<const v4f*>(&s_w17[0][16 * nb + 4 * q]);
                 const v4f v = *reinterpret_cast<const v4f*>(&s_w17[1][16 * nb + 4 * q]);
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        z16[e] += u[r] * act[e][nb][r];
-                        z17[e] += v[r] * act[e][nb][r];
+                        z16[e] += u[r] * act[e][r];
+                        z17[e] += v[r] * act[e][r];
                     }
-            }
 #pragma unroll
-            for (int m = 16; m <= 32; m *= 2)
+                for (int m = 16; m <= 32; m *= 2)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        z16[e] += __shfl_xor(z16[e], m);
+                        z17[e] += __shfl_xor(z17[e], m);
+                    }
+                // lane (i, q) holds the partial Z of its pixels for n = 4q + r, and 16, 17
+                float* zbase = s_in + (round ? ZOFF1 : 0) + nb * ZAREA;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    z16[e] += __shfl_xor(z16[e], m);
-                    z17[e] += __shfl_xor(z17[e], m);
+                    const int row = 2 * wr + (e >> 1), col = 2 * i + (e & 1);
+                    float* zp = zbase + (row * RW + col) * ZS34;
+                    *reinterpret_cast<float2*>(zp + 4 * q) = float2{ z0[e][0], z0[e][1] };
+                    *reinterpret_cast<float2*>(zp + 4 * q + 2) = float2{ z0[e][2], z0[e][3] };
+                    if (q == 0) *reinterpret_cast<float2*>(zp + 16) = float2{ z16[e], z17[e] };
                 }
-            // lane (i, q) holds Z of its pixels for n = 4q + r, and 16, 17
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int row = 2 * (wave + 4 * round) + (e >> 1), col = 2 * i + (e & 1);
-                float* zp = s_in + (row * RW + col) * ZS;
-                *reinterpret_cast<v4f*>(zp + 4 * q) = z0[e];
-                if (q == 0) {
-                    zp[16] = z16[e];
-                    zp[17] = z17[e];
-                }
-            }
-        });
+            });
+        }
         if (next < it.end) fetch_act(next);  // lands while the taps are summed
         __syncthreads();
-        // each output pixel sums its 9 taps: disp[o] = b4[o] + sum_t Z[pixel + tap t][9 o + t]
-        for (int e = tid; e < OH34 * OW34; e += kThreads) {
+        // each output pixel sums its 9 taps of both partials: disp[o] = b4[o] + sum_t Z[pixel + tap t][9 o + t]
+        for (int e = tid; e < OH34 * OW34; e += kThreads34) {
             const int oy = e / OW34, ox = e - oy * OW34;
             float d0 = bias4[0], d1 = bias4[1];
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
-                const float* zp = s_in + ((oy + t / 3) * RW + ox + t % 3) * ZS;
-                d0 += zp[t];
-                d1 += zp[9 + t];
+                const int pr = oy + t / 3, pc = ox + t % 3;
+                const float* zp = s_in + (pr < 8 ? 0 : ZOFF1) + ((pr & 7) * RW + pc) * ZS34;
+                d0 += zp[t] + zp[ZAREA + t];
+                d1 += zp[9 + t] + zp[ZAREA + 9 + t];
             }
             const int gy = ty0 + oy, gx = tx0 + ox;
             if (gy < G && gx < G) {
@@ -715,8 +651,8 @@ void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision
     const int tx12 = (int)cdiv(G, RW), n12 = tx12 * (int)cdiv(G, RH);
     const int tx34 = (int)cdiv(G, OW34), n34 = tx34 * (int)cdiv(G, OH34);
     k_conv12_f32<<<persistent_grid(n12), kThreads12, 0, stream>>>(G, tx12, n12, vel, w.w[0], w.b[0], u2, w.b[1], act2);
-    k_conv34_f32<<<persistent_grid(n34), kThreads, 0, stream>>>(G, tx34, n34, act2, u3, w.b[2], w.w[3], w.b[3],
-                                                               disp);
+    k_conv34_f32<<<persistent_grid(n34), kThreads34, 0, stream>>>(G, tx34, n34, act2, u3, w.b[2], w.w[3], w.b[3],
+                                                                 disp);
     hip_check(hipGetLastError(), "predict launch");
 }
 
