@@ -281,6 +281,10 @@ __global__ __launch_bounds__(kThreads12) __attribute__((amdgpu_waves_per_eu(2, 2
     __shared__ __attribute__((aligned(16))) float s_in[NIN_PAD * PS];
     __shared__ __attribute__((aligned(16))) float s_u[NU];
     __shared__ float s_vel[2 * VH * VW];
+    // conv1's weights (OIHW, 18 per output channel) and the biases of conv1 and conv2: read per
+    // tile from LDS rather than from global memory, so their latency is an LDS read's
+    __shared__ float s_w1[C * 18];
+    __shared__ __attribute__((aligned(16))) float s_b12[2][C];
 
     const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -290,6 +294,8 @@ __global__ __launch_bounds__(kThreads12) __attribute__((amdgpu_waves_per_eu(2, 2
     if (it.t >= it.end) return;
 
     load_u(u2, s_u);
+    for (int k = tid; k < C * 18; k += kThreads12) s_w1[k] = w1[k];
+    if (tid < 2 * C) s_b12[tid / C][tid % C] = (tid < C ? b1 : b2)[tid % C];
     // conv1's operands and conv2's biases are (re)loaded on every tile, from an index the
     // compiler cannot see through, so that none of them occupies registers during conv2
     auto conv1_setup = [&](float (&bw1)[5][2], v4f (&bias1)[2], int (&l1_off)[5], bool (&l1_on)[5]) {
@@ -304,12 +310,10 @@ __global__ __launch_bounds__(kThreads12) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
                 const int k = 4 * s + qq, o = nb * 16 + i;
-                bw1[s][nb] = k < 18 ? w1[(o * 2 + k / 9) * 9 + k % 9] : 0.f;
+                bw1[s][nb] = k < 18 ? s_w1[o * 18 + k] : 0.f;
             }
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) bias1[nb][r] = b1[16 * nb + 4 * qq + r];
+        for (int nb = 0; nb < 2; ++nb) bias1[nb] = *reinterpret_cast<const v4f*>(&s_b12[0][16 * nb + 4 * qq]);
         // B operands: k-step s of lane (i, q) reads s_vel at the pixel's base plus a per-lane
         // constant offset (channel k / 9, tap k % 9); slots k >= 18 read the pixel itself and
         // are zeroed by a select
@@ -422,8 +426,7 @@ __global__ __launch_bounds__(kThreads12) __attribute__((amdgpu_waves_per_eu(2, 2
             v4f bias2[2];  // of the lane's output channels 16 nb + 4q + r
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) bias2[nb][r] = b2[16 * nb + 4 * qq + r];
+                bias2[nb] = *reinterpret_cast<const v4f*>(&s_b12[1][16 * nb + 4 * qq]);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int gy = y0 + 2 * wave + (e >> 1), gx = x0 + 2 * i + (e & 1);
@@ -524,6 +527,9 @@ __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2
 
 #pragma unroll 1
         for (int round = 0; round < 2; ++round) {
+            // the next tile's input is requested at the start of the second round, so that the
+            // address work and the issue of its loads share the round with the matrix instructions
+            if (round == 1 && next < it.end) fetch_act(next);
             // each round's results go straight into conv4: for every pixel p of the round,
             // Z_nb[p][n] = sum over block nb's channels c of act3[p][c] w4[n / 9][c][n % 9] (n < 18), stored
             // over input rows that the remaining reads no longer need, after every wave has read them
@@ -575,7 +581,6 @@ __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2
                 }
             });
         }
-        if (next < it.end) fetch_act(next);  // lands while the taps are summed
         __syncthreads();
         // each output pixel sums its 9 taps of both partials: disp[o] = b4[o] + sum_t Z[pixel + tap t][9 o + t]
         for (int e = tid; e < OH34 * OW34; e += kThreads34) {
