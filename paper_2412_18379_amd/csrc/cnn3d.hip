@@ -203,7 +203,11 @@ __global__ void k3c_wprep4_bf16(const float* __restrict__ w, bf16x8* __restrict_
 // blocks: two for 32 -> 32, one for 32 -> 3 with the outputs padded to 16).
 constexpr int ZY = 8, ZX = 32, ZP = 32;           // cells per block: rows, columns, planes
 constexpr int ZSY = ZY + 2, ZSX = ZX + 2;         // slab with its border
-constexpr int ZCS = 40;                           // bf16 per slab cell (32 channels + 8 pad: 80 bytes)
+// bf16 per slab cell: 32 channels + 16 pad, 96 bytes.  The LDS serves a 16-byte read in groups of
+// 16 lanes over 64 four-byte banks, a group joining lanes 0-7 with 56-63 (8-15 with 48-55, ...): here
+// eight consecutive cells at one 16-byte channel chunk and eight others at the mirrored chunk.  With
+// a 96-byte pitch those sixteen reads fall in distinct bank groups; with 80 bytes half of them collide.
+constexpr int ZCS = 48;
 constexpr int ZSLAB = ZSY * ZSX * ZCS;            // bf16 per slab
 constexpr int kZThreads = 512;
 constexpr int ZCHUNKS = ZSY * ZSX * 4;            // 16-byte pieces of a slab
