@@ -43,6 +43,12 @@ constexpr int H2 = OH + 4, W2 = OW + 4;    // conv2 region (18 x 34)
 constexpr int H3 = OH + 2, W3 = OW + 2;    // conv3 region (16 x 32)
 constexpr int HV = OH + 8, WV = OW + 8;    // velocity tile (22 x 38)
 constexpr int PXS = 40;                    // bf16 per pixel in LDS (32 channels + 8 pad: 80 bytes)
+// bf16 per pixel of the conv2 output (conv3's input): 96 bytes.  The LDS serves a 16-byte read in
+// groups of 16 lanes over 64 four-byte banks, a group joining lanes 0-7 with 56-63 (8-15 with 48-55,
+// ...): eight consecutive pixels at one channel chunk and eight others at the mirrored chunk.  At a
+// 96-byte pitch those reads fall in distinct bank groups; at 80 bytes half of them collide.  (The
+// conv1 output keeps 80 bytes: the LDS holds only one of the two at 96.)
+constexpr int PXS2 = 48;
 constexpr int VEL_PER_THREAD = (HV * WV + kThreads - 1) / kThreads;  // velocity pixels per thread
 // M-blocks of 16 pixels per wavefront, and how many of them are in flight at once
 constexpr int NMB1 = H1 * W1 / 16, BPW1 = (NMB1 + kWaves - 1) / kWaves, MB1 = BPW1;
@@ -124,7 +130,7 @@ __device__ __forceinline__ uint32_t relu_pair(float v0, float v1)
 // Writes the 4 pixels (p0 .. p0 + 3 of an HO x WO region with grid origin
 // (oy0, ox0)) that lane (i, q) holds after a layer's M-block: ReLU pairs, and
 // zero for pixels outside the grid (the next layer's zero padding).
-template <int WO, bool EDGE>
+template <int WO, int OPXS, bool EDGE>
 __device__ __forceinline__ void store_block(bf16* __restrict__ out, int p0, int i, const v4f& d0, const v4f& d1,
                                             int oy0, int ox0, int G)
 {
@@ -135,7 +141,7 @@ __device__ __forceinline__ void store_block(bf16* __restrict__ out, int p0, int 
             const int p = p0 + r, gy = oy0 + p / WO, gx = ox0 + p % WO;
             if (!inside(gy, gx, G)) v = 0;
         }
-        *reinterpret_cast<uint32_t*>(out + (p0 + r) * PXS + 2 * i) = v;
+        *reinterpret_cast<uint32_t*>(out + (p0 + r) * OPXS + 2 * i) = v;
     }
 }
 
@@ -145,7 +151,7 @@ __device__ __forceinline__ void store_block(bf16* __restrict__ out, int p0, int 
 // them MB at a time; the A and B operands of the next two taps are read while
 // the matrix instructions of the current one issue.  Blocks past the region's last one are
 // computed on clamped pixels and not stored.
-template <int HO, int WO, int BPW, int MB, bool EDGE>
+template <int HO, int WO, int IPXS, int OPXS, int BPW, int MB, bool EDGE>
 __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* __restrict__ out,
                                             const bf16x8* __restrict__ sw, float blo, float bhi, int oy0, int ox0,
                                             int G, int wave, int lane)
@@ -164,14 +170,14 @@ __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* _
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
             const int p = min((g + m) * 16 + i, N - 1);
-            base[m] = ((p / WO) * WI + p % WO) * PXS + 8 * q;
+            base[m] = ((p / WO) * WI + p % WO) * IPXS + 8 * q;
             acc[m][0] = v4f{ blo, blo, blo, blo };
             acc[m][1] = v4f{ bhi, bhi, bhi, bhi };
         }
         // operands (and weights) of taps t+1 and t+2 are in flight while tap t's instructions issue
         constexpr int PF = 2;
         static_assert(PF * (MB + 2) <= 15, "outstanding LDS reads fit the wait counter");
-        auto tap_off = [](int t) { return ((t / 3) * WI + t % 3) * PXS; };
+        auto tap_off = [](int t) { return ((t / 3) * WI + t % 3) * IPXS; };
         bf16x8 a[PF + 1][MB], w[PF + 1][2];
         auto fetch = [&](int t, int slot) {
 #pragma unroll
@@ -198,7 +204,7 @@ __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* _
 #pragma unroll
         for (int m = 0; m < MB; ++m)
             if (NMB == BPW * kWaves || g + m < NMB)
-                store_block<WO, EDGE>(out, (g + m) * 16 + 4 * q, i, acc[m][0], acc[m][1], oy0, ox0, G);
+                store_block<WO, OPXS, EDGE>(out, (g + m) * 16 + 4 * q, i, acc[m][0], acc[m][1], oy0, ox0, G);
     }
 }
 
@@ -210,7 +216,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     __shared__ __attribute__((aligned(16))) bf16 bufA[H1 * W1 * PXS];  // conv1 out, then conv3 out
     static_assert(H1 * W1 >= NMB3 * 16, "conv3 output fits in bufA");
     // conv2 out, padded to the last stored M-block
-    __shared__ __attribute__((aligned(16))) bf16 bufB[NMB2 * 16 * PXS];
+    __shared__ __attribute__((aligned(16))) bf16 bufB[NMB2 * 16 * PXS2];
     __shared__ uint32_t s_vel[HV * WV];  // (u, v) of each velocity pixel as a packed BF16 pair
     __shared__ bf16x8 s_w1[P1];
     __shared__ bf16x8 s_w4[P4];
@@ -298,9 +304,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             for (int m = 0; m < MB1; ++m) {
                 if (NMB1 == BPW1 * kWaves || g + m < NMB1) {
                     if (edge)
-                        store_block<W1, true>(bufA, (g + m) * 16 + 4 * q, i, d[m][0], d[m][1], ty0 - 3, tx0 - 3, G);
+                        store_block<W1, PXS, true>(bufA, (g + m) * 16 + 4 * q, i, d[m][0], d[m][1], ty0 - 3, tx0 - 3,
+                                                   G);
                     else
-                        store_block<W1, false>(bufA, (g + m) * 16 + 4 * q, i, d[m][0], d[m][1], 0, 0, G);
+                        store_block<W1, PXS, false>(bufA, (g + m) * 16 + 4 * q, i, d[m][0], d[m][1], 0, 0, G);
                 }
             }
         }
@@ -322,15 +329,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         if (next < it.end) fetch_vel(next);  // lands while conv2-conv4 run
 
         if (edge)
-            conv32_bf16<H2, W2, BPW2, MB2, true>(bufA, bufB, s_w23, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave, lane);
+            conv32_bf16<H2, W2, PXS, PXS2, BPW2, MB2, true>(bufA, bufB, s_w23, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave,
+                                                            lane);
         else
-            conv32_bf16<H2, W2, BPW2, MB2, false>(bufA, bufB, s_w23, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave, lane);
+            conv32_bf16<H2, W2, PXS, PXS2, BPW2, MB2, false>(bufA, bufB, s_w23, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave,
+                                                             lane);
         __syncthreads();
         if (next < it.end) stash_vel();
         if (edge)
-            conv32_bf16<H3, W3, BPW3, MB3, true>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G, wave, lane);
+            conv32_bf16<H3, W3, PXS2, PXS, BPW3, MB3, true>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G,
+                                                            wave, lane);
         else
-            conv32_bf16<H3, W3, BPW3, MB3, false>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G, wave, lane);
+            conv32_bf16<H3, W3, PXS2, PXS, BPW3, MB3, false>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G,
+                                                             wave, lane);
         __syncthreads();
 
         // conv4 as a contraction: for every pixel p of the 16 x 32 conv3 region,
