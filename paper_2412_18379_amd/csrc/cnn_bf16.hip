@@ -42,13 +42,14 @@ constexpr int H1 = OH + 6, W1 = OW + 6;    // conv1 region (20 x 36)
 constexpr int H2 = OH + 4, W2 = OW + 4;    // conv2 region (18 x 34)
 constexpr int H3 = OH + 2, W3 = OW + 2;    // conv3 region (16 x 32)
 constexpr int HV = OH + 8, WV = OW + 8;    // velocity tile (22 x 38)
-constexpr int PXS = 40;                    // bf16 per pixel in LDS (32 channels + 8 pad: 80 bytes)
-// bf16 per pixel of the conv2 output (conv3's input): 96 bytes.  The LDS serves a 16-byte read in
-// groups of 16 lanes over 64 four-byte banks, a group joining lanes 0-7 with 56-63 (8-15 with 48-55,
-// ...): eight consecutive pixels at one channel chunk and eight others at the mirrored chunk.  At a
-// 96-byte pitch those reads fall in distinct bank groups; at 80 bytes half of them collide.  (The
-// conv1 output keeps 80 bytes: the LDS holds only one of the two at 96.)
-constexpr int PXS2 = 48;
+// bf16 per pixel of the conv1 and conv3 outputs (96 bytes) and of the conv2 output (80 bytes).  The
+// LDS serves a 16-byte read in groups of 16 lanes over 64 four-byte banks, a group joining lanes 0-7
+// with 56-63 (8-15 with 48-55, ...): for the operand reads, eight consecutive pixels at one channel
+// chunk and eight others at the mirrored chunk.  At a 96-byte pitch those reads fall in distinct bank
+// groups; at 80 bytes half of them collide.  The LDS holds only one of the two layer buffers at 96:
+// it goes to conv2's input, the layer with the more operand reads per tile.
+constexpr int PXS = 48;
+constexpr int PXS2 = 40;
 constexpr int VEL_PER_THREAD = (HV * WV + kThreads - 1) / kThreads;  // velocity pixels per thread
 // M-blocks of 16 pixels per wavefront, and how many of them are in flight at once
 constexpr int NMB1 = H1 * W1 / 16, BPW1 = (NMB1 + kWaves - 1) / kWaves, MB1 = BPW1;
