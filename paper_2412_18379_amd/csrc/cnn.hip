@@ -248,6 +248,18 @@ __device__ __forceinline__ void conv32_wino_nb(const float* __restrict__ s_in, c
     emit(y);
 }
 
+// x summed over the four lanes l % 16 + 16 k of its 16-lane column: x + (x of lane l ^ 16), then the
+// same with lane l ^ 32, through the lane-swap instructions (no trip through the LDS).  With both
+// operands x, the swap returns x of lane l in one half and of its partner in the other, so their sum
+// is x_l + x_(l ^ 16); the two addends may come in either order, which leaves the sum unchanged.
+__device__ __forceinline__ float sum_lane_column(float x)
+{
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
 // Block loads of the transformed 32->32 weights into LDS.
 __device__ __forceinline__ void load_u(const float* __restrict__ u, float* __restrict__ s_u)
 {
@@ -563,12 +575,10 @@ __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2
                         z17[e] += v[r] * act[e][r];
                     }
 #pragma unroll
-                for (int m = 16; m <= 32; m *= 2)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        z16[e] += __shfl_xor(z16[e], m);
-                        z17[e] += __shfl_xor(z17[e], m);
-                    }
+                for (int e = 0; e < 4; ++e) {
+                    z16[e] = sum_lane_column(z16[e]);
+                    z17[e] = sum_lane_column(z17[e]);
+                }
                 // lane (i, q) holds the partial Z of its pixels for n = 4q + r, and 16, 17
                 float* zbase = s_in + (round ? ZOFF1 : 0) + nb * ZAREA;
 #pragma unroll
