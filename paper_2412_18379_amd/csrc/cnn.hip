@@ -13,7 +13,9 @@
 //           32-channel activation, pixel-major ([G][G][32]).
 //   conv34: 8 wavefronts, two per SIMD, each owning one 16-channel block of
 //           conv3's output for two rows of 2 x 2 blocks: conv3 on a 16 x 32
-//           region (the 14 x 30 output tile plus a one-pixel border); its
+//           region (a 14 x 30 output tile plus a one-pixel border; tiles
+//           walk down column strips, and a tile that continues a strip
+//           reuses the two region rows above it and writes 16 x 30); its
 //           results feed conv4 (N = 2) in registers: per region pixel, the
 //           block's partial sums of its 18 (output channel, tap)
 //           contributions on the matrix cores, kept in LDS, then a 9-term sum
@@ -470,23 +472,61 @@ constexpr int ZAREA = NREG / 2 * ZS34;    // one round's 256 pixels, one partial
 constexpr int ZOFF1 = 8 * IW * PS;        // round 1's partials: past the input rows 0 .. 7 that hold round 0's
 static_assert(2 * ZAREA <= ZOFF1, "round 0's partials fit in the input rows that round 1 does not read");
 static_assert(ZOFF1 + 2 * ZAREA <= NIN * PS, "round 1's partials fit after them");
+constexpr int OHB = RH;                   // output rows of a tile that continues a strip
+
+// conv34 walks down column strips (OW34 outputs wide) in segments of seg_rows output rows: the first
+// tile of a segment computes conv3 on its 16 x 32 region and writes OH34 = 14 output rows; every
+// further tile computes conv3 on the 16 rows below the previous region only and writes OHB = 16 rows,
+// taking the conv4 products of the two region rows above it (the previous region's last two, kept in
+// LDS as the sum of both channel blocks' partials) instead of recomputing them.  Segments are
+// numbered row-major over (segment row, strip) and split into 8 contiguous ranges, one per XCD, as
+// the tiles of conv12.
+struct StripIter {
+    int s, end, step, j, tiles_x, seg_rows, G;
+    __device__ StripIter(int nseg, int tiles_x_, int seg_rows_, int G_)
+        : j(0), tiles_x(tiles_x_), seg_rows(seg_rows_), G(G_)
+    {
+        const int nx = 8;
+        const int xcd = blockIdx.x % nx, slot = blockIdx.x / nx;
+        s = (int)((int64_t)nseg * xcd / nx) + slot;
+        end = (int)((int64_t)nseg * (xcd + 1) / nx);
+        step = gridDim.x / nx;
+    }
+    __device__ bool valid() const { return s < end; }
+    __device__ bool continues() const { return j > 0; }
+    __device__ int y() const { return (s / tiles_x) * seg_rows + (j == 0 ? 0 : OH34 + OHB * (j - 1)); }
+    __device__ int x() const { return (s % tiles_x) * OW34; }
+    __device__ void advance()
+    {
+        const int ylim = min((s / tiles_x + 1) * seg_rows, G);
+        if ((s / tiles_x) * seg_rows + OH34 + OHB * j < ylim) {
+            ++j;
+        } else {
+            s += step;
+            j = 0;
+        }
+    }
+};
 
 __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_conv34_f32(
-    int32_t G, int tiles_x, int ntiles, const float* __restrict__ act2, const float* __restrict__ u3,
+    int32_t G, int tiles_x, int nseg, int seg_rows, const float* __restrict__ act2, const float* __restrict__ u3,
     const float* __restrict__ b3, const float* __restrict__ w4, const float* __restrict__ b4,
     float* __restrict__ disp)
 {
     __shared__ __attribute__((aligned(16))) float s_in[NIN * PS];
     __shared__ __attribute__((aligned(16))) float s_u[NU];
     __shared__ __attribute__((aligned(16))) float s_w17[2][C];  // w4[1][c][7], w4[1][c][8]
+    // conv4 products (both channel blocks summed) of the last two region rows of the previous tile,
+    // double-buffered: a tile reads one and writes the other
+    __shared__ float s_zs[2][2][RW][ZS34];
 
     const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nb = wave >> 2, wr = wave & 3;
     const int64_t GG = (int64_t)G * G;
 
-    TileIter it(ntiles);
-    if (it.t >= it.end) return;
+    StripIter it(nseg, tiles_x, seg_rows, G);
+    if (!it.valid()) return;
 
     load_u(u3, s_u);
     // conv3 biases of the lane's output channels 16 nb + 4q + r
@@ -507,8 +547,10 @@ __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2
 
     // next tile's input, as float4 chunks (8 per pixel) of the 18 x 34 tile
     v4f pa[CHUNKS_PER_THREAD34];
-    auto fetch_act = [&](int t) {
-        const int y0 = (t / tiles_x) * OH34 - 1, x0 = (t % tiles_x) * OW34 - 1;  // conv3 region origin
+    // the conv3 region of a tile starts one row above its outputs, or (continuing a strip) one below
+    auto region_y = [](const StripIter& t) { return t.y() + (t.continues() ? 1 : -1); };
+    auto fetch_act = [&](const StripIter& t) {
+        const int y0 = region_y(t), x0 = t.x() - 1;  // conv3 region origin
 #pragma unroll
         for (int k = 0; k < CHUNKS_PER_THREAD34; ++k) {
             int e = tid + k * kThreads34;
@@ -528,20 +570,23 @@ __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2
             if (e < CHUNKS) *reinterpret_cast<v4f*>(s_in + (e >> 3) * PS + (e & 7) * 4) = pa[k];
         }
     };
-    fetch_act(it.t);
+    fetch_act(it);
     stash_act();
     __syncthreads();
 
-    for (; it.t < it.end; it.t += it.step) {
-        const int ty0 = (it.t / tiles_x) * OH34, tx0 = (it.t % tiles_x) * OW34;  // output tile origin
-        const int y0 = ty0 - 1, x0 = tx0 - 1;                                      // conv3 region origin
-        const int next = it.t + it.step;
+    for (int k = 0; it.valid(); ++k) {
+        const int ty0 = it.y(), tx0 = it.x();                 // output tile origin
+        const int y0 = region_y(it), x0 = tx0 - 1;            // conv3 region origin
+        const bool cont = it.continues();
+        StripIter nx = it;
+        nx.advance();
+        const bool more = nx.valid();
 
 #pragma unroll 1
         for (int round = 0; round < 2; ++round) {
             // the next tile's input is requested at the start of the second round, so that the
             // address work and the issue of its loads share the round with the matrix instructions
-            if (round == 1 && next < it.end) fetch_act(next);
+            if (round == 1 && more) fetch_act(nx);
             // each round's results go straight into conv4: for every pixel p of the round,
             // Z_nb[p][n] = sum over block nb's channels c of act3[p][c] w4[n / 9][c][n % 9] (n < 18), stored
             // over input rows that the remaining reads no longer need, after every wave has read them
@@ -592,16 +637,26 @@ __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2
             });
         }
         __syncthreads();
-        // each output pixel sums its 9 taps of both partials: disp[o] = b4[o] + sum_t Z[pixel + tap t][9 o + t]
-        for (int e = tid; e < OH34 * OW34; e += kThreads34) {
+        // each output pixel sums its 9 taps of both partials: disp[o] = b4[o] + sum_t Z[pixel + tap t][9 o + t].
+        // Tap rows are counted from the row above the outputs; continuing a strip, the first two of
+        // them are the previous region's last two (kept summed), the rest this region's rows 0, 1, ...
+        const int oh = cont ? OHB : OH34, rshift = cont ? 2 : 0;
+        const float(*zs_prev)[RW][ZS34] = s_zs[(k & 1) ^ 1];
+        for (int e = tid; e < oh * OW34; e += kThreads34) {
             const int oy = e / OW34, ox = e - oy * OW34;
             float d0 = bias4[0], d1 = bias4[1];
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
-                const int pr = oy + t / 3, pc = ox + t % 3;
-                const float* zp = s_in + (pr < 8 ? 0 : ZOFF1) + ((pr & 7) * RW + pc) * ZS34;
-                d0 += zp[t] + zp[ZAREA + t];
-                d1 += zp[9 + t] + zp[ZAREA + 9 + t];
+                const int zr = oy + t / 3, pc = ox + t % 3;
+                if (zr < rshift) {
+                    d0 += zs_prev[zr][pc][t];
+                    d1 += zs_prev[zr][pc][9 + t];
+                } else {
+                    const int pr = zr - rshift;
+                    const float* zp = s_in + (pr < 8 ? 0 : ZOFF1) + ((pr & 7) * RW + pc) * ZS34;
+                    d0 += zp[t] + zp[ZAREA + t];
+                    d1 += zp[9 + t] + zp[ZAREA + 9 + t];
+                }
             }
             const int gy = ty0 + oy, gx = tx0 + ox;
             if (gy < G && gx < G) {
@@ -609,9 +664,16 @@ __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2
                 disp[GG + (int64_t)gy * G + gx] = d1;
             }
         }
+        // this region's last two rows (14, 15) for the next tile of the strip
+        for (int e = tid; e < 2 * RW * ZS34; e += kThreads34) {
+            const int rr = e / (RW * ZS34), rem = e - rr * (RW * ZS34), pc = rem / ZS34, n = rem - pc * ZS34;
+            const float* zp = s_in + ZOFF1 + ((6 + rr) * RW + pc) * ZS34;
+            s_zs[k & 1][rr][pc][n] = zp[n] + zp[ZAREA + n];
+        }
         __syncthreads();
-        if (next < it.end) stash_act();
+        if (more) stash_act();
         __syncthreads();
+        it = nx;
     }
 }
 
@@ -664,10 +726,28 @@ void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision
     k_wino_weights<<<cdiv(NU, 256), 256, 0, stream>>>(w.w[1], u2);
     k_wino_weights<<<cdiv(NU, 256), 256, 0, stream>>>(w.w[2], u3);
     const int tx12 = (int)cdiv(G, RW), n12 = tx12 * (int)cdiv(G, RH);
-    const int tx34 = (int)cdiv(G, OW34), n34 = tx34 * (int)cdiv(G, OH34);
+    const int tx34 = (int)cdiv(G, OW34);
+    // segment length: the number of continuing tiles per segment that minimises the tiles of the
+    // busiest block (the first tile of a segment writes OH34 rows, the others OHB)
+    int kb34 = 0, n34 = 0;
+    {
+        const unsigned gmax = persistent_grid(1 << 30);
+        int64_t best = -1;
+        for (int kb = 0; kb <= 64; ++kb) {
+            const int seg = OH34 + OHB * kb, nseg = tx34 * (int)cdiv(G, seg);
+            const unsigned grid = nseg < (int)gmax ? (unsigned)std::max(8, (nseg + 7) / 8 * 8) : gmax;
+            const int64_t cost = (int64_t)cdiv(nseg, grid) * (kb + 1);
+            if (best < 0 || cost <= best) {
+                best = cost;
+                kb34 = kb;
+                n34 = nseg;
+            }
+            if (seg >= G) break;
+        }
+    }
     k_conv12_f32<<<persistent_grid(n12), kThreads12, 0, stream>>>(G, tx12, n12, vel, w.w[0], w.b[0], u2, w.b[1], act2);
-    k_conv34_f32<<<persistent_grid(n34), kThreads34, 0, stream>>>(G, tx34, n34, act2, u3, w.b[2], w.w[3], w.b[3],
-                                                                 disp);
+    k_conv34_f32<<<persistent_grid(n34), kThreads34, 0, stream>>>(G, tx34, n34, OH34 + OHB * kb34, act2, u3,
+                                                                 w.b[2], w.w[3], w.b[3], disp);
     hip_check(hipGetLastError(), "predict launch");
 }
 
