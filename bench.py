@@ -37,15 +37,51 @@ CNN_MACS_PER_PIXEL = 2 * 32 * 9 + 32 * 32 * 9 * 2 + 32 * 2 * 9  # 19,584
 WINO_USEFUL_MACS_PER_PIXEL = 2 * 32 * 9 + 2 * 32 * 32 * 4 + 32 * 2 * 9  # 9,344
 
 
+def _cdiv(a, b):
+    return -(-a // b)
+
+
+def conv34_tiles(G: int, cus: int) -> int:
+    """Tiles the FP32 conv34 kernel runs over a G x G overlay: column strips 30 outputs wide, cut into
+    segments of 14 + 16 kb rows (a first tile of 14 output rows, then kb tiles of 16 that reuse the two
+    region rows above them), kb chosen as the kernel's host code chooses it for `cus` compute units."""
+    tx, gmax = _cdiv(G, 30), max(8, _cdiv(cus, 8) * 8)
+    best = None
+    for kb in range(65):
+        seg = 14 + 16 * kb
+        nseg = tx * _cdiv(G, seg)
+        grid = max(8, _cdiv(nseg, 8) * 8) if nseg < gmax else gmax
+        cost = _cdiv(nseg, grid) * (kb + 1)
+        if best is None or cost <= best[0]:
+            best = (cost, kb)
+        if seg >= G:
+            break
+    seg = 14 + 16 * best[1]
+    tiles = 0
+    for sy in range(_cdiv(G, seg)):
+        ylim, n = min((sy + 1) * seg, G), 1
+        while sy * seg + 14 + 16 * (n - 1) < ylim:
+            n += 1
+        tiles += n
+    return tx * tiles
+
+
+def _cus() -> int:
+    """Compute units of GPU 0 (the MI355X's 256 when no GPU is visible)."""
+    import torch
+    if not torch.cuda.is_available():
+        return 256
+    return torch.cuda.get_device_properties(0).multi_processor_count
+
+
 def cnn_issued_macs(G: int, precision: str) -> float:
     """Matrix-core MACs one forward pass issues over a G x G overlay, padding and recomputed halos
     included (per tile, as the kernels are written)."""
-    def cdiv(a, b):
-        return -(-a // b)
+    cdiv = _cdiv
     if precision == "f32":
         regions12 = cdiv(G, 32) * cdiv(G, 16)  # 16 x 32 regions: conv1 (K 18 -> 20) on the 39 M-blocks of
-        tiles34 = cdiv(G, 30) * cdiv(G, 14)    # the 18 x 34 input tile, then conv2 as Winograd F(2x2,3x3);
-        # 14 x 30 output tiles: conv3 as Winograd on their 16 x 32 region, conv4 as 16 matrix columns
+        tiles34 = conv34_tiles(G, _cus())      # the 18 x 34 input tile, then conv2 as Winograd F(2x2,3x3);
+        # conv34 tiles: conv3 as Winograd on a 16 x 32 region, conv4 as 16 matrix columns
         return (regions12 * (624 * 20 * 32 + 128 * 16 * 32 * 32) +
                 tiles34 * (128 * 16 * 32 * 32 + 512 * 32 * 16))
     if precision == "bf16":
