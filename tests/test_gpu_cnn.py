@@ -49,8 +49,10 @@ def _square_mesh(C, G):
 
 
 # G = 601: several tiles per persistent block (the loop paths with a next tile), ragged in
-# every tile dimension of both precisions
-@pytest.mark.parametrize("G,seed", [(1, 1), (2, 2), (3, 3), (37, 4), (64, 5), (100, 6), (131, 7), (601, 8)])
+# every tile dimension of both precisions; 601 and 777: conv34's strips in segments of 62 and 94 rows
+# (tiles that continue a strip), the last segment of 777 ending 11 rows past the grid
+@pytest.mark.parametrize("G,seed", [(1, 1), (2, 2), (3, 3), (37, 4), (64, 5), (100, 6), (131, 7), (601, 8),
+                                    (777, 9)])
 def test_cnn_f32_full_grid(C, oracle_mod, wl, G, seed):
     print(f"[cnn f32] G={G} seed={seed}", flush=True)
     rng = np.random.default_rng(seed)
