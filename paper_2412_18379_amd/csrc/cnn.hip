@@ -32,6 +32,7 @@
 // The next tile's input is fetched into registers while the current tile
 // computes.
 #include "common.h"
+#include "strip.h"
 
 namespace cnnsns {
 namespace {
@@ -474,39 +475,11 @@ static_assert(2 * ZAREA <= ZOFF1, "round 0's partials fit in the input rows that
 static_assert(ZOFF1 + 2 * ZAREA <= NIN * PS, "round 1's partials fit after them");
 constexpr int OHB = RH;                   // output rows of a tile that continues a strip
 
-// conv34 walks down column strips (OW34 outputs wide) in segments of seg_rows output rows: the first
-// tile of a segment computes conv3 on its 16 x 32 region and writes OH34 = 14 output rows; every
-// further tile computes conv3 on the 16 rows below the previous region only and writes OHB = 16 rows,
-// taking the conv4 products of the two region rows above it (the previous region's last two, kept in
-// LDS as the sum of both channel blocks' partials) instead of recomputing them.  Segments are
-// numbered row-major over (segment row, strip) and split into 8 contiguous ranges, one per XCD, as
-// the tiles of conv12.
-struct StripIter {
-    int s, end, step, j, tiles_x, seg_rows, G;
-    __device__ StripIter(int nseg, int tiles_x_, int seg_rows_, int G_)
-        : j(0), tiles_x(tiles_x_), seg_rows(seg_rows_), G(G_)
-    {
-        const int nx = 8;
-        const int xcd = blockIdx.x % nx, slot = blockIdx.x / nx;
-        s = (int)((int64_t)nseg * xcd / nx) + slot;
-        end = (int)((int64_t)nseg * (xcd + 1) / nx);
-        step = gridDim.x / nx;
-    }
-    __device__ bool valid() const { return s < end; }
-    __device__ bool continues() const { return j > 0; }
-    __device__ int y() const { return (s / tiles_x) * seg_rows + (j == 0 ? 0 : OH34 + OHB * (j - 1)); }
-    __device__ int x() const { return (s % tiles_x) * OW34; }
-    __device__ void advance()
-    {
-        const int ylim = min((s / tiles_x + 1) * seg_rows, G);
-        if ((s / tiles_x) * seg_rows + OH34 + OHB * j < ylim) {
-            ++j;
-        } else {
-            s += step;
-            j = 0;
-        }
-    }
-};
+// conv34 walks down column strips (strip.h): the first tile of a segment computes conv3 on its 16 x 32
+// region and writes OH34 = 14 output rows; every further tile computes conv3 on the 16 rows below the
+// previous region only and writes OHB = 16 rows, taking the conv4 products of the two region rows
+// above it (the previous region's last two, kept in LDS as the sum of both channel blocks' partials).
+using Strip34 = StripIter<OH34, OHB, OW34>;
 
 __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_conv34_f32(
     int32_t G, int tiles_x, int nseg, int seg_rows, const float* __restrict__ act2, const float* __restrict__ u3,
@@ -525,7 +498,7 @@ __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2
     const int nb = wave >> 2, wr = wave & 3;
     const int64_t GG = (int64_t)G * G;
 
-    StripIter it(nseg, tiles_x, seg_rows, G);
+    Strip34 it(nseg, tiles_x, seg_rows, G);
     if (!it.valid()) return;
 
     load_u(u3, s_u);
@@ -548,8 +521,8 @@ __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2
     // next tile's input, as float4 chunks (8 per pixel) of the 18 x 34 tile
     v4f pa[CHUNKS_PER_THREAD34];
     // the conv3 region of a tile starts one row above its outputs, or (continuing a strip) one below
-    auto region_y = [](const StripIter& t) { return t.y() + (t.continues() ? 1 : -1); };
-    auto fetch_act = [&](const StripIter& t) {
+    auto region_y = [](const Strip34& t) { return t.y() + (t.continues() ? 1 : -1); };
+    auto fetch_act = [&](const Strip34& t) {
         const int y0 = region_y(t), x0 = t.x() - 1;  // conv3 region origin
 #pragma unroll
         for (int k = 0; k < CHUNKS_PER_THREAD34; ++k) {
@@ -578,7 +551,7 @@ __global__ __launch_bounds__(kThreads34) __attribute__((amdgpu_waves_per_eu(2, 2
         const int ty0 = it.y(), tx0 = it.x();                 // output tile origin
         const int y0 = region_y(it), x0 = tx0 - 1;            // conv3 region origin
         const bool cont = it.continues();
-        StripIter nx = it;
+        Strip34 nx = it;
         nx.advance();
         const bool more = nx.valid();
 
@@ -727,24 +700,8 @@ void run_cnn(int32_t G, const float* vel, const cnnsns_cnn& w, int32_t precision
     k_wino_weights<<<cdiv(NU, 256), 256, 0, stream>>>(w.w[2], u3);
     const int tx12 = (int)cdiv(G, RW), n12 = tx12 * (int)cdiv(G, RH);
     const int tx34 = (int)cdiv(G, OW34);
-    // segment length: the number of continuing tiles per segment that minimises the tiles of the
-    // busiest block (the first tile of a segment writes OH34 rows, the others OHB)
-    int kb34 = 0, n34 = 0;
-    {
-        const unsigned gmax = persistent_grid(1 << 30);
-        int64_t best = -1;
-        for (int kb = 0; kb <= 64; ++kb) {
-            const int seg = OH34 + OHB * kb, nseg = tx34 * (int)cdiv(G, seg);
-            const unsigned grid = nseg < (int)gmax ? (unsigned)std::max(8, (nseg + 7) / 8 * 8) : gmax;
-            const int64_t cost = (int64_t)cdiv(nseg, grid) * (kb + 1);
-            if (best < 0 || cost <= best) {
-                best = cost;
-                kb34 = kb;
-                n34 = nseg;
-            }
-            if (seg >= G) break;
-        }
-    }
+    int n34 = 0;
+    const int kb34 = strip_plan(G, OH34, OHB, OW34, persistent_grid(1 << 30), &n34);
     k_conv12_f32<<<persistent_grid(n12), kThreads12, 0, stream>>>(G, tx12, n12, vel, w.w[0], w.b[0], u2, w.b[1], act2);
     k_conv34_f32<<<persistent_grid(n34), kThreads34, 0, stream>>>(G, tx34, n34, OH34 + OHB * kb34, act2, u3,
                                                                  w.b[2], w.w[3], w.b[3], disp);
