@@ -40,7 +40,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # the source file(s) each benchmark kernel group is built from
 SOURCES = {
-    "cnn_forward_f32": ("cnn.hip",),
+    "cnn_forward_f32": ("cnn.hip", "strip.h"),
     "cnn_forward_bf16": ("cnn_bf16.hip",),
     "cnn_forward_fp8": ("cnn_fp8.hip",),
     "k_locate_plain": ("sns_walk.hip",),
