@@ -1,0 +1,208 @@
+"""Bit-for-bit parity of the displacement CNN forward passes (Sec. 2.3) on representable nets.
+
+A net whose weights are 0, +-1 or +-1/2 and whose biases are small integers or quarters, fed with
+integer velocities in [-3, 3], keeps every hidden activation a small integer and every output a
+multiple of 1/8.  Every arithmetic step of every pass is then exact, whatever its order:
+* FP32, conv2/conv3 as Winograd F(2x2,3x3): the weight transform scales by 1/2 and 1/4, the input
+  and output transforms only add and subtract, so every transformed value and every partial sum is
+  a multiple of 1/8 far below 2^21 (exact in FP32);
+* BF16: integers up to 256 and the weights are BF16 values; products accumulate in FP32;
+* FP8 e4m3: integers up to 16 at the layer's power-of-two scale (the interval bound below);
+* 3D (3 x 3 x 3 kernels), FP32 and BF16 (whose split first layer has zero low parts here).
+So each pass must equal the FP64 oracle exactly: over the whole grid on small overlays, and on
+sampled pixels and dense windows of the 16M-triangle workload's 4096 x 4096 overlay and the
+5.8M-tetrahedron workload's 128^3 overlay, in the launch configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+import torch
+
+from test_gpu_cnn_fp8 import exact_net
+
+
+def _bounds(ws, bs, vmax):
+    """Interval bound of each layer's output magnitude given |velocity| <= vmax, at any grid size
+    (ReLU only shrinks magnitudes)."""
+    b, out = float(vmax), []
+    for w, bias in zip(ws, bs):
+        row = np.abs(np.asarray(w, np.float64)).reshape(w.shape[0], -1).sum(axis=1)
+        b = float((row * b + np.abs(np.asarray(bias, np.float64))).max())
+        out.append(b)
+    return out
+
+
+def _representable(ws, bs):
+    for w in ws:
+        assert np.all(np.isin(np.asarray(w, np.float64), (0.0, 1.0, -1.0, 0.5, -0.5)))
+    for b in bs:
+        assert np.all(np.asarray(b, np.float64) * 4 == np.round(np.asarray(b, np.float64) * 4))
+
+
+def exact_net3(seed):
+    """The 3D form: one or two +-1 weights per output channel of layers 1-3 at random input channels
+    and taps, six +-1/2 weights per output of layer 4, small integer biases."""
+    rng = np.random.default_rng(seed)
+    ch = (3, 32, 32, 32, 3)
+    ws = [np.zeros((ch[l + 1], ch[l], 3, 3, 3), np.float32) for l in range(4)]
+    bs = [rng.integers(0, 2, 32).astype(np.float32), rng.integers(-1, 2, 32).astype(np.float32),
+          rng.integers(-1, 2, 32).astype(np.float32), np.array([0.25, -1.5, 0.5], np.float32)]
+    for l in range(3):
+        for o in range(32):
+            for _ in range(rng.integers(1, 3)):
+                dz, dy, dx = rng.integers(0, 3, 3)
+                ws[l][o, rng.integers(0, ch[l]), dz, dy, dx] = rng.choice([-1, 1])
+    for o in range(3):
+        for _ in range(6):
+            dz, dy, dx = rng.integers(0, 3, 3)
+            ws[3][o, rng.integers(0, 32), dz, dy, dx] = rng.choice([-0.5, 0.5])
+    return ws, bs
+
+
+def test_exact_nets_are_representable(oracle_mod):
+    """CPU: the premise.  The 2D net's hidden layers stay within 16 (FP8's exact integers) and the 3D
+    net's within 256 (BF16's), at any grid size; on a small grid the oracle's outputs are multiples of
+    1/8 and equal torch's float64 convolutions exactly."""
+    for seed in (1, 2, 4):
+        ws, bs = exact_net(seed)
+        _representable(ws, bs)
+        assert max(_bounds(ws, bs, 3)[:3]) <= 16
+    ws3, bs3 = exact_net3(6)
+    _representable(ws3, bs3)
+    assert max(_bounds(ws3, bs3, 3)[:3]) <= 256
+
+    rng = np.random.default_rng(1)
+    vel = rng.integers(-3, 4, size=(2, 23, 23)).astype(np.float32)
+    ws, bs = exact_net(2)
+    ref = oracle_mod.cnn_forward(vel, ws, bs)
+    x = torch.from_numpy(vel.astype(np.float64))[None]
+    for l in range(4):
+        x = torch.nn.functional.conv2d(x, torch.from_numpy(ws[l].astype(np.float64)),
+                                       torch.from_numpy(bs[l].astype(np.float64)), padding=1)
+        if l < 3:
+            x = torch.relu(x)
+    assert np.array_equal(ref, x[0].numpy())
+    assert np.all(ref * 8 == np.round(ref * 8))
+
+    vel3 = rng.integers(-3, 4, size=(3, 9, 9, 9)).astype(np.float32)
+    ref3 = oracle_mod.cnn3_forward(vel3, ws3, bs3)
+    x = torch.from_numpy(vel3.astype(np.float64))[None]
+    for l in range(4):
+        x = torch.nn.functional.conv3d(x, torch.from_numpy(ws3[l].astype(np.float64)),
+                                       torch.from_numpy(bs3[l].astype(np.float64)), padding=1)
+        if l < 3:
+            x = torch.relu(x)
+    assert np.array_equal(ref3, x[0].numpy())
+    assert np.all(ref3 * 8 == np.round(ref3 * 8))
+
+
+@pytest.fixture(scope="module")
+def C():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_18379_amd import cnnsns
+    cnnsns.lib()
+    return cnnsns
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _square_mesh(C, G):
+    xy = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], dtype=np.float64)
+    tri = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    return C.Mesh(xy, tri, overlay_side=G)
+
+
+def _cube_mesh(C, G):
+    from paper_2412_18379_amd import workload as W
+    xyz, tet = W.kuhn_mesh(2, seed=0, jitter=0.0)
+    return C.Mesh3D(xyz, tet, overlay_side=G)
+
+
+# 7: one tile; 131: ragged tiles; 601: several tiles per persistent block and conv34 tiles that
+# continue a column strip
+@pytest.mark.gpu
+@pytest.mark.parametrize("G,seed", [(7, 1), (131, 2), (601, 4)])
+def test_exact_full_grid(C, oracle_mod, G, seed):
+    print(f"[cnn exact] G={G} seed={seed}", flush=True)
+    rng = np.random.default_rng(300 + G)
+    vel = rng.integers(-3, 4, size=(2, G, G)).astype(np.float32)
+    ws, bs = exact_net(seed)
+    ref = oracle_mod.cnn_forward(vel, ws, bs)
+    mesh = _square_mesh(C, G)
+    W = C.Weights(ws, bs)
+    for prec in ("f32", "bf16", "fp8"):
+        got = C.predict(mesh, _dev(vel), W, prec).cpu().numpy().astype(np.float64)
+        bad = np.count_nonzero(got != ref)
+        print(f"  {prec}: {bad} of {ref.size} outputs differ", flush=True)
+        assert bad == 0
+    mesh.close()
+
+
+@pytest.mark.gpu
+def test_exact_full_size_sampled(C, oracle_mod):
+    """The 4096 x 4096 overlay: 2000 random pixels, the four corners and three dense 64 x 64 windows
+    (a corner, one across the middle, the opposite corner) in all three precisions."""
+    G = 4096
+    print(f"[cnn exact] G={G}", flush=True)
+    rng = np.random.default_rng(304)
+    vel = rng.integers(-3, 4, size=(2, G, G)).astype(np.float32)
+    ws, bs = exact_net(4)
+    rows = np.concatenate([rng.integers(0, G, 2000), [0, 0, G - 1, G - 1]])
+    cols = np.concatenate([rng.integers(0, G, 2000), [0, G - 1, 0, G - 1]])
+    ref_px = oracle_mod.cnn_pixels(vel, ws, bs, rows, cols).T
+    wins = [(0, 0), (G // 2 - 37, G // 2 - 29), (G - 64, G - 64)]
+    ref_w = [oracle_mod.cnn_window(vel, ws, bs, r, c, 64, 64) for r, c in wins]
+    mesh = _square_mesh(C, G)
+    W = C.Weights(ws, bs)
+    vd = _dev(vel)
+    for prec in ("f32", "bf16", "fp8"):
+        got = C.predict(mesh, vd, W, prec).cpu().numpy()
+        assert np.array_equal(got[:, rows, cols].astype(np.float64), ref_px), prec
+        for (r, c), ref in zip(wins, ref_w):
+            assert np.array_equal(got[:, r:r + 64, c:c + 64].astype(np.float64), ref), (prec, r, c)
+        print(f"  {prec}: equal", flush=True)
+    mesh.close()
+
+
+# 5: inside one block; 33 and 70: ragged z-sweep blocks and FP32 row segments
+@pytest.mark.gpu
+@pytest.mark.parametrize("G", [5, 33, 70])
+def test_exact3_full_grid(C, oracle_mod, G):
+    print(f"[cnn3d exact] G={G}", flush=True)
+    rng = np.random.default_rng(400 + G)
+    vel = rng.integers(-3, 4, size=(3, G, G, G)).astype(np.float32)
+    ws, bs = exact_net3(6)
+    ref = oracle_mod.cnn3_forward(vel, ws, bs)
+    mesh = _cube_mesh(C, G)
+    W = C.Weights3D(ws, bs)
+    for prec in ("f32", "bf16"):
+        got = C.predict3d(mesh, _dev(vel), W, prec).cpu().numpy().astype(np.float64)
+        bad = np.count_nonzero(got != ref)
+        print(f"  {prec}: {bad} of {ref.size} outputs differ", flush=True)
+        assert bad == 0
+    mesh.close()
+
+
+@pytest.mark.gpu
+def test_exact3_full_size_windows(C, oracle_mod):
+    """The 128^3 overlay: windows on the faces, across the middle and at the far corner."""
+    G = 128
+    print(f"[cnn3d exact] G={G}", flush=True)
+    rng = np.random.default_rng(528)
+    vel = rng.integers(-3, 4, size=(3, G, G, G)).astype(np.float32)
+    ws, bs = exact_net3(6)
+    wins = [((0, 0, 0), (1, G, G)), ((G // 2 - 2, G // 2 - 5, 0), (4, 10, G)), ((G - 3, G - 9, G - 40), (3, 9, 40)),
+            ((31, 7, 60), (3, 3, 8))]
+    refs = [oracle_mod.cnn3_window(vel, ws, bs, o, s) for o, s in wins]
+    mesh = _cube_mesh(C, G)
+    W = C.Weights3D(ws, bs)
+    vd = _dev(vel)
+    for prec in ("f32", "bf16"):
+        got = C.predict3d(mesh, vd, W, prec).cpu().numpy()
+        for (o, s), ref in zip(wins, refs):
+            win = got[:, o[0]:o[0] + s[0], o[1]:o[1] + s[1], o[2]:o[2] + s[2]].astype(np.float64)
+            assert np.array_equal(win, ref), (prec, o, s)
+        print(f"  {prec}: equal", flush=True)
+    mesh.close()
