@@ -103,10 +103,35 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _stream(stream) -> ctypes.c_void_p:
+def _stream(stream, device: Optional[int] = None) -> ctypes.c_void_p:
+    """The given stream, else the current stream of `device` (default: the current device)."""
     if stream is None:
-        stream = torch.cuda.current_stream()
+        stream = torch.cuda.current_stream(device)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _on(device: int, *named):
+    """Every given device tensor must be on the GPU the mesh was built on: the library takes raw
+    pointers of that device."""
+    for name, t in named:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError(f"{name}: device tensor expected")
+        if t.device.index != device:
+            raise ValueError(f"{name}: on cuda:{t.device.index}, but the mesh is on cuda:{device}")
+
+
+CNN_SHAPES = [(32, 2, 3, 3), (32, 32, 3, 3), (32, 32, 3, 3), (2, 32, 3, 3)]
+CNN3_SHAPES = [(32, 3, 3, 3, 3), (32, 32, 3, 3, 3), (32, 32, 3, 3, 3), (3, 32, 3, 3, 3)]
+
+
+def _check_layers(ws, bs, shapes, what):
+    """The kernels read every weight and bias at fixed offsets: all shapes must be exact."""
+    gw, gb = [tuple(w.shape) for w in ws], [tuple(b.shape) for b in bs]
+    if gw != list(shapes) or gb != [(sh[0],) for sh in shapes]:
+        raise ValueError(f"{what}: weights of shapes {list(shapes)} and biases of sizes "
+                         f"{[sh[0] for sh in shapes]} expected, got {gw} and {gb}")
 
 
 def _need(t: Optional[torch.Tensor], dtype, shape=None, name="tensor"):
@@ -128,6 +153,7 @@ class Mesh:
         if xy.ndim != 2 or xy.shape[1] != 2 or tri.ndim != 2 or tri.shape[1] != 3:
             raise ValueError("xy must be [n,2] and tri [m,3]")
         h = ctypes.c_void_p()
+        self.device = torch.cuda.current_device()  # the library builds on the current device
         _check(lib().cnnsns_build_mesh(xy.ctypes.data, xy.shape[0], tri.ctypes.data, tri.shape[0],
                                        int(overlay_side), _stream(stream), ctypes.byref(h)))
         self.handle = h
@@ -155,11 +181,8 @@ class Weights:
     def __init__(self, ws: Sequence, bs: Sequence, device="cuda"):
         self.w = [torch.as_tensor(w, dtype=torch.float32).to(device).contiguous() for w in ws]
         self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in bs]
-        if len(self.w) != 4 or len(self.b) != 4:
-            raise ValueError("four layers expected")
-        chans = [self.w[0].shape[1]] + [w.shape[0] for w in self.w]
-        if chans != [2, 32, 32, 32, 2] or any(tuple(w.shape[2:]) != (3, 3) for w in self.w):
-            raise ValueError(f"expected a 2-32-32-32-2 3x3 net, got {chans}")
+        _check_layers(self.w, self.b, CNN_SHAPES, "a 2-32-32-32-2 net of 3x3 kernels")
+        self.device = self.w[0].device
         self.struct = _Cnn()
         for l in range(4):
             self.struct.w[l] = self.w[l].data_ptr()
@@ -173,9 +196,10 @@ def predict(mesh: Mesh, vel: torch.Tensor, weights: Weights, precision="f32", di
     if disp is None:
         disp = torch.empty((2, G, G), dtype=torch.float32, device=vel.device)
     _need(disp, torch.float32, (2, G, G), "disp")
+    _on(mesh.device, ("vel", vel), ("disp", disp), ("weights", weights.w[0]))
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     _check(lib().cnnsns_predict(mesh.handle, _ptr(vel), ctypes.byref(weights.struct), p, _ptr(disp),
-                                _stream(stream)))
+                                _stream(stream, mesh.device)))
     return disp
 
 
@@ -186,9 +210,10 @@ def predict_noalloc(mesh: Mesh, vel: torch.Tensor, weights: Weights, disp: torch
     G = mesh.G
     _need(vel, torch.float32, (2, G, G), "vel")
     _need(disp, torch.float32, (2, G, G), "disp")
+    _on(mesh.device, ("vel", vel), ("disp", disp), ("weights", weights.w[0]))
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     _check(lib().cnnsns_predict_noalloc(mesh.handle, _ptr(vel), ctypes.byref(weights.struct), p, _ptr(disp),
-                                        _stream(stream)))
+                                        _stream(stream, mesh.device)))
     return disp
 
 
@@ -210,8 +235,10 @@ def locate(mesh: Mesh, xp: torch.Tensor, start: torch.Tensor = None, origin: tor
     _need(host, torch.int32, (n,), "host")
     _need(iters, torch.int32, (n,), "iters")
     _need(status, torch.uint8, (n,), "status")
+    _on(mesh.device, ("xp", xp), ("start", start), ("origin", origin), ("disp", disp), ("host", host),
+        ("iters", iters), ("status", status))
     _check(lib().cnnsns_locate(mesh.handle, n, _ptr(xp), _ptr(start), _ptr(origin), _ptr(disp), int(max_iter),
-                               _ptr(host), _ptr(iters), _ptr(status), _stream(stream)))
+                               _ptr(host), _ptr(iters), _ptr(status), _stream(stream, mesh.device)))
     return host, iters, status
 
 
@@ -224,9 +251,8 @@ class ClsWeights:
     def __init__(self, ws: Sequence, bs: Sequence, device="cuda"):
         self.w = [torch.as_tensor(w, dtype=torch.float32).to(device).contiguous() for w in ws]
         self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in bs]
-        if [tuple(w.shape) for w in self.w] != CLS_SHAPES or [tuple(b.shape) for b in self.b] != \
-                [(s[0],) for s in CLS_SHAPES]:
-            raise ValueError(f"classifier weights of shapes {CLS_SHAPES} expected")
+        _check_layers(self.w, self.b, CLS_SHAPES, "the classifier")
+        self.device = self.w[0].device
         self.struct = _Cls()
         for l in range(6):
             self.struct.w[l] = self.w[l].data_ptr()
@@ -244,8 +270,9 @@ def classify(mesh: Mesh, xp: torch.Tensor, weights: ClsWeights, fallback: torch.
     _need(start, torch.int32, (n,), "start")
     cls = torch.empty(n, dtype=torch.int32, device=xp.device) if want_class else None
     logits = torch.empty((n, 81), dtype=torch.float32, device=xp.device) if want_logits else None
+    _on(mesh.device, ("xp", xp), ("fallback", fallback), ("start", start), ("weights", weights.w[0]))
     _check(lib().cnnsns_classify(mesh.handle, n, _ptr(xp), ctypes.byref(weights.struct), _ptr(fallback),
-                                 _ptr(start), _ptr(cls), _ptr(logits), _stream(stream)))
+                                 _ptr(start), _ptr(cls), _ptr(logits), _stream(stream, mesh.device)))
     return start, cls, logits
 
 
@@ -272,9 +299,11 @@ def locate_interpolate(mesh: Mesh, xp: torch.Tensor, nodal: torch.Tensor, start:
     _need(iters, torch.int32, (n,), "iters")
     _need(status, torch.uint8, (n,), "status")
     _need(out, torch.float64, (n, 2), "out")
+    _on(mesh.device, ("xp", xp), ("start", start), ("origin", origin), ("disp", disp), ("host", host),
+        ("iters", iters), ("status", status), ("nodal", nodal), ("out", out))
     _check(lib().cnnsns_locate_interpolate(mesh.handle, n, _ptr(xp), _ptr(start), _ptr(origin), _ptr(disp),
                                            int(max_iter), _ptr(host), _ptr(iters), _ptr(status), _ptr(nodal),
-                                           _ptr(out), _stream(stream)))
+                                           _ptr(out), _stream(stream, mesh.device)))
     return host, iters, status, out
 
 
@@ -288,6 +317,7 @@ class Mesh3D:
         if xyz.ndim != 2 or xyz.shape[1] != 3 or tet.ndim != 2 or tet.shape[1] != 4:
             raise ValueError("xyz must be [n,3] and tet [m,4]")
         h = ctypes.c_void_p()
+        self.device = torch.cuda.current_device()
         _check(lib().cnnsns_build_mesh3d(xyz.ctypes.data, xyz.shape[0], tet.ctypes.data, tet.shape[0],
                                          int(overlay_side), _stream(stream), ctypes.byref(h)))
         self.handle = h
@@ -314,13 +344,8 @@ class Weights3D:
     def __init__(self, ws: Sequence, bs: Sequence, device="cuda"):
         self.w = [torch.as_tensor(w, dtype=torch.float32).to(device).contiguous() for w in ws]
         self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in bs]
-        if len(self.w) != 4 or len(self.b) != 4:
-            raise ValueError("four layers expected")
-        chans = [self.w[0].shape[1]] + [w.shape[0] for w in self.w]
-        if chans != [3, 32, 32, 32, 3] or any(tuple(w.shape[2:]) != (3, 3, 3) for w in self.w):
-            raise ValueError(f"expected a 3-32-32-32-3 3x3x3 net, got {chans}")
-        if [b.shape[0] for b in self.b] != chans[1:]:
-            raise ValueError("bias sizes must match the output channels")
+        _check_layers(self.w, self.b, CNN3_SHAPES, "a 3-32-32-32-3 net of 3x3x3 kernels")
+        self.device = self.w[0].device
         self.struct = _Cnn()
         for l in range(4):
             self.struct.w[l] = self.w[l].data_ptr()
@@ -335,9 +360,10 @@ def predict3d(mesh: Mesh3D, vel: torch.Tensor, weights: Weights3D, precision="f3
     if disp is None:
         disp = torch.empty((3, G, G, G), dtype=torch.float32, device=vel.device)
     _need(disp, torch.float32, (3, G, G, G), "disp")
+    _on(mesh.device, ("vel", vel), ("disp", disp), ("weights", weights.w[0]))
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     _check(lib().cnnsns_predict3d(mesh.handle, _ptr(vel), ctypes.byref(weights.struct), p, _ptr(disp),
-                                  _stream(stream)))
+                                  _stream(stream, mesh.device)))
     return disp
 
 
@@ -358,8 +384,10 @@ def locate3d(mesh: Mesh3D, xp: torch.Tensor, start: torch.Tensor = None, origin:
     _need(host, torch.int32, (n,), "host")
     _need(iters, torch.int32, (n,), "iters")
     _need(status, torch.uint8, (n,), "status")
+    _on(mesh.device, ("xp", xp), ("start", start), ("origin", origin), ("disp", disp), ("host", host),
+        ("iters", iters), ("status", status))
     _check(lib().cnnsns_locate3d(mesh.handle, n, _ptr(xp), _ptr(start), _ptr(origin), _ptr(disp), int(max_iter),
-                                 _ptr(host), _ptr(iters), _ptr(status), _stream(stream)))
+                                 _ptr(host), _ptr(iters), _ptr(status), _stream(stream, mesh.device)))
     return host, iters, status
 
 
@@ -374,8 +402,9 @@ def interpolate3d(mesh: Mesh3D, xp: torch.Tensor, host: torch.Tensor, nodal: tor
     if out is None:
         out = torch.empty((n, 3), dtype=torch.float64, device=xp.device)
     _need(out, torch.float64, (n, 3), "out")
+    _on(mesh.device, ("xp", xp), ("host", host), ("nodal", nodal), ("out", out))
     _check(lib().cnnsns_interpolate3d(mesh.handle, n, _ptr(xp), _ptr(host), _ptr(nodal), _ptr(out),
-                                      _stream(stream)))
+                                      _stream(stream, mesh.device)))
     return out
 
 
@@ -390,7 +419,9 @@ def interpolate(mesh: Mesh, xp: torch.Tensor, host: torch.Tensor, nodal: torch.T
     if out is None:
         out = torch.empty((n, 2), dtype=torch.float64, device=xp.device)
     _need(out, torch.float64, (n, 2), "out")
-    _check(lib().cnnsns_interpolate(mesh.handle, n, _ptr(xp), _ptr(host), _ptr(nodal), _ptr(out), _stream(stream)))
+    _on(mesh.device, ("xp", xp), ("host", host), ("nodal", nodal), ("out", out))
+    _check(lib().cnnsns_interpolate(mesh.handle, n, _ptr(xp), _ptr(host), _ptr(nodal), _ptr(out),
+                                    _stream(stream, mesh.device)))
     return out
 
 
@@ -418,9 +449,12 @@ class Server:
         _need(host, torch.int32, (n,), "host")
         _need(iters, torch.int32, (n,), "iters")
         _need(start, torch.int32, (n,), "start")
+        _on(mesh.device, ("vel", vel), ("xp", xp), ("origin", origin), ("host", host), ("iters", iters),
+            ("start", start), ("weights", self.weights.w[0]))
         jid = ctypes.c_uint64()
         _check(lib().cnnsns_submit(self.handle, mesh.handle, _ptr(vel), n, _ptr(xp), _ptr(origin),
-                                   _ptr(start), _ptr(host), _ptr(iters), _stream(stream), ctypes.byref(jid)))
+                                   _ptr(start), _ptr(host), _ptr(iters), _stream(stream, mesh.device),
+                                   ctypes.byref(jid)))
         self._keep[jid.value] = (mesh, vel, xp, origin, host, iters, start)
         return jid.value
 

@@ -60,3 +60,42 @@ def test_serving_switched_off_by_default(L):
     assert L.cnnsns_server_create(1 << 20, 2, 8, C.BF16, ctypes.byref(cnn), ctypes.byref(out)) == C.EINVAL
     assert b"switched off" in L.cnnsns_last_error()
     assert not out.value
+
+
+def test_binding_rejects_malformed_nets_and_host_tensors():
+    """The kernels read every weight at a fixed offset, so the binding accepts only exact layer shapes
+    (a wrong input-channel count or a short bias would otherwise be read past its end), and passes
+    only device tensors (weights on the host would reach the kernels as host pointers)."""
+    import numpy as np
+    import torch
+    from paper_2412_18379_amd import cnnsns as C
+
+    def net(shapes):
+        return [np.zeros(s, np.float32) for s in shapes], [np.zeros(s[0], np.float32) for s in shapes]
+
+    ws, bs = net(C.CNN_SHAPES)
+    W = C.Weights(ws, bs, device="cpu")  # shapes are checked before any device is touched
+    assert W.device.type == "cpu"
+    bad = list(ws)
+    bad[1] = np.zeros((32, 16, 3, 3), np.float32)  # the second layer's input channels
+    with pytest.raises(ValueError, match="expected"):
+        C.Weights(bad, bs, device="cpu")
+    with pytest.raises(ValueError, match="expected"):
+        C.Weights(ws, bs[:3] + [np.zeros(1, np.float32)], device="cpu")  # a short last bias
+    with pytest.raises(ValueError, match="expected"):
+        C.Weights(ws[:3], bs[:3], device="cpu")
+    ws3, bs3 = net(C.CNN3_SHAPES)
+    C.Weights3D(ws3, bs3, device="cpu")
+    bad3 = list(ws3)
+    bad3[3] = np.zeros((3, 16, 3, 3, 3), np.float32)
+    with pytest.raises(ValueError, match="expected"):
+        C.Weights3D(bad3, bs3, device="cpu")
+    wc, bc = net(C.CLS_SHAPES)
+    C.ClsWeights(wc, bc, device="cpu")
+    with pytest.raises(ValueError, match="expected"):
+        C.ClsWeights(wc, bc[:5] + [np.zeros(80, np.float32)], device="cpu")
+    with pytest.raises(ValueError, match="device tensor"):
+        C._on(0, ("weights", W.w[0]))
+    C._on(0, ("absent", None))
+    with pytest.raises(ValueError, match="device tensor"):
+        C._ptr(torch.zeros(4))
