@@ -121,9 +121,9 @@ def _cube_mesh(C, G):
 
 
 # 7: one tile; 131: ragged tiles; 601: several tiles per persistent block and conv34 tiles that
-# continue a column strip
+# continue a column strip; 1024: every pixel of the 1M-triangle workloads' overlay
 @pytest.mark.gpu
-@pytest.mark.parametrize("G,seed", [(7, 1), (131, 2), (601, 4)])
+@pytest.mark.parametrize("G,seed", [(7, 1), (131, 2), (601, 4), (1024, 1)])
 def test_exact_full_grid(C, oracle_mod, G, seed):
     print(f"[cnn exact] G={G} seed={seed}", flush=True)
     rng = np.random.default_rng(300 + G)
