@@ -219,6 +219,15 @@ __device__ __forceinline__ void conv32_wino_nb(const float* __restrict__ s_in, c
     v4f acc[16];
 #pragma unroll
     for (int xn = 0; xn < 16; ++xn) acc[xn] = v4f{ 0.f, 0.f, 0.f, 0.f };
+    // the weights of the next group of four transformed positions are read while this group's
+    // matrix instructions issue
+    v4f bc[2][4];
+    auto wload = [&](int stage, v4f (&b)[4]) {
+        const int hh = stage >> 2, gg = stage & 3;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) b[x] = su[(((4 * gg + x) * 2 + nb) * 2 + hh) * 64];
+    };
+    wload(0, bc[0]);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         v4f d[4][4];
@@ -226,16 +235,18 @@ __device__ __forceinline__ void conv32_wino_nb(const float* __restrict__ s_in, c
         wino_input_transform(d);
 #pragma unroll
         for (int grp = 0; grp < 4; ++grp) {
-            v4f bc[4];
-#pragma unroll
-            for (int x = 0; x < 4; ++x) bc[x] = su[(((4 * grp + x) * 2 + nb) * 2 + h) * 64];
+            const int stage = 4 * h + grp;
+            if (stage + 1 < 8) wload(stage + 1, bc[(stage + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            const v4f(&cur)[4] = bc[stage & 1];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
                     const int xn = 4 * grp + x;
-                    acc[xn] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[x][j], d[xn >> 2][xn & 3][j], acc[xn], 0, 0, 0);
+                    acc[xn] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[x][j], d[xn >> 2][xn & 3][j], acc[xn], 0, 0, 0);
                 }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     v4f m0[4], m1[4], y[4];
