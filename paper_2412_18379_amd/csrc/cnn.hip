@@ -351,7 +351,12 @@ __global__ __launch_bounds__(kThreads12) __attribute__((amdgpu_waves_per_eu(2, 2
         }
     };
 
+    // The next tile's velocity is loaded unconditionally, from clamped (valid) positions, and what
+    // lies outside the grid is zeroed when it is stashed: with no branch between the loads and their
+    // use, the compiled code waits for them only at the stash, not at the start of the tile (where
+    // it would also wait for the previous tile's activation stores).
     float pv[VEL_PER_THREAD12];
+    bool pin[VEL_PER_THREAD12];
     auto fetch_vel = [&](int t) {
         const int y0 = (t / tiles_x) * RH, x0 = (t % tiles_x) * RW;
 #pragma unroll
@@ -359,20 +364,20 @@ __global__ __launch_bounds__(kThreads12) __attribute__((amdgpu_waves_per_eu(2, 2
             // opaque to the compiler, so the positions are not kept in registers across tiles
             int e = tid + k * kThreads12;
             asm volatile("" : "+v"(e));
-            float v = 0.f;
-            if (e < 2 * VH * VW) {
-                const int c = e / (VH * VW), rem = e % (VH * VW);
-                const int gy = y0 - 2 + rem / VW, gx = x0 - 2 + rem % VW;
-                if (gy >= 0 && gy < G && gx >= 0 && gx < G) v = vel[c * GG + (int64_t)gy * G + gx];
-            }
-            pv[k] = v;
+            const int ec = min(e, 2 * VH * VW - 1);
+            const int c = ec / (VH * VW), rem = ec % (VH * VW);
+            const int gy = y0 - 2 + rem / VW, gx = x0 - 2 + rem % VW;
+            pin[k] = gy >= 0 && gy < G && gx >= 0 && gx < G;
+            pv[k] = vel[c * GG + (int64_t)min(max(gy, 0), G - 1) * G + min(max(gx, 0), G - 1)];
         }
     };
     auto stash_vel = [&]() {
 #pragma unroll
         for (int k = 0; k < VEL_PER_THREAD12; ++k) {
-            const int e = tid + k * kThreads12;
-            if (e < 2 * VH * VW) s_vel[e] = pv[k];
+            // threads past the end write the last element again, the value its owner writes (their
+            // loads were clamped to it): every store is unconditional, so no load sinks to it
+            const int e = min(tid + k * kThreads12, 2 * VH * VW - 1);
+            s_vel[e] = pin[k] ? pv[k] : 0.f;
         }
     };
     // conv1 of tile t from s_vel into s_in
@@ -446,7 +451,8 @@ __global__ __launch_bounds__(kThreads12) __attribute__((amdgpu_waves_per_eu(2, 2
     for (; it.t < it.end; it.t += it.step) {
         const int y0 = (it.t / tiles_x) * RH, x0 = (it.t % tiles_x) * RW;
         const int next = it.t + it.step;
-        if (next < it.end) fetch_vel(next);  // lands while conv2 runs
+        fetch_vel(next < it.end ? next : it.t);  // lands while conv2 runs (after the last tile: unused)
+        __builtin_amdgcn_sched_barrier(0);  // the loads stay here (the scheduler would sink them to their use)
 
         // A tile takes two phases.  First conv2's matrix instructions and output transform on block
         // row ty = wave (reading s_in) and the next tile's velocity into s_vel; then the next tile's
@@ -462,7 +468,7 @@ __global__ __launch_bounds__(kThreads12) __attribute__((amdgpu_waves_per_eu(2, 2
                 yk[e][1] = y[e][1];
             }
         });
-        if (next < it.end) stash_vel();  // conv1 of this tile is done with s_vel
+        stash_vel();  // conv1 of this tile is done with s_vel
         __syncthreads();                 // every wave is done reading this tile's s_in
         if (next < it.end) conv1(next);
         {

@@ -247,30 +247,30 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         l1_off[jj] = t < 9 ? (t / 3) * WV + t % 3 : 0;
     }
 
+    // The next tile's velocity is loaded unconditionally, from clamped (valid) positions, and what
+    // lies outside the grid is zeroed when it is stashed: with no branch between the loads and their
+    // use, the compiled code waits for them at the stash and not before conv2's first matrix
+    // instruction (which a register shared with a pending load had made it do).
     float pu[VEL_PER_THREAD], pw[VEL_PER_THREAD];
+    bool pin[VEL_PER_THREAD];
     auto fetch_vel = [&](int t) {
         const int y0 = (t / tiles_x) * OH - 4, x0 = (t % tiles_x) * OW - 4;
 #pragma unroll
         for (int k = 0; k < VEL_PER_THREAD; ++k) {
-            const int e = tid + k * kThreads;
-            float u = 0.f, v = 0.f;
-            if (e < HV * WV) {
-                const int gy = y0 + e / WV, gx = x0 + e % WV;
-                if (inside(gy, gx, G)) {
-                    const int64_t o = (int64_t)gy * G + gx;
-                    u = vel[o];
-                    v = vel[GG + o];
-                }
-            }
-            pu[k] = u;
-            pw[k] = v;
+            const int e = min(tid + k * kThreads, HV * WV - 1);
+            const int gy = y0 + e / WV, gx = x0 + e % WV;
+            pin[k] = inside(gy, gx, G);
+            const int64_t o = (int64_t)min(max(gy, 0), G - 1) * G + min(max(gx, 0), G - 1);
+            pu[k] = vel[o];
+            pw[k] = vel[GG + o];
         }
     };
     auto stash_vel = [&]() {
 #pragma unroll
         for (int k = 0; k < VEL_PER_THREAD; ++k) {
             const int e = tid + k * kThreads;
-            if (e < HV * WV) s_vel[e] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{ pu[k], pw[k] }, bf16x2));
+            const float u = pin[k] ? pu[k] : 0.f, v = pin[k] ? pw[k] : 0.f;
+            if (e < HV * WV) s_vel[e] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{ u, v }, bf16x2));
         }
     };
     // conv1 of tile t on its 20 x 36 region into bufA: K = 18 (9 taps x 2 channels) padded to 32
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         const bool edge = ty0 < 4 || tx0 < 4 || ty0 + OH + 4 > G || tx0 + OW + 4 > G;
 
         const int next = it.t + it.step;
-        if (next < it.end) fetch_vel(next);  // lands while conv2-conv4 run
+        fetch_vel(next < it.end ? next : it.t);  // lands while conv2-conv4 run (after the last tile: unused)
 
         if (edge)
             conv32_bf16<H2, W2, PXS, PXS2, BPW2, MB2, true>(bufA, bufB, s_w23, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave,
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             conv32_bf16<H2, W2, PXS, PXS2, BPW2, MB2, false>(bufA, bufB, s_w23, b2lo, b2hi, ty0 - 2, tx0 - 2, G, wave,
                                                              lane);
         __syncthreads();
-        if (next < it.end) stash_vel();
+        stash_vel();
         if (edge)
             conv32_bf16<H3, W3, PXS2, PXS, BPW3, MB3, true>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G,
                                                             wave, lane);

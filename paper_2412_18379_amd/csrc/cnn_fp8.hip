@@ -332,29 +332,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
 
     float pu[VEL_PER_THREAD], pw[VEL_PER_THREAD];
-    auto fetch_vel = [&](int t) {
+    bool pin[VEL_PER_THREAD];
+    auto fetch_vel = [&](int t) {  // unconditional loads from clamped positions, as in the BF16 pass
         const int y0 = (t / tiles_x) * OH - 4, x0 = (t % tiles_x) * OW - 4;
 #pragma unroll
         for (int k = 0; k < VEL_PER_THREAD; ++k) {
-            const int e = tid + k * kThreads;
-            float u = 0.f, v = 0.f;
-            if (e < HV * WV) {
-                const int gy = y0 + e / WV, gx = x0 + e % WV;
-                if (inside(gy, gx, G)) {
-                    const int64_t o = (int64_t)gy * G + gx;
-                    u = vel[o];
-                    v = vel[GG + o];
-                }
-            }
-            pu[k] = u;
-            pw[k] = v;
+            const int e = min(tid + k * kThreads, HV * WV - 1);
+            const int gy = y0 + e / WV, gx = x0 + e % WV;
+            pin[k] = inside(gy, gx, G);
+            const int64_t o = (int64_t)min(max(gy, 0), G - 1) * G + min(max(gx, 0), G - 1);
+            pu[k] = vel[o];
+            pw[k] = vel[GG + o];
         }
     };
     auto stash_vel = [&]() {
 #pragma unroll
         for (int k = 0; k < VEL_PER_THREAD; ++k) {
             const int e = tid + k * kThreads;
-            if (e < HV * WV) s_vel[e] = (uint16_t)to_e4m3_pair(pu[k] * rv, pw[k] * rv);
+            const float u = pin[k] ? pu[k] : 0.f, v = pin[k] ? pw[k] : 0.f;
+            if (e < HV * WV) s_vel[e] = (uint16_t)to_e4m3_pair(u * rv, v * rv);
         }
     };
     auto conv1 = [&](int t) {
@@ -404,7 +400,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         const int ty0 = (it.t / tiles_x) * OH, tx0 = (it.t % tiles_x) * OW;
         const bool edge = ty0 < 4 || tx0 < 4 || ty0 + OH + 4 > G || tx0 + OW + 4 > G;
         const int next = it.t + it.step;
-        if (next < it.end) fetch_vel(next);
+        fetch_vel(next < it.end ? next : it.t);  // after the last tile: unused
 
         if (edge)
             conv32_fp8<H2, W2, BPW2, MB2, true>(bufA, bufB, s_w23, i2lo, i2hi, f2lo, f2hi, ty0 - 2, tx0 - 2, G, wave,
@@ -413,7 +409,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             conv32_fp8<H2, W2, BPW2, MB2, false>(bufA, bufB, s_w23, i2lo, i2hi, f2lo, f2hi, ty0 - 2, tx0 - 2, G, wave,
                                                  lane);
         __syncthreads();
-        if (next < it.end) stash_vel();
+        stash_vel();
         if (edge)
             conv32_fp8<H3, W3, BPW3, MB3, true>(bufB, bufA, s_w23 + P2, i3lo, i3hi, f3lo, f3hi, ty0 - 1, tx0 - 1, G,
                                                 wave, lane);
