@@ -238,27 +238,32 @@ __global__ __launch_bounds__(kZThreads) __attribute__((amdgpu_waves_per_eu(2, 2)
 #pragma unroll
     for (int h = 0; h < 2; ++h) base[h] = (r * ZSX + 16 * h + col) * ZCS + 8 * grp;
 
+    // Plane p of the slab into registers: unconditional loads from clamped positions (a chunk past
+    // the end loads the last one again); the zero padding is applied when the plane is stashed,
+    // every store unconditional (a thread past the end writes the last chunk again, the value its
+    // owner writes).  So the loads stay in flight while a plane's taps run; with a branch around them
+    // the compiled code had waited for them before the plane's first matrix instruction.
     bf16x8 pf[ZCH_PER_THREAD];
-    auto fetch = [&](int p) {  // plane p of the slab into registers (zero outside the grid)
+    auto fetch = [&](int p) {
+        const int pc = min(max(p, 0), G - 1);
 #pragma unroll
         for (int k = 0; k < ZCH_PER_THREAD; ++k) {
-            const int e = tid + k * kZThreads;
-            bf16x8 v = bf16x8{ 0, 0, 0, 0, 0, 0, 0, 0 };
-            if (e < ZCHUNKS) {
-                const int cell = e >> 2, part = e & 3;
-                const int gy = ty0 + cell / ZSX - 1, gx = tx0 + cell % ZSX - 1;
-                if (p >= 0 && p < G && gy >= 0 && gy < G && gx >= 0 && gx < G)
-                    v = *reinterpret_cast<const bf16x8*>(in + ((int64_t)p * GG + (int64_t)gy * G + gx) * C + 8 * part);
-            }
-            pf[k] = v;
+            const int e = min(tid + k * kZThreads, ZCHUNKS - 1);
+            const int cell = e >> 2, part = e & 3;
+            const int gy = min(max(ty0 + cell / ZSX - 1, 0), G - 1), gx = min(max(tx0 + cell % ZSX - 1, 0), G - 1);
+            pf[k] = *reinterpret_cast<const bf16x8*>(in + ((int64_t)pc * GG + (int64_t)gy * G + gx) * C + 8 * part);
         }
     };
     auto stash = [&](int p) {
         bf16* dst = s_slab + ((p + 3) % 3) * ZSLAB;
+        const bool pin = p >= 0 && p < G;
 #pragma unroll
         for (int k = 0; k < ZCH_PER_THREAD; ++k) {
-            const int e = tid + k * kZThreads;
-            if (e < ZCHUNKS) *reinterpret_cast<bf16x8*>(dst + (e >> 2) * ZCS + 8 * (e & 3)) = pf[k];
+            const int e = min(tid + k * kZThreads, ZCHUNKS - 1);
+            const int cell = e >> 2;
+            const int gy = ty0 + cell / ZSX - 1, gx = tx0 + cell % ZSX - 1;
+            const bool on = pin && gy >= 0 && gy < G && gx >= 0 && gx < G;
+            *reinterpret_cast<bf16x8*>(dst + cell * ZCS + 8 * (e & 3)) = on ? pf[k] : bf16x8{ 0, 0, 0, 0, 0, 0, 0, 0 };
         }
     };
     fetch(z0 - 1);
@@ -285,7 +290,8 @@ __global__ __launch_bounds__(kZThreads) __attribute__((amdgpu_waves_per_eu(2, 2)
         }
     }
     for (int z = z0; z < z1; ++z) {
-        if (z + 2 < z1 + 1) fetch(z + 2);  // lands while this plane computes
+        fetch(z + 2);  // lands while this plane computes (after the block's last plane: unused)
+        __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of the plane's taps
         v4f acc[2][NB];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -328,7 +334,7 @@ __global__ __launch_bounds__(kZThreads) __attribute__((amdgpu_waves_per_eu(2, 2)
             }
         }
         __syncthreads();           // every wavefront is done with the slab of plane z - 1
-        if (z + 2 < z1 + 1) stash(z + 2);
+        stash(z + 2);  // after the last plane it replaces a plane no longer read
         __syncthreads();
     }
 }
