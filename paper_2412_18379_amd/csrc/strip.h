@@ -18,23 +18,28 @@ namespace cnnsns {
 template <int FIRST, int NEXT, int W>
 struct StripIter {
     int s, end, step, j, tiles_x, seg_rows, G;
-    __device__ StripIter(int nseg, int tiles_x_, int seg_rows_, int G_)
+    // the tiles of block `block` of `grid` (the host-side form lets the plan be checked on the CPU)
+    __host__ __device__ StripIter(int nseg, int tiles_x_, int seg_rows_, int G_, unsigned block, unsigned grid)
         : j(0), tiles_x(tiles_x_), seg_rows(seg_rows_), G(G_)
     {
         const int nx = 8;
-        const int xcd = blockIdx.x % nx, slot = blockIdx.x / nx;
+        const int xcd = block % nx, slot = block / nx;
         s = (int)((int64_t)nseg * xcd / nx) + slot;
         end = (int)((int64_t)nseg * (xcd + 1) / nx);
-        step = gridDim.x / nx;
+        step = grid / nx;
     }
-    __device__ bool valid() const { return s < end; }
-    __device__ bool continues() const { return j > 0; }                   // not the segment's first tile
-    __device__ int rows() const { return j > 0 ? NEXT : FIRST; }          // output rows it writes
-    __device__ int y() const { return (s / tiles_x) * seg_rows + (j == 0 ? 0 : FIRST + NEXT * (j - 1)); }
-    __device__ int x() const { return (s % tiles_x) * W; }
-    __device__ void advance()
+    __device__ StripIter(int nseg, int tiles_x_, int seg_rows_, int G_)
+        : StripIter(nseg, tiles_x_, seg_rows_, G_, blockIdx.x, gridDim.x)
     {
-        const int ylim = min((s / tiles_x + 1) * seg_rows, G);
+    }
+    __host__ __device__ bool valid() const { return s < end; }
+    __host__ __device__ bool continues() const { return j > 0; }           // not the segment's first tile
+    __host__ __device__ int rows() const { return j > 0 ? NEXT : FIRST; }  // output rows it writes
+    __host__ __device__ int y() const { return (s / tiles_x) * seg_rows + (j == 0 ? 0 : FIRST + NEXT * (j - 1)); }
+    __host__ __device__ int x() const { return (s % tiles_x) * W; }
+    __host__ __device__ void advance()
+    {
+        const int yend = (s / tiles_x + 1) * seg_rows, ylim = yend < G ? yend : G;
         if ((s / tiles_x) * seg_rows + FIRST + NEXT * j < ylim) {
             ++j;
         } else {
