@@ -8,7 +8,8 @@ several compute-unit counts, it plans the segments as the launcher does (strip_p
 min(units, segments) blocks rounded up to a multiple of 8), walks every block's tiles, and checks
 that in every strip the tiles' row spans partition [0, G) in order, none starting past the grid,
 that a continuing tile follows its block's previous tile directly, and that no block walks more
-tiles than the plan's cost.
+tiles than the plan's cost.  The benchmark's count of the pass's issued matrix work plans the tiles
+in Python; its tile totals must equal the walked ones.
 """
 import os
 import shutil
@@ -25,14 +26,18 @@ PROGRAM = r"""
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <utility>
 #include <vector>
 
 using namespace cnnsns;
 constexpr int FIRST = 14, NEXT = 16, W = 30;
 
+static long long total_tiles = 0;
+
 static int check(int G, unsigned cus)
 {
+    total_tiles = 0;
     const unsigned gmax = std::max(8u, (cus + 7) / 8 * 8);
     int nseg = 0;
     const int kb = strip_plan(G, FIRST, NEXT, W, gmax, &nseg);
@@ -57,6 +62,7 @@ static int check(int G, unsigned cus)
             prev_end = y + r;
             prev_x = x;
             ++n;
+            ++total_tiles;
         }
         if (n > cost) return printf("G=%d cus=%u: block %u walks %lld tiles, plan %lld\n", G, cus, b, n, cost), 1;
     }
@@ -73,8 +79,17 @@ static int check(int G, unsigned cus)
     return 0;
 }
 
-int main()
+int main(int argc, char** argv)
 {
+    if (argc > 1) {  // "G cus" pairs: the tiles the pass runs for each
+        for (int a = 1; a + 1 < argc; a += 2) {
+            const int G = atoi(argv[a]);
+            const unsigned cus = (unsigned)atoi(argv[a + 1]);
+            if (check(G, cus)) return 1;
+            printf("%d %u %lld\n", G, cus, total_tiles);
+        }
+        return 0;
+    }
     std::vector<int> sides;
     for (int G = 1; G <= 1024; ++G) sides.push_back(G);
     for (int G = 1031; G < 4096; G += 37) sides.push_back(G);
@@ -105,3 +120,15 @@ def test_strip_tiling_covers_every_pixel_once(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert r.stdout.startswith("ok"), r.stdout
+
+    # the benchmark's count of the matrix work this pass issues uses its own copy of the plan: it must
+    # give the tiles the kernel runs
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    cases = [(G, cus) for G in (1, 14, 30, 64, 601, 777, 1024, 2000, 4096) for cus in (8, 248, 256)]
+    r = subprocess.run([str(exe), *[str(v) for c in cases for v in c]], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout[-2000:]
+    got = {(int(a), int(b)): int(t) for a, b, t in (line.split() for line in r.stdout.strip().splitlines())}
+    for G, cus in cases:
+        assert bench.conv34_tiles(G, cus) == got[(G, cus)], (G, cus, bench.conv34_tiles(G, cus), got[(G, cus)])
