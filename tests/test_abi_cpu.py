@@ -3,6 +3,8 @@ arguments before touching the GPU (no compute call is made here)."""
 import ctypes
 import os
 import re
+import subprocess
+import sys
 
 import pytest
 
@@ -99,3 +101,24 @@ def test_binding_rejects_malformed_nets_and_host_tensors():
     C._on(0, ("absent", None))
     with pytest.raises(ValueError, match="device tensor"):
         C._ptr(torch.zeros(4))
+
+
+def test_missing_library_raises(tmp_path):
+    """Without the built library the loader that every entry point of the binding goes through
+raises, every time it is asked: there is no host fallback."""
+    prog = f"""
+from paper_2412_18379_amd import cnnsns as C
+C.LIB_PATH = {str(tmp_path / 'libcnnsns.so')!r}
+C._lib = None
+for _ in range(2):
+    try:
+        C.lib()
+    except RuntimeError as e:
+        assert "is not built" in str(e), e
+    else:
+        raise SystemExit("no error")
+print("raised")
+"""
+    r = subprocess.run([sys.executable, "-c", prog], capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-1500:]
+    assert r.stdout.strip() == "raised"
