@@ -47,7 +47,10 @@ constexpr int HV = OH + 8, WV = OW + 8;    // velocity tile (22 x 38)
 // with 56-63 (8-15 with 48-55, ...): for the operand reads, eight consecutive pixels at one channel
 // chunk and eight others at the mirrored chunk.  At a 96-byte pitch those reads fall in distinct bank
 // groups; at 80 bytes half of them collide.  The LDS holds only one of the two layer buffers at 96:
-// it goes to conv2's input, the layer with the more operand reads per tile.
+// it goes to conv2's input, the layer with the more operand reads per tile.  conv3 reads the 80-byte
+// buffer conflict-free all the same: its M-blocks take every second pixel of a 32-pixel row (one
+// block the even pixels, the next the odd ones), so at a 5-slot pitch all 16 pixels of a block sit in
+// 16-byte slots of one parity and the mirrored chunk (3 slots on) in the other.
 constexpr int PXS = 48;
 constexpr int PXS2 = 40;
 constexpr int VEL_PER_THREAD = (HV * WV + kThreads - 1) / kThreads;  // velocity pixels per thread
@@ -131,18 +134,19 @@ __device__ __forceinline__ uint32_t relu_pair(float v0, float v1)
 // Writes the 4 pixels (p0 .. p0 + 3 of an HO x WO region with grid origin
 // (oy0, ox0)) that lane (i, q) holds after a layer's M-block: ReLU pairs, and
 // zero for pixels outside the grid (the next layer's zero padding).
-template <int WO, int OPXS, bool EDGE>
+template <int WO, int OPXS, bool EDGE, int S = 1>
 __device__ __forceinline__ void store_block(bf16* __restrict__ out, int p0, int i, const v4f& d0, const v4f& d1,
                                             int oy0, int ox0, int G)
 {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         uint32_t v = relu_pair(d0[r], d1[r]);
+        const int p = p0 + S * r;
         if (EDGE) {
-            const int p = p0 + r, gy = oy0 + p / WO, gx = ox0 + p % WO;
+            const int gy = oy0 + p / WO, gx = ox0 + p % WO;
             if (!inside(gy, gx, G)) v = 0;
         }
-        *reinterpret_cast<uint32_t*>(out + (p0 + r) * OPXS + 2 * i) = v;
+        *reinterpret_cast<uint32_t*>(out + p * OPXS + 2 * i) = v;
     }
 }
 
@@ -150,14 +154,17 @@ __device__ __forceinline__ void store_block(bf16* __restrict__ out, int p0, int 
 // grid) reading an (HO+2) x (WO+2) input region, all in LDS, pixel-major.
 // Wavefront w takes the BPW M-blocks [w BPW, (w+1) BPW) and works through
 // them MB at a time; the A and B operands of the next two taps are read while
-// the matrix instructions of the current one issue.  Blocks past the region's last one are
+// the matrix instructions of the current one issue.  STRIDE2: block 2k + e holds
+// pixels 32k + e, 32k + e + 2, ..., 32k + e + 30 (rows of 32 pixels).  Blocks past the region's last one are
 // computed on clamped pixels and not stored.
-template <int HO, int WO, int IPXS, int OPXS, int BPW, int MB, bool EDGE>
+template <int HO, int WO, int IPXS, int OPXS, int BPW, int MB, bool EDGE, bool STRIDE2 = false>
 __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* __restrict__ out,
                                             const bf16x8* __restrict__ sw, float blo, float bhi, int oy0, int ox0,
                                             int G, int wave, int lane)
 {
     constexpr int WI = WO + 2, N = HO * WO, NMB = (N + 15) / 16;
+    static_assert(!STRIDE2 || (WO == 32 && BPW % 2 == 0 && MB % 2 == 0 && N % 32 == 0),
+                  "strided M-blocks pair up the two halves of one 32-pixel row");
     const int i = lane & 15, q = lane >> 4;
     int wl = lane;  // opaque to the compiler: the weights are read per tap, not held across calls
     asm volatile("" : "+v"(wl));
@@ -170,7 +177,7 @@ __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* _
         int base[MB];
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
-            const int p = min((g + m) * 16 + i, N - 1);
+            const int p = STRIDE2 ? ((g + m) >> 1) * 32 + 2 * i + ((g + m) & 1) : min((g + m) * 16 + i, N - 1);
             base[m] = ((p / WO) * WI + p % WO) * IPXS + 8 * q;
             acc[m][0] = v4f{ blo, blo, blo, blo };
             acc[m][1] = v4f{ bhi, bhi, bhi, bhi };
@@ -205,7 +212,13 @@ __device__ __forceinline__ void conv32_bf16(const bf16* __restrict__ in, bf16* _
 #pragma unroll
         for (int m = 0; m < MB; ++m)
             if (NMB == BPW * kWaves || g + m < NMB)
-                store_block<WO, OPXS, EDGE>(out, (g + m) * 16 + 4 * q, i, acc[m][0], acc[m][1], oy0, ox0, G);
+            {
+                if (STRIDE2)
+                    store_block<WO, OPXS, EDGE, 2>(out, ((g + m) >> 1) * 32 + 8 * q + ((g + m) & 1), i, acc[m][0],
+                                                   acc[m][1], oy0, ox0, G);
+                else
+                    store_block<WO, OPXS, EDGE>(out, (g + m) * 16 + 4 * q, i, acc[m][0], acc[m][1], oy0, ox0, G);
+            }
     }
 }
 
@@ -338,10 +351,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         __syncthreads();
         stash_vel();
         if (edge)
-            conv32_bf16<H3, W3, PXS2, PXS, BPW3, MB3, true>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G,
+            conv32_bf16<H3, W3, PXS2, PXS, BPW3, MB3, true, true>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G,
                                                             wave, lane);
         else
-            conv32_bf16<H3, W3, PXS2, PXS, BPW3, MB3, false>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G,
+            conv32_bf16<H3, W3, PXS2, PXS, BPW3, MB3, false, true>(bufB, bufA, s_w23 + P2, b3lo, b3hi, ty0 - 1, tx0 - 1, G,
                                                              wave, lane);
         __syncthreads();
 
